@@ -1,0 +1,291 @@
+"""Seeded synthetic scene generators (inputs only).
+
+This module builds meshes, materials, initial states and kinematic obstacle
+tracks.  It performs none of the simulation method's arithmetic (no masses,
+no element maps, no system matrices, no contact geometry): both the HIP path
+and the FP64 oracle consume what it returns.
+
+Shapes follow the workloads the FLASH paper uses its solver for: volumetric
+blocks squeezed by fingers and dropped on the ground, and cloth sheets
+(Sec. IV-A, Fig. 3; cloth material of the FLASH parameter table).  The paper's
+own meshes (scanned garments, towels) are not available, so seeded lattices
+stand in for them.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass, field
+from typing import List
+
+import numpy as np
+
+TET = 0
+TRI = 1
+
+PLANE = 0
+BOX = 1
+CAPSULE = 2
+
+MAX_OBSTACLES = 4
+
+
+@dataclass
+class EnvDesc:
+    """One environment: a single deformable body (tet block or cloth sheet)."""
+    elem: int
+    rest_x: np.ndarray          # (n_vertices, 3) float64, metres
+    elements: np.ndarray        # (n_elements, 4) tets or (n_elements, 3) tris, int32
+    density: float = 1000.0     # kg/m^3
+    thickness: float = 1e-3     # m, TRI only
+    young: float = 1e5          # Pa
+    poisson: float = 0.3
+    bending: float = 0.0        # TRI only (hinge stiffness)
+    mu: float = 0.5             # Coulomb coefficient against every obstacle
+
+    @property
+    def n_vertices(self) -> int:
+        return int(self.rest_x.shape[0])
+
+    @property
+    def n_elements(self) -> int:
+        return int(self.elements.shape[0])
+
+
+@dataclass
+class Obstacle:
+    """Kinematic obstacle.  Pose is the pose at the start of the next step.
+
+    kind: PLANE (normal = rot @ +y, passes through center), BOX (half extents
+    in size), CAPSULE (size = (radius, half_length, 0), axis = rot @ +x).
+    The obstacle translates by h*lin_vel per step for move_steps steps
+    (negative: forever), then holds.
+    """
+    kind: int
+    center: np.ndarray
+    rot: np.ndarray             # (3, 3) world-from-local rotation
+    size: np.ndarray
+    lin_vel: np.ndarray
+    move_steps: int = -1
+
+    def copy(self) -> "Obstacle":
+        return Obstacle(self.kind, self.center.copy(), self.rot.copy(), self.size.copy(),
+                        self.lin_vel.copy(), int(self.move_steps))
+
+
+@dataclass
+class Params:
+    h: float = 1.0 / 60.0
+    gravity: tuple = (0.0, -9.81, 0.0)
+    lg_iterations: int = 20
+    max_inner_iterations: int = 50
+    ncp_tol: float = 1e-6
+    contact_margin: float = 2e-3
+    max_force: float = 1e10
+
+
+@dataclass
+class Scene:
+    envs: List[EnvDesc]
+    x0: List[np.ndarray]                # per env (n_v, 3) float64
+    v0: List[np.ndarray]
+    obstacles: List[List[Obstacle]]     # per env
+    params: Params
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_envs(self) -> int:
+        return len(self.envs)
+
+
+# ----------------------------------------------------------------------------
+# meshes
+# ----------------------------------------------------------------------------
+
+def hex_lattice(nx: int, ny: int, nz: int, size, origin):
+    """Box lattice of nx*ny*nz hexes, each split into 6 Kuhn tets.
+
+    Vertices are in lexicographic (i, j, k) order, index
+    i*(ny+1)*(nz+1) + j*(nz+1) + k, with i along x, j along y, k along z.
+    Each hex is cut into the 6 tets that share its main diagonal.
+    """
+    sx, sy, sz = (float(s) for s in size)
+    ox, oy, oz = (float(o) for o in origin)
+    xs = ox + sx * np.arange(nx + 1) / nx
+    ys = oy + sy * np.arange(ny + 1) / ny
+    zs = oz + sz * np.arange(nz + 1) / nz
+    X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+    rest = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1).astype(np.float64)
+
+    def vid(i, j, k):
+        return (i * (ny + 1) + j) * (nz + 1) + k
+
+    perms = list(itertools.permutations(range(3)))
+    tets = []
+    for i in range(nx):
+        for j in range(ny):
+            for k in range(nz):
+                base = np.array([i, j, k])
+                for p in perms:
+                    c0 = base.copy()
+                    c1 = c0.copy(); c1[p[0]] += 1
+                    c2 = c1.copy(); c2[p[1]] += 1
+                    c3 = base + 1
+                    tets.append([vid(*c0), vid(*c1), vid(*c2), vid(*c3)])
+    return rest, np.asarray(tets, dtype=np.int32)
+
+
+def cloth_grid(n: int, side: float, origin, y: float):
+    """n*n vertex sheet in the xz-plane at height y, alternating diagonals."""
+    ox, oz = float(origin[0]), float(origin[1])
+    t = side * np.arange(n) / (n - 1)
+    X, Z = np.meshgrid(ox + t, oz + t, indexing="ij")
+    rest = np.stack([X.ravel(), np.full(n * n, float(y)), Z.ravel()], axis=1)
+    tris = []
+    for i in range(n - 1):
+        for k in range(n - 1):
+            a = i * n + k
+            b = (i + 1) * n + k
+            c = (i + 1) * n + k + 1
+            d = i * n + k + 1
+            if (i + k) % 2 == 0:
+                tris += [[a, b, c], [a, c, d]]
+            else:
+                tris += [[a, b, d], [b, c, d]]
+    return rest.astype(np.float64), np.asarray(tris, dtype=np.int32)
+
+
+# ----------------------------------------------------------------------------
+# obstacles
+# ----------------------------------------------------------------------------
+
+def ground(height: float = 0.0) -> Obstacle:
+    return Obstacle(PLANE, np.array([0.0, height, 0.0]), np.eye(3), np.zeros(3), np.zeros(3), -1)
+
+
+def tilted_plane(angle: float) -> Obstacle:
+    """Plane through the origin, rotated by `angle` about +z (normal leans toward -x)."""
+    c, s = math.cos(angle), math.sin(angle)
+    rot = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    return Obstacle(PLANE, np.zeros(3), rot, np.zeros(3), np.zeros(3), -1)
+
+
+def box(center, half, vel=(0.0, 0.0, 0.0), move_steps=-1, rot=None) -> Obstacle:
+    return Obstacle(BOX, np.asarray(center, float), np.eye(3) if rot is None else np.asarray(rot, float),
+                    np.asarray(half, float), np.asarray(vel, float), int(move_steps))
+
+
+def capsule(center, radius, half_length, vel=(0.0, 0.0, 0.0), move_steps=-1, rot=None) -> Obstacle:
+    return Obstacle(CAPSULE, np.asarray(center, float), np.eye(3) if rot is None else np.asarray(rot, float),
+                    np.array([radius, half_length, 0.0]), np.asarray(vel, float), int(move_steps))
+
+
+def random_rotation(rng: np.random.Generator) -> np.ndarray:
+    """Uniform random rotation from a normalised Gaussian quaternion."""
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+# ----------------------------------------------------------------------------
+# scenes
+# ----------------------------------------------------------------------------
+
+def drop_cube(seed: int = 0, hexes: int = 4, edge: float = 0.1, drop_height: float = 0.2,
+              young: float = 1e5, poisson: float = 0.3, density: float = 1000.0, mu: float = 0.5,
+              jitter: float = 1e-3, lg_iterations: int = 20) -> Scene:
+    """Single cube of hexes^3 hexes dropped onto the ground (125 vertices / 384 tets at hexes=4).
+
+    The bottom face starts at y = drop_height; initial positions (not the rest
+    shape) are jittered by U(-jitter, jitter) per coordinate.
+    """
+    rng = np.random.default_rng(seed)
+    rest, tets = hex_lattice(hexes, hexes, hexes, (edge, edge, edge), (-edge / 2, 0.0, -edge / 2))
+    x0 = rest + np.array([0.0, drop_height, 0.0])
+    x0 = x0 + rng.uniform(-jitter, jitter, size=x0.shape)
+    env = EnvDesc(TET, rest, tets, density=density, young=young, poisson=poisson, mu=mu)
+    params = Params(lg_iterations=lg_iterations)
+    return Scene([env], [x0], [np.zeros_like(x0)], [[ground()]], params, name="drop_cube")
+
+
+def squeeze_blocks(n_envs: int, seed: int = 0, hexes: int = 10, edge: float = 0.1,
+                   lg_iterations: int = 20, start_gap: float = 1e-3, indent: float = 1e-2,
+                   close_speed: float = 0.02, h: float = 1.0 / 60.0) -> Scene:
+    """Blocks resting on the ground, squeezed by two kinematic box fingers.
+
+    Per env: E ~ U(5e4, 5e5) Pa, nu ~ U(0.30, 0.45), mu ~ U(0.3, 0.8).  Fingers
+    (half extents 0.02 x 0.03 x 0.03 m) sit on the +-x faces at mid height with
+    `start_gap`, close at `close_speed` each until `indent`, then hold.
+    """
+    rng = np.random.default_rng(seed)
+    rest, tets = hex_lattice(hexes, hexes, hexes, (edge, edge, edge), (-edge / 2, 0.0, -edge / 2))
+    travel = start_gap + indent
+    move_steps = int(round(travel / (close_speed * h)))
+    half = np.array([0.02, 0.03, 0.03])
+    envs, xs, vs, obs = [], [], [], []
+    for _ in range(n_envs):
+        E = float(rng.uniform(5e4, 5e5))
+        nu = float(rng.uniform(0.30, 0.45))
+        mu = float(rng.uniform(0.3, 0.8))
+        envs.append(EnvDesc(TET, rest, tets, density=1000.0, young=E, poisson=nu, mu=mu))
+        xs.append(rest.copy())
+        vs.append(np.zeros_like(rest))
+        cx = edge / 2 + start_gap + half[0]
+        cy = edge / 2
+        obs.append([ground(),
+                    box((cx, cy, 0.0), half, (-close_speed, 0.0, 0.0), move_steps),
+                    box((-cx, cy, 0.0), half, (close_speed, 0.0, 0.0), move_steps)])
+    params = Params(h=h, lg_iterations=lg_iterations)
+    return Scene(envs, xs, vs, obs, params, name="squeeze_blocks",
+                 meta={"hexes": hexes, "move_steps": move_steps})
+
+
+def incline_block(mu: float, angle_deg: float = 30.0, young: float = 1e8, hexes: int = 2,
+                  edge: float = 0.05, lg_iterations: int = 5) -> Scene:
+    """Stiff block resting on a plane tilted by angle_deg (friction threshold test)."""
+    ang = math.radians(angle_deg)
+    rest, tets = hex_lattice(hexes, hexes, hexes, (edge, edge, edge), (-edge / 2, 0.0, -edge / 2))
+    c, s = math.cos(ang), math.sin(ang)
+    rot = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    x0 = rest @ rot.T
+    env = EnvDesc(TET, rest, tets, density=1000.0, young=young, poisson=0.3, mu=mu)
+    params = Params(lg_iterations=lg_iterations)
+    return Scene([env], [x0], [np.zeros_like(x0)], [[tilted_plane(ang)]], params, name="incline")
+
+
+def cloth_drop(n: int = 16, side: float = 0.5, height: float = 0.05, seed: int = 0,
+               bending: float = 0.2, lg_iterations: int = 10) -> Scene:
+    """Cloth sheet (FLASH cloth material: E=3e4, nu=0.4, bending 0.2) over a box."""
+    rng = np.random.default_rng(seed)
+    rest, tris = cloth_grid(n, side, (-side / 2, -side / 2), 0.0)
+    top = 0.05
+    x0 = rest + np.array([0.0, top + height, 0.0])
+    x0[:, 1] += rng.uniform(-1e-4, 1e-4, size=n * n)
+    env = EnvDesc(TRI, rest, tris, density=1000.0, thickness=1e-3, young=3e4, poisson=0.4,
+                  bending=bending, mu=0.5)
+    obs = [ground(), box((0.0, top / 2, 0.0), (0.08, top / 2, 0.08))]
+    params = Params(lg_iterations=lg_iterations)
+    return Scene([env], [x0], [np.zeros_like(x0)], [obs], params, name="cloth_drop")
+
+
+def single_tet_scene(kind: str = "ground", seed: int = 0, tang_speed: float = 0.2) -> Scene:
+    """Tiny scenes for brute-force enumeration of contact modes (1-3 contacts)."""
+    rng = np.random.default_rng(seed)
+    rest = np.array([[0.0, 0.0, 0.0], [0.02, 0.0, 0.0], [0.0, 0.0, 0.02], [0.0, 0.02, 0.0]])
+    tets = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    x0 = rest.copy()
+    x0[:, 1] += 0.0005
+    v0 = np.zeros_like(x0)
+    v0[:, 0] = rng.uniform(-tang_speed, tang_speed)
+    v0[:, 2] = rng.uniform(-tang_speed, tang_speed)
+    v0[:, 1] = -0.05
+    env = EnvDesc(TET, rest, tets, density=1000.0, young=float(rng.uniform(2e4, 2e5)), poisson=0.3,
+                  mu=float(rng.uniform(0.1, 0.9)))
+    params = Params(lg_iterations=2)
+    return Scene([env], [x0], [v0], [[ground()]], params, name="single_tet")
