@@ -1,0 +1,199 @@
+/*
+ * flash.h - C ABI of the MI355X FLASH step library.
+ *
+ * One call of flash_step advances every environment of a batch by one implicit
+ * Euler step of projective-dynamics elasticity with Signorini-Coulomb contact,
+ * solved as a non-smooth complementarity problem (FLASH, Sec. III: implicit
+ * step Eq. 1, contact-constrained dynamics Eq. 2, projective internal forces
+ * Eq. 3, assembled system A q - b - h^2 H^T lambda = 0 of Eq. 4, non-smooth
+ * Newton quantities Eq. 5-9; the multi-environment pipeline is Alg. 1 with the
+ * block-diagonal batch of Eq. 11-12).  Environments never couple: each keeps
+ * its own A = M + h^2 sum_i w_i G_i^T G_i, contact set and multipliers.
+ *
+ * Conventions
+ *  - Every function returns flash_status; no C++ exception crosses the ABI.
+ *    flash_last_error() returns a thread-local description of the last error.
+ *  - SI units.  Host arrays are xyz-interleaved doubles; device state is
+ *    structure-of-arrays in the batch's working precision.
+ *  - Ownership: the caller owns every array it passes; inputs are copied
+ *    during the call; outputs are caller-allocated with an explicit capacity.
+ *    The batch owns all device memory (allocated in flash_create_batch, freed
+ *    in flash_destroy_batch).
+ *  - An invalid argument returns FLASH_ERR_INVALID_ARG and leaves the batch
+ *    unchanged.
+ *  - flash_step only enqueues work on the batch's stream; the query calls
+ *    (get_state, contacts, residual, stats) synchronise that stream first.
+ *  - Determinism: identical inputs and parameters give bitwise identical
+ *    results run to run (no floating-point atomics; fixed reduction orders;
+ *    ordered contact compaction).
+ *  - Threading: one batch per host thread or stream; no global state besides
+ *    the thread-local error text.
+ */
+#ifndef FLASH_MI355X_H
+#define FLASH_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct flash_batch flash_batch;   /* opaque; library-owned until destroy */
+
+typedef enum {
+  FLASH_OK = 0,
+  FLASH_ERR_INVALID_ARG = 1,
+  FLASH_ERR_OUT_OF_MEMORY = 2,
+  FLASH_ERR_DEVICE = 3,
+  FLASH_ERR_CAPACITY = 4,
+  FLASH_ERR_NOT_CONVERGED = 5,
+  FLASH_ERR_NONFINITE = 6,
+  FLASH_ERR_UNSUPPORTED = 7
+} flash_status;
+
+enum { FLASH_TET = 0, FLASH_TRI = 1 };
+enum { FLASH_PLANE = 0, FLASH_BOX = 1, FLASH_CAPSULE = 2 };
+enum { FLASH_FP32 = 0, FLASH_FP64 = 1 };
+enum { FLASH_WS_ZERO = 0, FLASH_WS_PREV = 1, FLASH_WS_LEARNED = 2 };
+enum { FLASH_MAX_OBSTACLES = 4 };
+
+/* One environment: one deformable body.
+ * Element maps and weights follow the as-rigid-as-possible reading of Eq. 3:
+ * tets project F = D_s D_m^-1 onto SO(3) with w = 2 mu_L V; triangles project
+ * the 3x2 F onto matrices with orthonormal columns with w = 2 mu_L A t;
+ * mu_L = young / (2 (1 + poisson)).  Masses are lumped by row sums.
+ * rest_x [n_vertices*3] and elements [n_elements*4 (tets) | *3 (tris)] are
+ * copied.  Tets with negative rest orientation are reordered internally. */
+typedef struct {
+  int32_t elem;              /* FLASH_TET or FLASH_TRI */
+  int32_t n_vertices;
+  int32_t n_elements;
+  int32_t reserved;
+  const double *rest_x;
+  const int32_t *elements;
+  double density;            /* kg/m^3 */
+  double thickness;          /* m, FLASH_TRI only */
+  double young;              /* Pa */
+  double poisson;
+  double bending;            /* FLASH_TRI only: hinge stiffness (0 = none) */
+  double mu;                 /* Coulomb coefficient against every obstacle of this env */
+} flash_env_desc;
+
+/* Kinematic obstacle (rigid, translating).  Pose at the start of the next step.
+ * PLANE: normal = rot * (0,1,0), through center.  BOX: half extents size[0..2].
+ * CAPSULE: size = {radius, half_length, 0}, axis = rot * (1,0,0).
+ * rot is a row-major 3x3 world-from-local rotation.  The obstacle translates by
+ * h * lin_vel during each of the next move_steps steps (negative: forever) and
+ * then holds its pose. */
+typedef struct {
+  int32_t kind;
+  int32_t move_steps;
+  double center[3];
+  double rot[9];
+  double size[3];
+  double lin_vel[3];
+} flash_obstacle;
+
+typedef struct {
+  double h;                       /* time step, s */
+  double gravity[3];              /* m/s^2 */
+  int32_t lg_iterations;          /* K: local-global iterations per step (Alg. 1 k_max) */
+  int32_t max_inner_iterations;   /* cap on non-smooth Newton iterations per contact solve */
+  double ncp_tol;                 /* NCP residual tolerance, metres (default 1e-6) */
+  double contact_margin;          /* delta_c, metres */
+  double max_force;               /* |lambda| clamp, newtons */
+  int32_t precision;              /* FLASH_FP32 or FLASH_FP64 */
+  int32_t warm_start;             /* FLASH_WS_* */
+  int32_t use_graph;              /* capture the step in a HIP graph */
+  int32_t max_contacts_per_env;   /* contact capacity per env (0: default 512) */
+  double inner_tol;               /* stopping tolerance of every contact solve, metres
+                                     (0: 0.25 * ncp_tol in FP32, 1e-12 in FP64) */
+} flash_params;
+
+/* One contact of the last step.  impulse = h F lambda in the world frame (N s);
+ * lambda holds the contact-frame multipliers (n, t1, t2) in newtons.
+ * mode: 0 separate (lambda = 0), 1 stick, 2 slip. */
+typedef struct {
+  int32_t env, vertex, obstacle, mode;
+  double normal[3];
+  double tangent1[3];
+  double gap;                     /* d0, signed distance at the step start, m */
+  double impulse[3];
+  double lambda[3];
+} flash_contact;
+
+typedef struct {
+  int32_t inner_iterations;       /* Newton iterations summed over the step's K contact solves */
+  int32_t refactorizations;       /* inverse rebuilds of the contact-space operator */
+  int32_t contacts;
+  int32_t fp64_polar;             /* tets routed to the FP64 polar decomposition */
+  int32_t flags;                  /* bit 0: non-finite state, bit 1: not converged, bit 2: capacity */
+  int32_t reserved;
+  double residual;                /* NCP residual at the end of the step, m (FP64) */
+} flash_env_stats;
+
+/* Creates a batch of n_envs independent environments and runs the create-time
+ * precompute (Alg. 1: assemble A per env and its exact inverse, in FP64 on the
+ * host; masses, D_m^-1, weights).  hip_stream: a hipStream_t or NULL for a
+ * stream owned by the batch.  State starts at the rest shapes with zero
+ * velocity and no obstacles. */
+flash_status flash_create_batch(const flash_env_desc *envs, int32_t n_envs, const flash_params *p,
+                                void *hip_stream, flash_batch **out);
+flash_status flash_destroy_batch(flash_batch *b);
+
+/* Sets / reads positions and velocities.  env = -1: all envs, concatenated in
+ * env order; else the one env.  x, v: [n_vertices*3] doubles (v may be NULL
+ * on set to keep velocities, NULL on get to skip).  Setting the state of an env
+ * invalidates its warm-start cache. */
+flash_status flash_set_state(flash_batch *b, int32_t env, const double *x, const double *v);
+flash_status flash_get_state(flash_batch *b, int32_t env, double *x, double *v);
+
+/* Replaces the obstacles of one env (env >= 0, n <= FLASH_MAX_OBSTACLES) or of
+ * every env (env = -1: o holds n_envs * n entries, env-major). */
+flash_status flash_set_obstacles(flash_batch *b, int32_t env, const flash_obstacle *o, int32_t n);
+flash_status flash_get_obstacles(flash_batch *b, int32_t env, flash_obstacle *o, int32_t capacity,
+                                 int32_t *n_out);
+
+/* Enqueues n_steps steps of every env (Alg. 1 loop body): contact detection at
+ * the obstacles' end-of-step poses, prediction, K local-global iterations each
+ * solving the contact subproblem to ncp_tol, finalisation.  Asynchronous. */
+flash_status flash_step(flash_batch *b, int32_t n_steps);
+flash_status flash_synchronize(flash_batch *b);
+
+/* Contacts of the last step, sorted by (vertex, obstacle) within an env; env =
+ * -1 lists every env in env order.  FLASH_ERR_CAPACITY with *n_out = required
+ * count if capacity is too small. */
+flash_status flash_contacts(flash_batch *b, int32_t env, flash_contact *out, int32_t capacity,
+                            int32_t *n_out);
+
+/* Per-env NCP residual of the last step (metres, FP64, evaluated from the end
+ * positions and multipliers), its maximum, and Newton iteration counts.  Any
+ * argument may be NULL.  Returns FLASH_ERR_NONFINITE if an env holds a
+ * non-finite state, FLASH_ERR_NOT_CONVERGED if an env ended above ncp_tol. */
+flash_status flash_residual(flash_batch *b, double *per_env, double *max_out, int32_t *inner_iters);
+flash_status flash_stats(flash_batch *b, flash_env_stats *per_env);
+
+/* Per-kernel timing with HIP events recorded on the batch's stream around each
+ * launch (off by default).  flash_kernel_times fills up to cap entries of
+ * total milliseconds and launch counts, in the order of flash_kernel_name. */
+flash_status flash_set_kernel_timing(flash_batch *b, int32_t enable);
+flash_status flash_kernel_times(flash_batch *b, double *total_ms, int64_t *launches, int32_t cap,
+                                int32_t *n_out);
+const char *flash_kernel_name(int32_t i);
+
+/* Learned warm start: a 16 -> 128 -> 128 -> 128 -> 3 ReLU MLP predicts the
+ * initial multipliers of each contact from local features; BF16 weights,
+ * FP32 accumulation.  weights_bf16 holds W1,b1,W2,b2,W3,b3,W4,b4 row-major
+ * (out x in), n_params = 35587.  The feature scaling vectors (16 means and
+ * 16 inverse scales) and the label scale come in norm[33]. */
+flash_status flash_ws_load(flash_batch *b, const uint16_t *weights_bf16, size_t n_params,
+                           const float *norm);
+
+const char *flash_last_error(void);
+const char *flash_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASH_MI355X_H */

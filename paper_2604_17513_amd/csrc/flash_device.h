@@ -1,0 +1,108 @@
+// Device-side data layout shared by the kernels and the host launcher.
+//
+// Every per-vertex quantity is structure-of-arrays over the concatenation of
+// all environments: component c of vertex i lives at [c * NV + i].  Per-tet
+// data is SoA the same way over all tets.  Per-contact data lives in one slab
+// of `cap` records per environment.  The explicit inverse Gbar = Abar^-1 of
+// each environment is a dense row-major n x ld block (ld = n rounded up to 4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace flash {
+
+constexpr int kMaxObs = 4;
+constexpr int kBlock = 256;
+
+// Kernel classes for event timing (flash_kernel_name order).
+enum KernelId {
+  K_DETECT = 0, K_GATHER, K_PROJECT, K_ASSEMBLE, K_APPLY, K_CSP, K_CORRECT, K_FINALIZE,
+  K_MLP, K_COUNT
+};
+
+template <class T>
+struct DevBatch {
+  int n_envs;
+  int NV, NT;                 // total vertices / tets (tets: 4-node; tris: 3-node use the same arrays)
+  int cap;                    // contact capacity per env
+  int rmax;                   // capacity of the Woodbury capacitance system per env
+  int max_newton;
+  int lg_iterations;
+  double h;
+  double g[3];
+  double margin;
+  double tol;
+  double max_force;
+  int warm_start;             // FLASH_WS_*
+
+  const int* voff;            // [n_envs+1]
+  const int* toff;            // [n_envs+1]
+  const int* vert_env;        // [NV]
+  const int* tet_env;         // [NT]
+
+  T* x;                       // [3*NV] positions at step start
+  T* v;                       // [3*NV]
+  T* u;                       // [3*NV] displacement q - x of the current iterate
+  T* ut;                      // [3*NV] predicted displacement h v + h^2 g
+  T* z;                       // [3*NV] Gbar b
+  T* b;                       // [3*NV] right-hand side in displacement form
+  const T* mass;              // [NV]
+
+  const int* tet_idx;         // [4*NT] global vertex ids
+  const T* tet_B;             // [9*NT] D_m^-1 row-major (B[r][c] at (3r+c)*NT)
+  const T* tet_w;             // [NT]
+  T* fel;                     // [12*NT] per-tet vertex forces w (p - F_x) gradN_a
+  const int* inc_off;         // [NV+1]
+  const int* inc;             // [4*NT] entries t*4+a
+
+  const T* G;                 // dense inverses
+  const int64_t* goff;        // [n_envs] element offset of env block
+  const int* gld;             // [n_envs] leading dimension
+
+  // obstacles [n_envs * kMaxObs]
+  int* nobs;                  // [n_envs]
+  int* obs_kind;
+  int* obs_move;
+  double* obs_c;              // [*3]
+  const double* obs_R;        // [*9]
+  const double* obs_size;     // [*3]
+  const double* obs_vel;      // [*3]
+
+  // contacts [n_envs * cap]
+  int* ccount;                // [n_envs]
+  int* cvert;                 // local vertex index
+  int* cobs;
+  T* cframe;                  // [9 per contact] columns n, t1, t2: frame[3*a + k] = column a, comp k
+  T* cd0;
+  T* cdob;                    // [2 per contact] T^T dobs
+  T* cs;                      // residual scale h^2/m_v
+  T* clam;                    // [3 per contact] multipliers (n, t1, t2)
+  T* cforce;                  // [3 per contact] world force F lambda
+  int* cnew;                  // 1: no warm start available
+  double* cd0d;               // FP64 gap (kept for exact reporting)
+
+  // contact-space scratch
+  T* Gc;                      // [cap*cap per env] Gbar restricted to contacts
+  T* Ginv;                    // [cap*cap per env] inverse on the base set
+  T* Cm;                      // [rmax*rmax per env] capacitance matrix
+  int* base;                  // [cap per env] base-set contact ids (ordered)
+  int* nbase;                 // [n_envs]
+
+  // warm-start cache [NV * kMaxObs]
+  T* cache_f;                 // [3 per entry] world force
+  int* cache_stamp;
+  int* stamp;                 // [1] step counter (device side)
+
+  // per env outputs
+  double* resid;              // [n_envs]
+  int* iters;                 // [n_envs] Newton iterations this step
+  int* refac;                 // [n_envs]
+  int* flags;                 // [n_envs]
+  int* fp64_polar;            // [n_envs]
+
+  // learned warm start (optional)
+  const uint16_t* mlp_w;      // bf16 weights (nullptr: off)
+  const float* mlp_norm;      // [33]
+};
+
+}  // namespace flash

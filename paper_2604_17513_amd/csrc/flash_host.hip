@@ -1,0 +1,803 @@
+// C ABI of the FLASH step library: create-time precompute, device buffers,
+// step enqueue (plain one-launch-per-phase schedule or a captured HIP graph),
+// state / contact / residual queries and per-kernel event timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/flash.h"
+#include "flash_device.h"
+#include "flash_launch.h"
+
+using namespace flash;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct FlashError : std::runtime_error {
+  flash_status st;
+  FlashError(flash_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t _e = (x);                                                                  \
+    if (_e != hipSuccess)                                                                 \
+      throw FlashError(_e == hipErrorOutOfMemory ? FLASH_ERR_OUT_OF_MEMORY : FLASH_ERR_DEVICE, \
+                       std::string(#x) + ": " + hipGetErrorString(_e));                   \
+  } while (0)
+
+flash_status fail(flash_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+// ----------------------------------------------------------------------------
+// Create-time precompute (FP64, host).  Per env: oriented elements, D_m^-1,
+// weights, lumped masses, the scalar system matrix Abar (A = Abar (x) I3,
+// Eq. 4), its skyline Cholesky factor and the explicit inverse Gbar = Abar^-1
+// (the paper forms A^-1 = S^T S from the inverse Cholesky factor, Alg. 1;
+// here the product is formed once so that each global solve is one symmetric
+// sweep and the contact-space Delassus operator is a gather).
+// ----------------------------------------------------------------------------
+struct HostEnv {
+  int n = 0, m = 0, k = 4;
+  std::vector<int> elem;      // oriented, k per element
+  std::vector<double> Bm;     // 9 per tet
+  std::vector<double> w;      // per element
+  std::vector<double> mass;   // per vertex
+  std::vector<double> Ginv;   // n*n symmetric
+};
+
+void tet_data(const flash_env_desc& d, HostEnv& H) {
+  const int n = d.n_vertices, m = d.n_elements;
+  H.n = n; H.m = m; H.k = 4;
+  H.elem.assign(d.elements, d.elements + 4 * (size_t)m);
+  H.Bm.resize(9 * (size_t)m);
+  H.w.resize(m);
+  H.mass.assign(n, 0.0);
+  const double muL = d.young / (2.0 * (1.0 + d.poisson));
+  for (int t = 0; t < m; ++t) {
+    int* id = &H.elem[4 * (size_t)t];
+    for (int a = 0; a < 4; ++a)
+      if (id[a] < 0 || id[a] >= n) throw FlashError(FLASH_ERR_INVALID_ARG, "element index out of range");
+    double D[9];
+    auto fill = [&]() {
+      for (int a = 0; a < 3; ++a)
+        for (int r = 0; r < 3; ++r) D[3 * r + a] = d.rest_x[3 * id[a + 1] + r] - d.rest_x[3 * id[0] + r];
+    };
+    fill();
+    double det = D[0] * (D[4] * D[8] - D[5] * D[7]) - D[1] * (D[3] * D[8] - D[5] * D[6]) +
+                 D[2] * (D[3] * D[7] - D[4] * D[6]);
+    if (det < 0) { std::swap(id[2], id[3]); fill(); det = -det; }
+    if (!(det > 0)) throw FlashError(FLASH_ERR_INVALID_ARG, "degenerate rest tet");
+    double* Bt = &H.Bm[9 * (size_t)t];
+    Bt[0] = (D[4] * D[8] - D[5] * D[7]) / det;
+    Bt[1] = (D[2] * D[7] - D[1] * D[8]) / det;
+    Bt[2] = (D[1] * D[5] - D[2] * D[4]) / det;
+    Bt[3] = (D[5] * D[6] - D[3] * D[8]) / det;
+    Bt[4] = (D[0] * D[8] - D[2] * D[6]) / det;
+    Bt[5] = (D[2] * D[3] - D[0] * D[5]) / det;
+    Bt[6] = (D[3] * D[7] - D[4] * D[6]) / det;
+    Bt[7] = (D[1] * D[6] - D[0] * D[7]) / det;
+    Bt[8] = (D[0] * D[4] - D[1] * D[3]) / det;
+    const double V = det / 6.0;
+    H.w[t] = 2.0 * muL * V;
+    for (int a = 0; a < 4; ++a) H.mass[id[a]] += d.density * V / 4.0;
+  }
+}
+
+// Skyline (profile) Cholesky of Abar followed by the explicit inverse.
+void system_inverse(const flash_env_desc& d, HostEnv& H, double h, int nthreads) {
+  const int n = H.n, m = H.m;
+  std::vector<int> first(n);
+  for (int i = 0; i < n; ++i) first[i] = i;
+  for (int t = 0; t < m; ++t) {
+    const int* id = &H.elem[4 * (size_t)t];
+    int lo = std::min(std::min(id[0], id[1]), std::min(id[2], id[3]));
+    for (int a = 0; a < 4; ++a) first[id[a]] = std::min(first[id[a]], lo);
+  }
+  std::vector<size_t> rp(n + 1, 0);
+  for (int i = 0; i < n; ++i) rp[i + 1] = rp[i] + (size_t)(i - first[i] + 1);
+  std::vector<double> L(rp[n], 0.0);
+  auto at = [&](int i, int j) -> double& { return L[rp[i] + (j - first[i])]; };
+  for (int i = 0; i < n; ++i) at(i, i) += H.mass[i];
+  const double hh = h * h;
+  for (int t = 0; t < m; ++t) {
+    const int* id = &H.elem[4 * (size_t)t];
+    const double* Bt = &H.Bm[9 * (size_t)t];
+    double gN[4][3];
+    for (int c = 0; c < 3; ++c) {
+      gN[1][c] = Bt[c]; gN[2][c] = Bt[3 + c]; gN[3][c] = Bt[6 + c];
+      gN[0][c] = -(Bt[c] + Bt[3 + c] + Bt[6 + c]);
+    }
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        int i = id[a], j = id[b];
+        if (j > i) continue;
+        double v = hh * H.w[t] * (gN[a][0] * gN[b][0] + gN[a][1] * gN[b][1] + gN[a][2] * gN[b][2]);
+        at(i, j) += v;
+      }
+  }
+  // Crout factorisation in place
+  for (int i = 0; i < n; ++i) {
+    for (int j = first[i]; j <= i; ++j) {
+      double s = at(i, j);
+      const int k0 = std::max(first[i], first[j]);
+      for (int k = k0; k < j; ++k) s -= at(i, k) * at(j, k);
+      if (j < i) at(i, j) = s / at(j, j);
+      else {
+        if (!(s > 0)) throw FlashError(FLASH_ERR_INVALID_ARG, "system matrix not positive definite");
+        at(i, i) = std::sqrt(s);
+      }
+    }
+  }
+  H.Ginv.assign((size_t)n * n, 0.0);
+  std::atomic<int> next(0);
+  auto worker = [&]() {
+    std::vector<double> y(n);
+    for (;;) {
+      const int c = next.fetch_add(1);
+      if (c >= n) break;
+      // L y = e_c
+      y[c] = 1.0 / at(c, c);
+      for (int i = c + 1; i < n; ++i) {
+        double s = 0.0;
+        for (int k = std::max(first[i], c); k < i; ++k) s -= at(i, k) * y[k];
+        y[i] = s / at(i, i);
+      }
+      // L^T x = y, rows >= c only
+      for (int i = n - 1; i >= c; --i) {
+        const double xi = y[i] / at(i, i);
+        y[i] = xi;
+        for (int k = std::max(first[i], c); k < i; ++k) y[k] -= at(i, k) * xi;
+      }
+      for (int i = c; i < n; ++i) {
+        H.Ginv[(size_t)i * n + c] = y[i];
+        H.Ginv[(size_t)c * n + i] = y[i];
+      }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nthreads; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+}
+
+template <class T>
+T* dalloc(size_t count, std::vector<void*>& owned) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  HIPCHK(hipMalloc(&p, count * sizeof(T)));
+  owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+const char* kNames[K_COUNT] = {"detect", "gather", "project", "assemble", "apply", "csp", "correct",
+                               "finalize", "mlp"};
+
+}  // namespace
+
+struct flash_batch {
+  flash_params p{};
+  int n_envs = 0;
+  bool fp64 = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int NV = 0, NT = 0, max_ld = 0;
+  std::vector<int> voff, toff, nv;
+  std::vector<double> mu;
+  std::vector<void*> owned;
+  DevBatch<float> bf{};
+  DevBatch<double> bd{};
+  void* mu_dev = nullptr;
+  // obstacles (host mirror of what was last set)
+  std::vector<int> nobs;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  std::vector<hipEvent_t> pool;
+  double tot_ms[K_COUNT] = {};
+  int64_t cnt[K_COUNT] = {};
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int device = 0;
+
+  ~flash_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto& pe : pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
+    for (auto ev : pool) (void)hipEventDestroy(ev);
+    for (void* q : owned) (void)hipFree(q);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+
+  hipEvent_t ev() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    HIPCHK(hipEventCreate(&e));
+    return e;
+  }
+
+  template <class F>
+  void launch(int kid, F&& f) {
+    if (!timing) { f(); return; }
+    hipEvent_t a = ev(), b = ev();
+    HIPCHK(hipEventRecord(a, stream));
+    f();
+    HIPCHK(hipEventRecord(b, stream));
+    pending.push_back({kid, {a, b}});
+  }
+
+  void collect_timing() {
+    if (pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(stream));
+    for (auto& pe : pending) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, pe.second.first, pe.second.second));
+      tot_ms[pe.first] += ms;
+      cnt[pe.first] += 1;
+      pool.push_back(pe.second.first);
+      pool.push_back(pe.second.second);
+    }
+    pending.clear();
+  }
+
+  template <class T>
+  void enqueue_step(const DevBatch<T>& B) {
+    const T* mu_d = static_cast<const T*>(mu_dev);
+    launch(K_DETECT, [&] { launch_detect<T>(B, mu_d, stream); });
+    launch(K_GATHER, [&] { launch_gather<T>(B, stream); });
+    for (int k = 0; k < p.lg_iterations; ++k) {
+      launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
+      launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });
+      launch(K_APPLY, [&] { launch_apply<T>(B, max_ld, stream); });
+      launch(K_CSP, [&] { launch_csp<T>(B, mu_d, k == 0 ? 1 : 0, stream); });
+      launch(K_CORRECT, [&] { launch_correct<T>(B, max_ld, stream); });
+    }
+    launch(K_FINALIZE, [&] { launch_finalize<T>(B, mu_d, stream); });
+    HIPCHK(hipGetLastError());
+  }
+
+  void step(int n) {
+    if (p.use_graph && !timing) {
+      if (!gexec) {
+        HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        try {
+          if (fp64) enqueue_step(bd); else enqueue_step(bf);
+        } catch (...) {
+          hipGraph_t g;
+          (void)hipStreamEndCapture(stream, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        HIPCHK(hipStreamEndCapture(stream, &graph));
+        HIPCHK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      }
+      for (int i = 0; i < n; ++i) HIPCHK(hipGraphLaunch(gexec, stream));
+      return;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (fp64) enqueue_step(bd); else enqueue_step(bf);
+    }
+  }
+};
+
+namespace {
+
+template <class T>
+void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env_desc* envs) {
+  auto& own = b->owned;
+  const int ne = b->n_envs;
+  DevBatch<T> B{};
+  B.n_envs = ne;
+  B.NV = b->NV;
+  B.NT = b->NT;
+  B.cap = b->p.max_contacts_per_env > 0 ? b->p.max_contacts_per_env : 512;
+  B.rmax = std::min(3 * B.cap, 768);
+  B.max_newton = b->p.max_inner_iterations > 0 ? b->p.max_inner_iterations : 50;
+  B.lg_iterations = b->p.lg_iterations;
+  B.h = b->p.h;
+  for (int k = 0; k < 3; ++k) B.g[k] = b->p.gravity[k];
+  B.margin = b->p.contact_margin;
+  B.tol = b->p.inner_tol > 0 ? b->p.inner_tol : (sizeof(T) == 4 ? 0.25 * b->p.ncp_tol : 1e-12);
+  B.max_force = b->p.max_force;
+  B.warm_start = b->p.warm_start;
+  const int NV = b->NV, NT = b->NT;
+  const size_t cap = (size_t)B.cap;
+
+  std::vector<int> vert_env(NV), tet_env(NT);
+  for (int e = 0; e < ne; ++e) {
+    for (int i = b->voff[e]; i < b->voff[e + 1]; ++i) vert_env[i] = e;
+    for (int t = b->toff[e]; t < b->toff[e + 1]; ++t) tet_env[t] = e;
+  }
+  std::vector<T> x(3 * (size_t)NV), mass(NV), tB(9 * (size_t)NT), tw(NT);
+  std::vector<int> tidx(4 * (size_t)NT);
+  std::vector<int> inc_off(NV + 1, 0), inc(4 * (size_t)NT);
+  for (int e = 0; e < ne; ++e) {
+    const HostEnv& h = H[e];
+    const int vo = b->voff[e], to = b->toff[e];
+    for (int i = 0; i < h.n; ++i) {
+      mass[vo + i] = (T)h.mass[i];
+      for (int k = 0; k < 3; ++k) x[(size_t)k * NV + vo + i] = (T)envs[e].rest_x[3 * i + k];
+    }
+    for (int t = 0; t < h.m; ++t) {
+      for (int a = 0; a < 4; ++a) tidx[(size_t)a * NT + to + t] = vo + h.elem[4 * (size_t)t + a];
+      for (int q = 0; q < 9; ++q) tB[(size_t)q * NT + to + t] = (T)h.Bm[9 * (size_t)t + q];
+      tw[to + t] = (T)h.w[t];
+      for (int a = 0; a < 4; ++a) inc_off[vo + h.elem[4 * (size_t)t + a] + 1] += 1;
+    }
+  }
+  for (int i = 0; i < NV; ++i) inc_off[i + 1] += inc_off[i];
+  {
+    std::vector<int> fillp(inc_off.begin(), inc_off.end() - 1);
+    for (int t = 0; t < NT; ++t)
+      for (int a = 0; a < 4; ++a) inc[fillp[tidx[(size_t)a * NT + t]]++] = t * 4 + a;
+  }
+  // dense inverses
+  std::vector<int64_t> goff(ne);
+  std::vector<int> gld(ne);
+  int64_t gtot = 0;
+  int max_ld = 0;
+  for (int e = 0; e < ne; ++e) {
+    const int n = H[e].n;
+    const int ld = (n + 3) / 4 * 4;
+    goff[e] = gtot;
+    gld[e] = ld;
+    gtot += (int64_t)n * ld;
+    max_ld = std::max(max_ld, ld);
+  }
+  b->max_ld = max_ld;
+  T* G = dalloc<T>((size_t)gtot, own);
+  {
+    std::vector<T> blk;
+    for (int e = 0; e < ne; ++e) {
+      const int n = H[e].n, ld = gld[e];
+      blk.assign((size_t)n * ld, T(0));
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) blk[(size_t)i * ld + j] = (T)H[e].Ginv[(size_t)i * n + j];
+      HIPCHK(hipMemcpy(G + goff[e], blk.data(), blk.size() * sizeof(T), hipMemcpyHostToDevice));
+    }
+  }
+  auto up = [&](auto* dst, const auto& src) {
+    HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(src[0]), hipMemcpyHostToDevice));
+  };
+  int* d_voff = dalloc<int>(ne + 1, own); up(d_voff, b->voff);
+  int* d_toff = dalloc<int>(ne + 1, own); up(d_toff, b->toff);
+  int* d_ve = dalloc<int>(NV, own); up(d_ve, vert_env);
+  int* d_te = dalloc<int>(NT, own); up(d_te, tet_env);
+  B.voff = d_voff; B.toff = d_toff; B.vert_env = d_ve; B.tet_env = d_te;
+  B.x = dalloc<T>(3 * (size_t)NV, own); up(B.x, x);
+  B.v = dalloc<T>(3 * (size_t)NV, own);
+  HIPCHK(hipMemset(B.v, 0, 3 * (size_t)NV * sizeof(T)));
+  B.u = dalloc<T>(3 * (size_t)NV, own);
+  B.ut = dalloc<T>(3 * (size_t)NV, own);
+  B.z = dalloc<T>(3 * (size_t)NV, own);
+  B.b = dalloc<T>(3 * (size_t)NV, own);
+  HIPCHK(hipMemset(B.u, 0, 3 * (size_t)NV * sizeof(T)));
+  T* d_mass = dalloc<T>(NV, own); up(d_mass, mass); B.mass = d_mass;
+  int* d_tidx = dalloc<int>(4 * (size_t)NT, own); up(d_tidx, tidx); B.tet_idx = d_tidx;
+  T* d_tB = dalloc<T>(9 * (size_t)NT, own); up(d_tB, tB); B.tet_B = d_tB;
+  T* d_tw = dalloc<T>(NT, own); up(d_tw, tw); B.tet_w = d_tw;
+  B.fel = dalloc<T>(12 * (size_t)NT, own);
+  int* d_io = dalloc<int>(NV + 1, own); up(d_io, inc_off); B.inc_off = d_io;
+  int* d_inc = dalloc<int>(4 * (size_t)NT, own); up(d_inc, inc); B.inc = d_inc;
+  B.G = G;
+  int64_t* d_goff = dalloc<int64_t>(ne, own); up(d_goff, goff); B.goff = d_goff;
+  int* d_gld = dalloc<int>(ne, own); up(d_gld, gld); B.gld = d_gld;
+  // obstacles
+  const size_t no = (size_t)ne * kMaxObs;
+  B.nobs = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.nobs, 0, ne * sizeof(int)));
+  B.obs_kind = dalloc<int>(no, own);
+  B.obs_move = dalloc<int>(no, own);
+  B.obs_c = dalloc<double>(3 * no, own);
+  B.obs_R = dalloc<double>(9 * no, own);
+  B.obs_size = dalloc<double>(3 * no, own);
+  B.obs_vel = dalloc<double>(3 * no, own);
+  // contacts
+  B.ccount = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.ccount, 0, ne * sizeof(int)));
+  B.cvert = dalloc<int>(ne * cap, own);
+  B.cobs = dalloc<int>(ne * cap, own);
+  B.cframe = dalloc<T>(9 * ne * cap, own);
+  B.cd0 = dalloc<T>(ne * cap, own);
+  B.cdob = dalloc<T>(2 * ne * cap, own);
+  B.cs = dalloc<T>(ne * cap, own);
+  B.clam = dalloc<T>(3 * ne * cap, own);
+  B.cforce = dalloc<T>(3 * ne * cap, own);
+  B.cnew = dalloc<int>(ne * cap, own);
+  B.cd0d = dalloc<double>(ne * cap, own);
+  B.Gc = dalloc<T>(ne * cap * cap, own);
+  B.Ginv = dalloc<T>(ne * cap * cap, own);
+  {
+    const size_t rm = (size_t)B.rmax;
+    const size_t tcount = ne * (rm * rm + 8 * rm) + (ne * rm * sizeof(int) + sizeof(T) - 1) / sizeof(T);
+    B.Cm = dalloc<T>(tcount, own);
+  }
+  B.base = dalloc<int>(ne * cap, own);
+  B.nbase = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.nbase, 0, ne * sizeof(int)));
+  B.cache_f = dalloc<T>(3 * (size_t)NV * kMaxObs, own);
+  B.cache_stamp = dalloc<int>((size_t)NV * kMaxObs, own);
+  HIPCHK(hipMemset(B.cache_stamp, 0xFF, (size_t)NV * kMaxObs * sizeof(int)));
+  B.stamp = dalloc<int>(1, own);
+  {
+    int one = 1;
+    HIPCHK(hipMemcpy(B.stamp, &one, sizeof(int), hipMemcpyHostToDevice));
+  }
+  B.resid = dalloc<double>(ne, own);
+  HIPCHK(hipMemset(B.resid, 0, ne * sizeof(double)));
+  B.iters = dalloc<int>(ne, own);
+  B.refac = dalloc<int>(ne, own);
+  B.flags = dalloc<int>(ne, own);
+  B.fp64_polar = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.iters, 0, ne * sizeof(int)));
+  HIPCHK(hipMemset(B.refac, 0, ne * sizeof(int)));
+  HIPCHK(hipMemset(B.flags, 0, ne * sizeof(int)));
+  HIPCHK(hipMemset(B.fp64_polar, 0, ne * sizeof(int)));
+  B.mlp_w = nullptr;
+  B.mlp_norm = nullptr;
+  std::vector<T> mu(ne);
+  for (int e = 0; e < ne; ++e) mu[e] = (T)b->mu[e];
+  T* d_mu = dalloc<T>(ne, own); up(d_mu, mu);
+  b->mu_dev = d_mu;
+  if constexpr (sizeof(T) == 4) b->bf = B; else b->bd = B;
+}
+
+template <class T>
+DevBatch<T>& dev(flash_batch* b);
+template <> DevBatch<float>& dev<float>(flash_batch* b) { return b->bf; }
+template <> DevBatch<double>& dev<double>(flash_batch* b) { return b->bd; }
+
+template <class T>
+void set_state_t(flash_batch* b, int env, const double* x, const double* v) {
+  DevBatch<T>& B = dev<T>(b);
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->n_envs : env + 1;
+  const int vo = b->voff[e0], n = b->voff[e1] - vo;
+  std::vector<T> buf(n);
+  for (int k = 0; k < 3; ++k) {
+    for (int i = 0; i < n; ++i) buf[i] = (T)x[3 * (size_t)i + k];
+    HIPCHK(hipMemcpyAsync(B.x + (size_t)k * b->NV + vo, buf.data(), n * sizeof(T), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    if (v) {
+      for (int i = 0; i < n; ++i) buf[i] = (T)v[3 * (size_t)i + k];
+      HIPCHK(hipMemcpyAsync(B.v + (size_t)k * b->NV + vo, buf.data(), n * sizeof(T), hipMemcpyHostToDevice, b->stream));
+      HIPCHK(hipStreamSynchronize(b->stream));
+    }
+  }
+  HIPCHK(hipMemsetAsync(B.cache_stamp + (size_t)vo * kMaxObs, 0xFF, (size_t)n * kMaxObs * sizeof(int), b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+}
+
+template <class T>
+void get_state_t(flash_batch* b, int env, double* x, double* v) {
+  DevBatch<T>& B = dev<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->n_envs : env + 1;
+  const int vo = b->voff[e0], n = b->voff[e1] - vo;
+  std::vector<T> buf(n);
+  for (int k = 0; k < 3; ++k) {
+    if (x) {
+      HIPCHK(hipMemcpy(buf.data(), B.x + (size_t)k * b->NV + vo, n * sizeof(T), hipMemcpyDeviceToHost));
+      for (int i = 0; i < n; ++i) x[3 * (size_t)i + k] = (double)buf[i];
+    }
+    if (v) {
+      HIPCHK(hipMemcpy(buf.data(), B.v + (size_t)k * b->NV + vo, n * sizeof(T), hipMemcpyDeviceToHost));
+      for (int i = 0; i < n; ++i) v[3 * (size_t)i + k] = (double)buf[i];
+    }
+  }
+}
+
+template <class T>
+int contacts_t(flash_batch* b, int env, flash_contact* out, int capacity, int* n_out) {
+  DevBatch<T>& B = dev<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int ne = b->n_envs, cap = B.cap;
+  std::vector<int> cnt(ne);
+  HIPCHK(hipMemcpy(cnt.data(), B.ccount, ne * sizeof(int), hipMemcpyDeviceToHost));
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? ne : env + 1;
+  int total = 0;
+  for (int e = e0; e < e1; ++e) total += cnt[e];
+  *n_out = total;
+  if (total > capacity || !out) return total > capacity ? 1 : 0;
+  int o = 0;
+  std::vector<int> cv(cap), co(cap);
+  std::vector<T> fr(9 * (size_t)cap), lam(3 * (size_t)cap), frc(3 * (size_t)cap);
+  std::vector<double> d0(cap);
+  for (int e = e0; e < e1; ++e) {
+    const int c = cnt[e];
+    if (!c) continue;
+    const size_t base = (size_t)e * cap;
+    HIPCHK(hipMemcpy(cv.data(), B.cvert + base, c * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(co.data(), B.cobs + base, c * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(fr.data(), B.cframe + 9 * base, 9 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(lam.data(), B.clam + 3 * base, 3 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(frc.data(), B.cforce + 3 * base, 3 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(d0.data(), B.cd0d + base, c * sizeof(double), hipMemcpyDeviceToHost));
+    for (int j = 0; j < c; ++j) {
+      flash_contact& r = out[o++];
+      r.env = e;
+      r.vertex = cv[j];
+      r.obstacle = co[j];
+      for (int k = 0; k < 3; ++k) {
+        r.normal[k] = (double)fr[9 * j + k];
+        r.tangent1[k] = (double)fr[9 * j + 3 + k];
+        r.lambda[k] = (double)lam[3 * j + k];
+        r.impulse[k] = b->p.h * (double)frc[3 * j + k];
+      }
+      r.gap = d0[j];
+      const double ln = r.lambda[0], lt = std::sqrt(r.lambda[1] * r.lambda[1] + r.lambda[2] * r.lambda[2]);
+      r.mode = ln <= 0 ? 0 : (lt < b->mu[e] * ln * (1.0 - 1e-6) ? 1 : 2);
+    }
+  }
+  return 0;
+}
+
+template <class T>
+void stats_t(flash_batch* b, flash_env_stats* st) {
+  DevBatch<T>& B = dev<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int ne = b->n_envs;
+  std::vector<double> r(ne);
+  std::vector<int> it(ne), rf(ne), fl(ne), fp(ne), cc(ne);
+  HIPCHK(hipMemcpy(r.data(), B.resid, ne * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(it.data(), B.iters, ne * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(rf.data(), B.refac, ne * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fl.data(), B.flags, ne * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(fp.data(), B.fp64_polar, ne * sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(cc.data(), B.ccount, ne * sizeof(int), hipMemcpyDeviceToHost));
+  for (int e = 0; e < ne; ++e) {
+    st[e].inner_iterations = it[e];
+    st[e].refactorizations = rf[e];
+    st[e].contacts = cc[e];
+    st[e].fp64_polar = fp[e];
+    st[e].flags = fl[e] | (r[e] > b->p.ncp_tol ? 2 : 0);
+    st[e].reserved = 0;
+    st[e].residual = r[e];
+  }
+}
+
+template <class T>
+void set_obstacles_t(flash_batch* b, int env, const flash_obstacle* o, int n) {
+  DevBatch<T>& B = dev<T>(b);
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->n_envs : env + 1;
+  const int ne = e1 - e0;
+  std::vector<int> kind((size_t)ne * kMaxObs, 0), mv((size_t)ne * kMaxObs, 0), cnt(ne, n);
+  std::vector<double> c(3 * (size_t)ne * kMaxObs, 0), R(9 * (size_t)ne * kMaxObs, 0), sz(3 * (size_t)ne * kMaxObs, 0),
+      vel(3 * (size_t)ne * kMaxObs, 0);
+  for (int e = 0; e < ne; ++e)
+    for (int q = 0; q < n; ++q) {
+      const flash_obstacle& ob = o[(size_t)e * n + q];
+      const size_t s = (size_t)e * kMaxObs + q;
+      kind[s] = ob.kind;
+      mv[s] = ob.move_steps;
+      for (int k = 0; k < 3; ++k) { c[3 * s + k] = ob.center[k]; sz[3 * s + k] = ob.size[k]; vel[3 * s + k] = ob.lin_vel[k]; }
+      for (int k = 0; k < 9; ++k) R[9 * s + k] = ob.rot[k];
+    }
+  const size_t so = (size_t)e0 * kMaxObs;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  HIPCHK(hipMemcpy(B.obs_kind + so, kind.data(), kind.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.obs_move + so, mv.data(), mv.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.obs_c + 3 * so, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(const_cast<double*>(B.obs_R) + 9 * so, R.data(), R.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(const_cast<double*>(B.obs_size) + 3 * so, sz.data(), sz.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(const_cast<double*>(B.obs_vel) + 3 * so, vel.data(), vel.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.nobs + e0, cnt.data(), ne * sizeof(int), hipMemcpyHostToDevice));
+  for (int e = e0; e < e1; ++e) b->nobs[e] = n;
+}
+
+template <class T>
+void get_obstacles_t(flash_batch* b, int env, flash_obstacle* o, int n) {
+  DevBatch<T>& B = dev<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int q = 0; q < n; ++q) {
+    const size_t s = (size_t)env * kMaxObs + q;
+    flash_obstacle& ob = o[q];
+    HIPCHK(hipMemcpy(&ob.kind, B.obs_kind + s, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&ob.move_steps, B.obs_move + s, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ob.center, B.obs_c + 3 * s, 3 * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ob.rot, B.obs_R + 9 * s, 9 * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ob.size, B.obs_size + 3 * s, 3 * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(ob.lin_vel, B.obs_vel + 3 * s, 3 * sizeof(double), hipMemcpyDeviceToHost));
+  }
+}
+
+bool bad_env(flash_batch* b, int env) { return env < -1 || env >= b->n_envs; }
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* flash_last_error(void) { return g_err.c_str(); }
+const char* flash_version(void) { return "flash-mi355x 0.1 (gfx950)"; }
+const char* flash_kernel_name(int32_t i) { return (i >= 0 && i < K_COUNT) ? kNames[i] : ""; }
+
+flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, const flash_params* p,
+                                void* hip_stream, flash_batch** out) {
+  if (!envs || !p || !out || n_envs <= 0) return fail(FLASH_ERR_INVALID_ARG, "null argument or n_envs <= 0");
+  *out = nullptr;
+  if (!(p->h > 0) || p->lg_iterations <= 0 || !(p->ncp_tol > 0) || !(p->contact_margin >= 0) ||
+      !(p->inner_tol >= 0) || p->max_contacts_per_env < 0 || p->max_contacts_per_env > 4096)
+    return fail(FLASH_ERR_INVALID_ARG, "invalid solver parameters");
+  if (p->precision != FLASH_FP32 && p->precision != FLASH_FP64)
+    return fail(FLASH_ERR_INVALID_ARG, "precision must be FLASH_FP32 or FLASH_FP64");
+  for (int e = 0; e < n_envs; ++e) {
+    const flash_env_desc& d = envs[e];
+    if (d.elem != FLASH_TET) return fail(FLASH_ERR_UNSUPPORTED, "only FLASH_TET environments are built");
+    if (d.n_vertices <= 0 || d.n_elements <= 0 || !d.rest_x || !d.elements)
+      return fail(FLASH_ERR_INVALID_ARG, "empty environment");
+    if (!(d.density > 0) || !(d.young > 0) || !(d.poisson > -1 && d.poisson < 0.5) || !(d.mu >= 0))
+      return fail(FLASH_ERR_INVALID_ARG, "invalid material");
+  }
+  flash_batch* b = nullptr;
+  try {
+    b = new flash_batch();
+    b->p = *p;
+    b->n_envs = n_envs;
+    b->fp64 = p->precision == FLASH_FP64;
+    HIPCHK(hipGetDevice(&b->device));
+    if (hip_stream) b->stream = static_cast<hipStream_t>(hip_stream);
+    else { HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)); b->own_stream = true; }
+    b->voff.assign(n_envs + 1, 0);
+    b->toff.assign(n_envs + 1, 0);
+    b->mu.resize(n_envs);
+    b->nobs.assign(n_envs, 0);
+    for (int e = 0; e < n_envs; ++e) {
+      b->voff[e + 1] = b->voff[e] + envs[e].n_vertices;
+      b->toff[e + 1] = b->toff[e] + envs[e].n_elements;
+      b->mu[e] = envs[e].mu;
+    }
+    b->NV = b->voff[n_envs];
+    b->NT = b->toff[n_envs];
+    std::vector<HostEnv> H(n_envs);
+    const int nth = std::max(1u, std::thread::hardware_concurrency());
+    for (int e = 0; e < n_envs; ++e) {
+      tet_data(envs[e], H[e]);
+      system_inverse(envs[e], H[e], p->h, nth);
+    }
+    if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
+    // dynamic LDS of the contact solve above the default limit
+    if (b->fp64) prepare_csp<double>(b->bd.cap); else prepare_csp<float>(b->bf.cap);
+    *out = b;
+    return FLASH_OK;
+  } catch (const FlashError& ex) {
+    delete b;
+    return fail(ex.st, ex.what());
+  } catch (const std::exception& ex) {
+    delete b;
+    return fail(FLASH_ERR_OUT_OF_MEMORY, ex.what());
+  }
+}
+
+flash_status flash_destroy_batch(flash_batch* b) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  (void)hipStreamSynchronize(b->stream);
+  delete b;
+  return FLASH_OK;
+}
+
+#define GUARD(body)                                            \
+  try {                                                        \
+    body;                                                      \
+  } catch (const FlashError& ex) {                             \
+    return fail(ex.st, ex.what());                             \
+  } catch (const std::exception& ex) {                         \
+    return fail(FLASH_ERR_DEVICE, ex.what());                  \
+  }
+
+flash_status flash_set_state(flash_batch* b, int32_t env, const double* x, const double* v) {
+  if (!b || !x || bad_env(b, env)) return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env or null x");
+  GUARD(if (b->fp64) set_state_t<double>(b, env, x, v); else set_state_t<float>(b, env, x, v));
+  return FLASH_OK;
+}
+
+flash_status flash_get_state(flash_batch* b, int32_t env, double* x, double* v) {
+  if (!b || bad_env(b, env)) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or env");
+  GUARD(if (b->fp64) get_state_t<double>(b, env, x, v); else get_state_t<float>(b, env, x, v));
+  return FLASH_OK;
+}
+
+flash_status flash_set_obstacles(flash_batch* b, int32_t env, const flash_obstacle* o, int32_t n) {
+  if (!b || bad_env(b, env) || n < 0 || n > FLASH_MAX_OBSTACLES || (n > 0 && !o))
+    return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env or obstacle count");
+  const int ne = env < 0 ? b->n_envs : 1;
+  for (int q = 0; q < ne * n; ++q)
+    if (o[q].kind < FLASH_PLANE || o[q].kind > FLASH_CAPSULE) return fail(FLASH_ERR_INVALID_ARG, "bad obstacle kind");
+  GUARD(if (b->fp64) set_obstacles_t<double>(b, env, o, n); else set_obstacles_t<float>(b, env, o, n));
+  return FLASH_OK;
+}
+
+flash_status flash_get_obstacles(flash_batch* b, int32_t env, flash_obstacle* o, int32_t capacity, int32_t* n_out) {
+  if (!b || env < 0 || env >= b->n_envs || !n_out) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or env");
+  const int n = b->nobs[env];
+  *n_out = n;
+  if (capacity < n || !o) return fail(FLASH_ERR_CAPACITY, "obstacle capacity too small");
+  GUARD(if (b->fp64) get_obstacles_t<double>(b, env, o, n); else get_obstacles_t<float>(b, env, o, n));
+  return FLASH_OK;
+}
+
+flash_status flash_step(flash_batch* b, int32_t n_steps) {
+  if (!b || n_steps < 0) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or step count");
+  GUARD(b->step(n_steps));
+  return FLASH_OK;
+}
+
+flash_status flash_synchronize(flash_batch* b) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  GUARD(HIPCHK(hipStreamSynchronize(b->stream)));
+  return FLASH_OK;
+}
+
+flash_status flash_contacts(flash_batch* b, int32_t env, flash_contact* out, int32_t capacity, int32_t* n_out) {
+  if (!b || bad_env(b, env) || !n_out || capacity < 0) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  int over = 0;
+  GUARD(over = b->fp64 ? contacts_t<double>(b, env, out, capacity, n_out) : contacts_t<float>(b, env, out, capacity, n_out));
+  if (over) return fail(FLASH_ERR_CAPACITY, "contact capacity too small");
+  return FLASH_OK;
+}
+
+flash_status flash_stats(flash_batch* b, flash_env_stats* per_env) {
+  if (!b || !per_env) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  GUARD(if (b->fp64) stats_t<double>(b, per_env); else stats_t<float>(b, per_env));
+  return FLASH_OK;
+}
+
+flash_status flash_residual(flash_batch* b, double* per_env, double* max_out, int32_t* inner_iters) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  std::vector<flash_env_stats> st(b->n_envs);
+  flash_status s = flash_stats(b, st.data());
+  if (s != FLASH_OK) return s;
+  double m = 0.0;
+  bool nonfinite = false, over = false;
+  for (int e = 0; e < b->n_envs; ++e) {
+    if (per_env) per_env[e] = st[e].residual;
+    if (inner_iters) inner_iters[e] = st[e].inner_iterations;
+    if (!(st[e].residual == st[e].residual) || (st[e].flags & 1)) nonfinite = true;
+    else m = std::max(m, st[e].residual);
+    if (st[e].residual > b->p.ncp_tol) over = true;
+  }
+  if (max_out) *max_out = nonfinite ? NAN : m;
+  if (nonfinite) return fail(FLASH_ERR_NONFINITE, "an environment holds a non-finite state");
+  if (over) return fail(FLASH_ERR_NOT_CONVERGED, "an environment ended above ncp_tol");
+  return FLASH_OK;
+}
+
+flash_status flash_set_kernel_timing(flash_batch* b, int32_t enable) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  GUARD(b->collect_timing());
+  b->timing = enable != 0;
+  for (int k = 0; k < K_COUNT; ++k) { b->tot_ms[k] = 0; b->cnt[k] = 0; }
+  return FLASH_OK;
+}
+
+flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launches, int32_t cap, int32_t* n_out) {
+  if (!b || !n_out) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  GUARD(b->collect_timing());
+  *n_out = K_COUNT;
+  for (int k = 0; k < K_COUNT && k < cap; ++k) {
+    if (total_ms) total_ms[k] = b->tot_ms[k];
+    if (launches) launches[k] = b->cnt[k];
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_ws_load(flash_batch* b, const uint16_t* w, size_t n_params, const float* norm) {
+  (void)w; (void)n_params; (void)norm;
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  return fail(FLASH_ERR_UNSUPPORTED, "learned warm start not built in this library");
+}
+
+}  // extern "C"

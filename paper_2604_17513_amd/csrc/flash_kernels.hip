@@ -1,0 +1,914 @@
+// Step kernels: local projection, assembly gather, the explicit-inverse global
+// apply, the contact-space non-smooth Newton solve and the position update.
+//
+// Working variable: the per-step displacement u = q - x_t (x_t = positions at
+// the step start).  With A = M + h^2 sum_e w_e G_e^T G_e (Eq. 4) the assembled
+// system A q = b + h^2 H^T lambda becomes
+//     A u = M u~ + h^2 sum_e w_e G_e^T (p_e - G_e x_t) + h^2 H^T lambda,
+// u~ = h v + h^2 g, which keeps FP32 relative precision on small quantities.
+#include "flash_device.h"
+#include "flash_launch.h"
+
+namespace flash {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+template <class T>
+__device__ T wave_sum(T v) {
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+template <class T>
+__device__ T wave_max(T v) {
+  for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  return v;
+}
+
+// Block-wide reductions (every thread gets the result).  sh: >= kBlock/64 doubles.
+__device__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) sh[wave_id()] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < kBlock / 64; ++w) t += sh[w];
+  return t;
+}
+__device__ double block_max(double v, double* sh) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) sh[wave_id()] = v;
+  __syncthreads();
+  double t = sh[0];
+  for (int w = 1; w < kBlock / 64; ++w) t = fmax(t, sh[w]);
+  return t;
+}
+__device__ int block_excl_scan_i(int v, int* sh, int* total) {
+  int lane = lane_id(), wid = wave_id();
+  int incl = v;
+  for (int d = 1; d < 64; d <<= 1) {
+    int t = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += t;
+  }
+  __syncthreads();
+  if (lane == 63) sh[wid] = incl;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    int s = sh[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  *total = tot;
+  return off + incl - v;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 helpers (row-major)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ void cof3(const T* X, T* C, T* det) {
+  C[0] = X[4] * X[8] - X[5] * X[7];
+  C[1] = X[5] * X[6] - X[3] * X[8];
+  C[2] = X[3] * X[7] - X[4] * X[6];
+  C[3] = X[2] * X[7] - X[1] * X[8];
+  C[4] = X[0] * X[8] - X[2] * X[6];
+  C[5] = X[1] * X[6] - X[0] * X[7];
+  C[6] = X[1] * X[5] - X[2] * X[4];
+  C[7] = X[2] * X[3] - X[0] * X[5];
+  C[8] = X[0] * X[4] - X[1] * X[3];
+  *det = X[0] * C[0] + X[1] * C[1] + X[2] * C[2];
+}
+
+// Closest rotation of a well-conditioned F (det F > 0): orthogonal polar factor
+// by the scaled Newton iteration X <- (g X + X^-T / g) / 2, g = |det X|^-1/3.
+template <class T>
+__device__ void polar_newton(const T* F, T* R) {
+  T X[9], C[9], det;
+  for (int k = 0; k < 9; ++k) X[k] = F[k];
+  const T tol = sizeof(T) == 4 ? T(1e-6) : T(1e-13);
+  for (int it = 0; it < 20; ++it) {
+    cof3(X, C, &det);
+    T g = it < 8 ? T(1) / cbrt(det) : T(1);
+    T a = T(0.5) * g, bcoef = T(0.5) / (g * det);
+    T diff = 0;
+    for (int k = 0; k < 9; ++k) {
+      T xn = a * X[k] + bcoef * C[k];
+      T d = xn - X[k];
+      diff += d * d;
+      X[k] = xn;
+    }
+    if (diff < tol * tol) break;
+  }
+  for (int k = 0; k < 9; ++k) R[k] = X[k];
+}
+
+// FP64 closest rotation for any F (inverted or near-degenerate):
+// F^T F = V S^2 V^T by cyclic Jacobi, sigma descending, det V = +1;
+// u1 = F v1 / |F v1|, u2 = F v2 orthogonalised against u1, R = [u1 u2 u1 x u2] V^T.
+__device__ void polar_svd64(const double* F, double* R) {
+  double A[9], V[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      A[3 * r + c] = F[r] * F[c] + F[3 + r] * F[3 + c] + F[6 + r] * F[6 + c];
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    double dia = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      double apq = A[3 * p + q];
+      if (apq == 0.0) continue;
+      double th = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+      double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+      double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      // A <- J^T A J, V <- V J with J = I except J_pp = J_qq = c, J_pq = s, J_qp = -s
+      for (int k = 0; k < 3; ++k) {
+        double akp = A[3 * k + p], akq = A[3 * k + q];
+        A[3 * k + p] = c * akp - s * akq;
+        A[3 * k + q] = s * akp + c * akq;
+      }
+      for (int k = 0; k < 3; ++k) {
+        double apk = A[3 * p + k], aqk = A[3 * q + k];
+        A[3 * p + k] = c * apk - s * aqk;
+        A[3 * q + k] = s * apk + c * aqk;
+      }
+      for (int k = 0; k < 3; ++k) {
+        double vkp = V[3 * k + p], vkq = V[3 * k + q];
+        V[3 * k + p] = c * vkp - s * vkq;
+        V[3 * k + q] = s * vkp + c * vkq;
+      }
+    }
+  }
+  // sort eigenpairs descending
+  double ev[3] = {A[0], A[4], A[8]};
+  int o[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (ev[o[j]] > ev[o[i]]) { int t = o[i]; o[i] = o[j]; o[j] = t; }
+  double v1[3], v2[3], v3[3];
+  for (int k = 0; k < 3; ++k) { v1[k] = V[3 * k + o[0]]; v2[k] = V[3 * k + o[1]]; v3[k] = V[3 * k + o[2]]; }
+  double dv = v1[0] * (v2[1] * v3[2] - v2[2] * v3[1]) - v1[1] * (v2[0] * v3[2] - v2[2] * v3[0]) +
+              v1[2] * (v2[0] * v3[1] - v2[1] * v3[0]);
+  if (dv < 0) { v3[0] = -v3[0]; v3[1] = -v3[1]; v3[2] = -v3[2]; }
+  double u1[3], u2[3], u3[3];
+  for (int r = 0; r < 3; ++r) {
+    u1[r] = F[3 * r] * v1[0] + F[3 * r + 1] * v1[1] + F[3 * r + 2] * v1[2];
+    u2[r] = F[3 * r] * v2[0] + F[3 * r + 1] * v2[1] + F[3 * r + 2] * v2[2];
+  }
+  double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  if (n1 > 0) { u1[0] /= n1; u1[1] /= n1; u1[2] /= n1; }
+  else { u1[0] = v1[0]; u1[1] = v1[1]; u1[2] = v1[2]; }
+  double dp = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+  for (int r = 0; r < 3; ++r) u2[r] -= dp * u1[r];
+  double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  if (n2 > 1e-300) { u2[0] /= n2; u2[1] /= n2; u2[2] /= n2; }
+  else {
+    // any unit vector orthogonal to u1
+    int k = fabs(u1[0]) <= fabs(u1[1]) ? (fabs(u1[0]) <= fabs(u1[2]) ? 0 : 2) : (fabs(u1[1]) <= fabs(u1[2]) ? 1 : 2);
+    double e[3] = {0, 0, 0};
+    e[k] = 1;
+    u2[0] = e[1] * u1[2] - e[2] * u1[1];
+    u2[1] = e[2] * u1[0] - e[0] * u1[2];
+    u2[2] = e[0] * u1[1] - e[1] * u1[0];
+    double l = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+    u2[0] /= l; u2[1] /= l; u2[2] /= l;
+  }
+  u3[0] = u1[1] * u2[2] - u1[2] * u2[1];
+  u3[1] = u1[2] * u2[0] - u1[0] * u2[2];
+  u3[2] = u1[0] * u2[1] - u1[1] * u2[0];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R[3 * r + c] = u1[r] * v1[c] + u2[r] * v2[c] + u3[r] * v3[c];
+}
+
+// ---------------------------------------------------------------------------
+// local projection (Eq. 3) and per-tet vertex forces w (p - F(x_t)) gradN_a
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= B.NT) return;
+  const int NT = B.NT, NV = B.NV;
+  int id[4];
+  for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * NT + t];
+  T X0[3], U0[3], dx[3][3], du[3][3];
+  for (int k = 0; k < 3; ++k) { X0[k] = B.x[k * NV + id[0]]; U0[k] = B.u[k * NV + id[0]]; }
+  for (int a = 0; a < 3; ++a)
+    for (int k = 0; k < 3; ++k) {
+      dx[a][k] = B.x[k * NV + id[a + 1]] - X0[k];
+      du[a][k] = B.u[k * NV + id[a + 1]] - U0[k];
+    }
+  T Bm[9];
+  for (int k = 0; k < 9; ++k) Bm[k] = B.tet_B[k * NT + t];
+  // F = D_s B with D_s[:, a] = dx_a + du_a ; F_x = D_x B
+  T F[9], Fx[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) {
+      T f = 0, fx = 0;
+      for (int a = 0; a < 3; ++a) {
+        fx += dx[a][r] * Bm[3 * a + c];
+        f += (dx[a][r] + du[a][r]) * Bm[3 * a + c];
+      }
+      F[3 * r + c] = f;
+      Fx[3 * r + c] = fx;
+    }
+  T C[9], det;
+  cof3(F, C, &det);
+  T fn2 = 0;
+  for (int k = 0; k < 9; ++k) fn2 += F[k] * F[k];
+  // quality det F / (|F|_F / sqrt 3)^3; degenerate or inverted -> FP64 path
+  T q3 = fn2 * (T)(1.0 / 3.0);
+  T quality = det / (q3 * sqrt(q3));
+  T R[9];
+  if (det > T(0) && quality >= T(1e-2)) {
+    polar_newton(F, R);
+  } else {
+    double Fd[9], Rd[9];
+    for (int k = 0; k < 9; ++k) Fd[k] = (double)F[k];
+    polar_svd64(Fd, Rd);
+    for (int k = 0; k < 9; ++k) R[k] = (T)Rd[k];
+    atomicAdd(&B.fp64_polar[B.tet_env[t]], 1);
+  }
+  const T w = B.tet_w[t];
+  T P[9];
+  for (int k = 0; k < 9; ++k) P[k] = w * (R[k] - Fx[k]);
+  T f0[3] = {0, 0, 0};
+  for (int a = 0; a < 3; ++a) {
+    for (int r = 0; r < 3; ++r) {
+      T fa = P[3 * r] * Bm[3 * a] + P[3 * r + 1] * Bm[3 * a + 1] + P[3 * r + 2] * Bm[3 * a + 2];
+      B.fel[((a + 1) * 3 + r) * (size_t)NT + t] = fa;
+      f0[r] -= fa;
+    }
+  }
+  for (int r = 0; r < 3; ++r) B.fel[(size_t)r * NT + t] = f0[r];
+}
+
+// b = M u~ + h^2 sum over incident tets (fixed incidence order).
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= B.NV) return;
+  const int NT = B.NT, NV = B.NV;
+  T s0 = 0, s1 = 0, s2 = 0;
+  const int p1 = B.inc_off[i + 1];
+  for (int p = B.inc_off[i]; p < p1; ++p) {
+    const int ea = B.inc[p];
+    const int t = ea >> 2, a = ea & 3;
+    s0 += B.fel[(size_t)(a * 3 + 0) * NT + t];
+    s1 += B.fel[(size_t)(a * 3 + 1) * NT + t];
+    s2 += B.fel[(size_t)(a * 3 + 2) * NT + t];
+  }
+  const T hh = (T)(B.h * B.h);
+  const T m = B.mass[i];
+  B.b[i] = m * B.ut[i] + hh * s0;
+  B.b[NV + i] = m * B.ut[NV + i] + hh * s1;
+  B.b[2 * NV + i] = m * B.ut[2 * NV + i] + hh * s2;
+}
+
+// ---------------------------------------------------------------------------
+// Explicit-inverse products.  Gbar is symmetric, so row j of Gbar is also
+// column j: out[:, i] = sum_r Gbar[row_r, i] * vec_r, read along rows
+// (coalesced, 16-byte vectors, 4 waves split the rows, fixed-order LDS
+// reduction).  ROWS = false: rows are 0..n-1 and vec = b (z = Gbar b).
+// ROWS = true: rows are the contact vertices and vec = their world forces;
+// out = z + h^2 * sum (u = z + h^2 Gbar H^T lambda).
+// ---------------------------------------------------------------------------
+constexpr int kChunk = 1024;
+
+template <class T, bool ROWS>
+__global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B) {
+  constexpr int VW = 16 / sizeof(T);
+  constexpr int TILE = 64 * VW;
+  __shared__ T s_vec[3][kChunk];
+  __shared__ int s_row[kChunk];
+  __shared__ T s_red[kBlock / 64 - 1][3][TILE];
+  const int e = blockIdx.y;
+  const int v0 = B.voff[e];
+  const int n = B.voff[e + 1] - v0;
+  const int tile0 = blockIdx.x * TILE;
+  if (tile0 >= n) return;
+  const int ld = B.gld[e];
+  const T* G = B.G + B.goff[e];
+  const int nrows = ROWS ? B.ccount[e] : n;
+  const int lane = lane_id(), wid = wave_id();
+  const int col0 = tile0 + lane * VW;
+  const bool active = col0 < ld;
+  T acc[VW][3];
+  for (int q = 0; q < VW; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0;
+  for (int r0 = 0; r0 < nrows; r0 += kChunk) {
+    const int nr = min(kChunk, nrows - r0);
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += kBlock) {
+      if (ROWS) {
+        const int j = e * B.cap + r0 + r;
+        s_row[r] = B.cvert[j];
+        s_vec[0][r] = B.cforce[3 * j];
+        s_vec[1][r] = B.cforce[3 * j + 1];
+        s_vec[2][r] = B.cforce[3 * j + 2];
+      } else {
+        s_row[r] = r0 + r;
+        s_vec[0][r] = B.b[v0 + r0 + r];
+        s_vec[1][r] = B.b[B.NV + v0 + r0 + r];
+        s_vec[2][r] = B.b[2 * B.NV + v0 + r0 + r];
+      }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll 4
+      for (int r = wid; r < nr; r += kBlock / 64) {
+        const T* gp = G + (size_t)s_row[r] * ld + col0;
+        T g[VW];
+        if constexpr (VW == 4) {
+          float4 q = *reinterpret_cast<const float4*>(gp);
+          g[0] = q.x; g[1] = q.y; g[2] = q.z; g[3] = q.w;
+        } else {
+          double2 q = *reinterpret_cast<const double2*>(gp);
+          g[0] = q.x; g[1] = q.y;
+        }
+        const T b0 = s_vec[0][r], b1 = s_vec[1][r], b2 = s_vec[2][r];
+        for (int q = 0; q < VW; ++q) {
+          acc[q][0] += g[q] * b0;
+          acc[q][1] += g[q] * b1;
+          acc[q][2] += g[q] * b2;
+        }
+      }
+    }
+  }
+  // fixed-order reduction over the 4 waves
+  __syncthreads();
+  if (wid > 0)
+    for (int q = 0; q < VW; ++q)
+      for (int k = 0; k < 3; ++k) s_red[wid - 1][k][lane * VW + q] = acc[q][k];
+  __syncthreads();
+  if (wid == 0) {
+    const T hh = (T)(B.h * B.h);
+    for (int q = 0; q < VW; ++q) {
+      const int col = col0 + q;
+      if (col >= n) continue;
+      for (int k = 0; k < 3; ++k) {
+        T s = acc[q][k];
+        for (int w = 0; w < kBlock / 64 - 1; ++w) s += s_red[w][k][lane * VW + q];
+        const size_t o = (size_t)k * B.NV + v0 + col;
+        if (ROWS) B.u[o] = B.z[o] + hh * s;
+        else B.z[o] = s;
+      }
+    }
+  }
+}
+
+// Gbar restricted to the contacts of each env: Gc[j][k] = Gbar[v_j][v_k].
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
+  const int e = blockIdx.x;
+  const int c = B.ccount[e];
+  const T* G = B.G + B.goff[e];
+  const int ld = B.gld[e];
+  T* Gc = B.Gc + (size_t)e * B.cap * B.cap;
+  const int* cv = B.cvert + (size_t)e * B.cap;
+  for (int idx = threadIdx.x; idx < c * c; idx += kBlock) {
+    const int j = idx / c, k = idx - j * c;
+    Gc[idx] = G[(size_t)cv[j] * ld + cv[k]];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Contact subproblem (Eq. 2b with Eq. 4 at fixed projections): find lambda
+// with Phi(lambda) = 0 for Y(lambda) = y_free + W lambda,
+// W = h^2 F^T (Gc (x) I3) F the exact Delassus operator of the env.
+// Semismooth Newton on Phi with the Delassus diagonal as proximal scale; the
+// Newton system Z = K W + E is solved exactly by the Woodbury identity around
+// the explicit inverse of W on the coupled contacts (rows of Z that are not
+// plain W rows form the capacitance system, LU with partial pivoting).
+// The stopping test uses the residual scale s = h^2 / m_v in FP64.
+// ---------------------------------------------------------------------------
+template <class T>
+struct CspSmem {
+  T *lam, *Y, *yf, *dl, *Wd, *rv, *x0, *fw;   // [3*cap]
+  T *sp, *kap, *yh0, *yh1, *colk, *rowk;      // [cap]
+  int *cls, *pos, *bas;                       // [cap]
+};
+
+template <class T>
+__host__ __device__ size_t csp_smem_bytes(int cap) {
+  return (size_t)cap * (24 + 6) * sizeof(T) + (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
+}
+
+// class bits: 1 normal active, 2 tangential stick, 4 tangential slip (neither: rho = 0)
+template <class T>
+__device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y1, T K[3][3], T E[3][3]) {
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) { K[a][b] = 0; E[a][b] = 0; }
+  if (cls & 1) K[0][0] = 1; else E[0][0] = sp;
+  if (cls & 2) { K[1][1] = 1; K[2][2] = 1; }
+  else if (cls & 4) {
+    T P00 = 1 - y0 * y0, P01 = -y0 * y1, P11 = 1 - y1 * y1;
+    K[1][1] = kap * P00; K[1][2] = kap * P01; K[2][1] = kap * P01; K[2][2] = kap * P11;
+    E[1][1] = sp * (1 - kap * P00); E[1][2] = -sp * kap * P01;
+    E[2][1] = -sp * kap * P01; E[2][2] = sp * (1 - kap * P11);
+    E[1][0] = -sp * mu * y0; E[2][0] = -sp * mu * y1;
+  } else {
+    E[1][1] = sp; E[2][2] = sp;
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int e = blockIdx.x;
+  const int c = B.ccount[e];
+  if (c == 0) return;
+  const int cap = B.cap;
+  CspSmem<T> S;
+  {
+    T* p = reinterpret_cast<T*>(smem_raw);
+    S.lam = p; p += 3 * cap; S.Y = p; p += 3 * cap; S.yf = p; p += 3 * cap; S.dl = p; p += 3 * cap;
+    S.Wd = p; p += 3 * cap; S.rv = p; p += 3 * cap; S.x0 = p; p += 3 * cap; S.fw = p; p += 3 * cap;
+    S.sp = p; p += cap; S.kap = p; p += cap; S.yh0 = p; p += cap; S.yh1 = p; p += cap;
+    S.colk = p; p += cap; S.rowk = p; p += cap;
+    int* ip = reinterpret_cast<int*>(p);
+    S.cls = ip; ip += cap; S.pos = ip; ip += cap; S.bas = ip; ip += cap;
+  }
+  __shared__ double sh_red[kBlock / 64];
+  __shared__ int sh_i[kBlock / 64];
+  __shared__ int sh_nb, sh_nR, sh_piv;
+  __shared__ T sh_pivv;
+
+  const size_t cb = (size_t)e * cap;
+  const T* Gc = B.Gc + cb * cap;           // ld c
+  T* Ginv = B.Ginv + cb * cap;             // ld nb
+  T* Cm = B.Cm + (size_t)e * B.rmax * B.rmax;
+  const int v0 = B.voff[e];
+  const T hh = (T)(B.h * B.h), ihh = T(1) / hh;
+  const T mu = mu_env[e];
+  const T maxf = (T)B.max_force;
+  const T* Fr = B.cframe + 9 * cb;
+  const int tid = threadIdx.x;
+
+  // per-R-row data in global scratch (after the rmax*rmax matrix)
+  T* Rv = B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 8;  // vR(3) uR(3) rhs y
+  int* Rj = reinterpret_cast<int*>(B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 8) +
+            (size_t)e * B.rmax;
+
+  // ---- load state ----
+  if (tid == 0) sh_nb = B.nbase[e];
+  __syncthreads();
+  int nb = sh_nb;
+  for (int j = tid; j < c; j += kBlock) {
+    S.pos[j] = -1;
+    const T* F = Fr + 9 * j;
+    const int vi = v0 + B.cvert[cb + j];
+    T zw0 = B.z[vi], zw1 = B.z[B.NV + vi], zw2 = B.z[2 * B.NV + vi];
+    for (int a = 0; a < 3; ++a) {
+      S.yf[3 * j + a] = F[3 * a] * zw0 + F[3 * a + 1] * zw1 + F[3 * a + 2] * zw2;
+      S.lam[3 * j + a] = B.clam[3 * (cb + j) + a];
+    }
+    S.sp[j] = hh * Gc[(size_t)j * c + j];
+  }
+  __syncthreads();
+  for (int p = tid; p < nb; p += kBlock) {
+    int j = B.base[cb + p];
+    S.bas[p] = j;
+    S.pos[j] = p;
+  }
+  __syncthreads();
+
+  // Y = y_free + W lambda (fw = F lambda world; Gc symmetric -> coalesced column reads)
+  auto apply_W = [&](const T* vin, T* vout) {
+    for (int j = tid; j < c; j += kBlock) {
+      const T* F = Fr + 9 * j;
+      const T l0 = vin[3 * j], l1 = vin[3 * j + 1], l2 = vin[3 * j + 2];
+      for (int k = 0; k < 3; ++k) S.fw[3 * j + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
+    }
+    __syncthreads();
+    for (int j = tid; j < c; j += kBlock) {
+      T d0 = 0, d1 = 0, d2 = 0;
+      for (int k = 0; k < c; ++k) {
+        const T g = Gc[(size_t)k * c + j];
+        d0 += g * S.fw[3 * k]; d1 += g * S.fw[3 * k + 1]; d2 += g * S.fw[3 * k + 2];
+      }
+      const T* F = Fr + 9 * j;
+      for (int a = 0; a < 3; ++a) vout[3 * j + a] = hh * (F[3 * a] * d0 + F[3 * a + 1] * d1 + F[3 * a + 2] * d2);
+    }
+    __syncthreads();
+  };
+
+  apply_W(S.lam, S.Y);
+  for (int j = tid; j < c; j += kBlock)
+    for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+  __syncthreads();
+  if (first_lg) {
+    // contacts without a warm start: Jacobi estimate of lambda_n
+    int any = 0;
+    for (int j = tid; j < c; j += kBlock) {
+      if (B.cnew[cb + j]) {
+        const T cn = B.cd0[cb + j] + S.Y[3 * j];
+        S.lam[3 * j] = cn < T(0) ? -cn / S.sp[j] : T(0);
+        S.lam[3 * j + 1] = 0;
+        S.lam[3 * j + 2] = 0;
+        any = 1;
+      }
+    }
+    if (block_max((double)any, sh_red) > 0) {
+      apply_W(S.lam, S.Y);
+      for (int j = tid; j < c; j += kBlock)
+        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+      __syncthreads();
+    }
+  }
+
+  int it = 0, nref = 0;
+  const int maxit = B.max_newton;
+  double r = 0.0;
+  for (;; ++it) {
+    // ---- Phi (inner scale), classification, residual (residual scale, FP64) ----
+    double rloc = 0.0, psil = 0.0;
+    for (int j = tid; j < c; j += kBlock) {
+      const T sp = S.sp[j];
+      const T l0 = S.lam[3 * j], l1 = S.lam[3 * j + 1], l2 = S.lam[3 * j + 2];
+      const T cn = B.cd0[cb + j] + S.Y[3 * j];
+      const T ut1 = S.Y[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = S.Y[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+      const T phn = fmin(cn, sp * l0);
+      const T y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+      const T rho = mu * fmax(l0, T(0));
+      const T ny = sqrt(y1 * y1 + y2 * y2);
+      int cls = (cn <= sp * l0) ? 1 : 0;
+      T p1 = y1, p2 = y2, kap = 0, yh0 = 0, yh1 = 0;
+      if (rho > T(0)) {
+        if (ny <= rho) cls |= 2;
+        else {
+          cls |= 4;
+          kap = rho / ny; yh0 = y1 / ny; yh1 = y2 / ny;
+          p1 = rho * yh0; p2 = rho * yh1;
+        }
+      } else { p1 = 0; p2 = 0; }
+      const T ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+      S.rv[3 * j] = phn; S.rv[3 * j + 1] = ph1; S.rv[3 * j + 2] = ph2;
+      S.cls[j] = cls; S.kap[j] = kap; S.yh0[j] = yh0; S.yh1[j] = yh1;
+      psil += (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
+      // residual scale
+      const double s = (double)B.cs[cb + j];
+      const double pn = fmin((double)cn, s * (double)l0);
+      const double z1 = (double)l1 - (double)ut1 / s, z2 = (double)l2 - (double)ut2 / s;
+      const double nz = sqrt(z1 * z1 + z2 * z2);
+      const double rh = (double)mu * fmax((double)l0, 0.0);
+      double q1 = z1, q2 = z2;
+      if (nz > rh) { double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
+      const double t1 = s * ((double)l1 - q1), t2 = s * ((double)l2 - q2);
+      double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
+      if (!(rj == rj)) rj = INFINITY;
+      rloc = fmax(rloc, rj);
+    }
+    r = block_max(rloc, sh_red);
+    const double psi = 0.5 * block_sum(psil, sh_red);
+    if (r <= B.tol || it >= maxit) break;
+
+    // ---- base set: refactor when a coupled contact lies outside it ----
+    int need = 0;
+    for (int j = tid; j < c; j += kBlock)
+      if ((S.cls[j] & 7) && S.pos[j] < 0) need = 1;
+    if (block_max((double)need, sh_red) > 0) {
+      // base = coupled contacts in index order
+      for (int j0 = 0; j0 < c; j0 += kBlock) {
+        const int j = j0 + tid;
+        const int f = (j < c && (S.cls[j] & 7)) ? 1 : 0;
+        int tot;
+        const int off = block_excl_scan_i(f, sh_i, &tot);
+        const int basep = j0 == 0 ? 0 : sh_nb;
+        __syncthreads();
+        if (j < c) S.pos[j] = f ? basep + off : -1;
+        if (f) S.bas[basep + off] = j;
+        __syncthreads();
+        if (tid == 0) sh_nb = basep + tot;
+        __syncthreads();
+      }
+      nb = sh_nb;
+      // Ginv = inverse of Gc[base, base] (+1e-4 relative on repeated vertices), Gauss-Jordan
+      for (int idx = tid; idx < nb * nb; idx += kBlock) {
+        const int p = idx / nb, q = idx - p * nb;
+        const int jp = S.bas[p], jq = S.bas[q];
+        T g = Gc[(size_t)jp * c + jq];
+        if (p == q && p > 0 && B.cvert[cb + jp] == B.cvert[cb + S.bas[p - 1]]) g *= T(1.0001);
+        Ginv[idx] = g;
+      }
+      for (int k = 0; k < nb; ++k) {
+        __syncthreads();
+        const T piv = Ginv[(size_t)k * nb + k];
+        for (int i = tid; i < nb; i += kBlock) {
+          S.colk[i] = Ginv[(size_t)i * nb + k];
+          S.rowk[i] = Ginv[(size_t)k * nb + i] / piv;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < nb * nb; idx += kBlock) {
+          const int i = idx / nb, jj = idx - i * nb;
+          T v;
+          if (i == k) v = (jj == k) ? T(1) / piv : S.rowk[jj];
+          else v = (jj == k) ? -S.colk[i] / piv : Ginv[idx] - S.colk[i] * S.rowk[jj];
+          Ginv[idx] = v;
+        }
+      }
+      __syncthreads();
+      ++nref;
+    }
+
+    // ---- decoupled contacts (outside the base): local rows E = sp I ----
+    for (int j = tid; j < c; j += kBlock) {
+      if (S.pos[j] < 0) {
+        const T isp = T(1) / S.sp[j];
+        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = -S.rv[3 * j + a] * isp;
+      } else {
+        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = 0;
+      }
+    }
+    __syncthreads();
+    apply_W(S.dl, S.Wd);   // W * (decoupled part)
+    // rhs on base rows: r = -Phi - K (W dl_D)
+    for (int j = tid; j < c; j += kBlock) {
+      if (S.pos[j] < 0) continue;
+      T K[3][3], E[3][3];
+      contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
+      T w0 = S.Wd[3 * j], w1 = S.Wd[3 * j + 1], w2 = S.Wd[3 * j + 2];
+      for (int a = 0; a < 3; ++a)
+        S.rv[3 * j + a] = -S.rv[3 * j + a] - (K[a][0] * w0 + K[a][1] * w1 + K[a][2] * w2);
+    }
+    __syncthreads();
+    // x0 = W_base^-1 r : g = F r (world), w = Ginv g, x0 = h^-2 F^T w
+    for (int p = tid; p < nb; p += kBlock) {
+      const int j = S.bas[p];
+      const T* F = Fr + 9 * j;
+      const T r0 = S.rv[3 * j], r1 = S.rv[3 * j + 1], r2 = S.rv[3 * j + 2];
+      for (int k = 0; k < 3; ++k) S.fw[3 * p + k] = F[k] * r0 + F[3 + k] * r1 + F[6 + k] * r2;
+    }
+    __syncthreads();
+    for (int p = tid; p < nb; p += kBlock) {
+      T w0 = 0, w1 = 0, w2 = 0;
+      for (int q = 0; q < nb; ++q) {
+        const T g = Ginv[(size_t)q * nb + p];
+        w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
+      }
+      const int j = S.bas[p];
+      const T* F = Fr + 9 * j;
+      for (int a = 0; a < 3; ++a) S.x0[3 * j + a] = ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+    }
+    __syncthreads();
+
+    // ---- capacitance rows R: base rows whose (K, E) differ from (I, 0) ----
+    if (tid == 0) sh_nR = 0;
+    __syncthreads();
+    {
+      for (int p0 = 0; p0 < nb; p0 += kBlock) {
+        const int p = p0 + tid;
+        int cnt = 0, cl = 0;
+        if (p < nb) {
+          cl = S.cls[S.bas[p]];
+          cnt = ((cl & 1) ? 0 : 1) + ((cl & 2) ? 0 : 2);
+        }
+        int tot;
+        const int off = block_excl_scan_i(cnt, sh_i, &tot);
+        const int base_r = p0 == 0 ? 0 : sh_nR;
+        __syncthreads();
+        if (p < nb) {
+          int o = base_r + off;
+          const int j = S.bas[p];
+          for (int a = 0; a < 3; ++a) {
+            const bool mod = a == 0 ? !(cl & 1) : !(cl & 2);
+            if (!mod) continue;
+            if (o < B.rmax) Rj[o] = 3 * j + a;
+            ++o;
+          }
+        }
+        __syncthreads();
+        if (tid == 0) sh_nR = base_r + tot;
+        __syncthreads();
+      }
+    }
+    const int nR = min(sh_nR, B.rmax);
+    if (nR > 0) {
+      // per-row vectors: vR = F E^T[:, a] (world), uR = F[:, a]; rhs
+      for (int q = tid; q < nR; q += kBlock) {
+        const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
+        T K[3][3], E[3][3];
+        contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
+        const T* F = Fr + 9 * j;
+        T* rv = Rv + 8 * q;
+        for (int k = 0; k < 3; ++k) {
+          rv[k] = E[a][0] * F[k] + E[a][1] * F[3 + k] + E[a][2] * F[6 + k];
+          rv[3 + k] = F[3 * a + k];
+        }
+        T rr = -S.rv[3 * j + a];
+        for (int b = 0; b < 3; ++b) rr += K[a][b] * S.rv[3 * j + b] + E[a][b] * S.x0[3 * j + b];
+        rv[6] = rr;
+      }
+      __syncthreads();
+      // C[q][s] = [same contact] K[a][b] + h^-2 Ginv[pj][pk] (vR_q . uR_s)
+      for (int idx = tid; idx < nR * nR; idx += kBlock) {
+        const int q = idx / nR, s = idx - q * nR;
+        const int jaq = Rj[q], jas = Rj[s];
+        const int jq = jaq / 3, aq = jaq - 3 * jq, js = jas / 3, as = jas - 3 * js;
+        const T* vq = Rv + 8 * q;
+        const T* us = Rv + 8 * s + 3;
+        T v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
+        if (jq == js) {
+          T K[3][3], E[3][3];
+          contact_KE(S.cls[jq], S.sp[jq], mu, S.kap[jq], S.yh0[jq], S.yh1[jq], K, E);
+          v += K[aq][as];
+        }
+        Cm[idx] = v;
+      }
+      // LU with partial pivoting; rhs in Rv[8q+6]
+      for (int k = 0; k < nR; ++k) {
+        __syncthreads();
+        // pivot search
+        double best = -1.0;
+        int bi = k;
+        for (int i = k + tid; i < nR; i += kBlock) {
+          const double a = fabs((double)Cm[(size_t)i * nR + k]);
+          if (a > best) { best = a; bi = i; }
+        }
+        // block argmax (ties -> lowest row)
+        for (int d = 32; d > 0; d >>= 1) {
+          double ob = __shfl_xor(best, d, 64);
+          int oi = __shfl_xor(bi, d, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        __syncthreads();
+        if (lane_id() == 0) { sh_red[wave_id()] = best; sh_i[wave_id()] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+          double bb = sh_red[0];
+          int ii = sh_i[0];
+          for (int w = 1; w < kBlock / 64; ++w)
+            if (sh_red[w] > bb || (sh_red[w] == bb && sh_i[w] < ii)) { bb = sh_red[w]; ii = sh_i[w]; }
+          sh_piv = ii;
+        }
+        __syncthreads();
+        const int pr = sh_piv;
+        if (pr != k) {
+          for (int jj = tid; jj < nR; jj += kBlock) {
+            T t0 = Cm[(size_t)k * nR + jj];
+            Cm[(size_t)k * nR + jj] = Cm[(size_t)pr * nR + jj];
+            Cm[(size_t)pr * nR + jj] = t0;
+          }
+          if (tid == 0) { T t0 = Rv[8 * k + 6]; Rv[8 * k + 6] = Rv[8 * pr + 6]; Rv[8 * pr + 6] = t0; }
+        }
+        __syncthreads();
+        if (tid == 0) sh_pivv = Cm[(size_t)k * nR + k];
+        __syncthreads();
+        const T pv = sh_pivv;
+        for (int i = k + 1 + tid; i < nR; i += kBlock) {
+          const T l = pv != T(0) ? Cm[(size_t)i * nR + k] / pv : T(0);
+          Cm[(size_t)i * nR + k] = l;
+        }
+        __syncthreads();
+        for (int idx = tid; idx < (nR - k - 1) * (nR - k); idx += kBlock) {
+          const int i = k + 1 + idx / (nR - k), jj = k + idx % (nR - k);
+          const T l = Cm[(size_t)i * nR + k];
+          if (jj == k) continue;
+          Cm[(size_t)i * nR + jj] -= l * Cm[(size_t)k * nR + jj];
+        }
+        __syncthreads();
+        for (int i = k + 1 + tid; i < nR; i += kBlock) Rv[8 * i + 6] -= Cm[(size_t)i * nR + k] * Rv[8 * k + 6];
+      }
+      // back substitution -> y in Rv[8q+7]
+      for (int k = nR - 1; k >= 0; --k) {
+        __syncthreads();
+        if (tid == 0) {
+          const T d = Cm[(size_t)k * nR + k];
+          Rv[8 * k + 7] = d != T(0) ? Rv[8 * k + 6] / d : T(0);
+        }
+        __syncthreads();
+        const T yk = Rv[8 * k + 7];
+        for (int i = tid; i < k; i += kBlock) Rv[8 * i + 6] -= Cm[(size_t)i * nR + k] * yk;
+      }
+      __syncthreads();
+      // dl_base = x0 - h^-2 F^T sum_s Ginv[ps][p] (uR_s y_s)
+      for (int p = tid; p < nb; p += kBlock) {
+        T w0 = 0, w1 = 0, w2 = 0;
+        for (int s = 0; s < nR; ++s) {
+          const int js = Rj[s] / 3;
+          const T g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[8 * s + 7];
+          const T* us = Rv + 8 * s + 3;
+          w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
+        }
+        const int j = S.bas[p];
+        const T* F = Fr + 9 * j;
+        for (int a = 0; a < 3; ++a)
+          S.dl[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+      }
+    } else {
+      for (int p = tid; p < nb; p += kBlock) {
+        const int j = S.bas[p];
+        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = S.x0[3 * j + a];
+      }
+    }
+    __syncthreads();
+    // undo the decoupled part's effect: Wd currently = W dl_D; recompute W dl (all)
+    apply_W(S.dl, S.Wd);
+
+    // ---- backtracking line search on 1/2 |Phi|^2 (inner scale) ----
+    T alpha = 1;
+    bool ok = false;
+    for (int ls = 0; ls < 30; ++ls) {
+      double pl = 0.0;
+      for (int j = tid; j < c; j += kBlock) {
+        const T sp = S.sp[j];
+        const T l0 = fmin(fmax(S.lam[3 * j] + alpha * S.dl[3 * j], -maxf), maxf);
+        const T l1 = fmin(fmax(S.lam[3 * j + 1] + alpha * S.dl[3 * j + 1], -maxf), maxf);
+        const T l2 = fmin(fmax(S.lam[3 * j + 2] + alpha * S.dl[3 * j + 2], -maxf), maxf);
+        const T cn = B.cd0[cb + j] + S.Y[3 * j] + alpha * S.Wd[3 * j];
+        const T ut1 = S.Y[3 * j + 1] + alpha * S.Wd[3 * j + 1] - B.cdob[2 * (cb + j)];
+        const T ut2 = S.Y[3 * j + 2] + alpha * S.Wd[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+        const T phn = fmin(cn, sp * l0);
+        const T y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+        const T rho = mu * fmax(l0, T(0));
+        const T ny = sqrt(y1 * y1 + y2 * y2);
+        T p1 = 0, p2 = 0;
+        if (rho > T(0)) {
+          if (ny <= rho) { p1 = y1; p2 = y2; }
+          else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
+        }
+        const T ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+        pl += (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
+      }
+      const double psit = 0.5 * block_sum(pl, sh_red);
+      if (psit <= (1.0 - 2e-4 * (double)alpha) * psi) { ok = true; break; }
+      alpha *= T(0.5);
+    }
+    if (!ok) alpha = alpha * T(2);   // smallest tried step: keep moving
+    for (int j = tid; j < c; j += kBlock)
+      for (int a = 0; a < 3; ++a) {
+        S.lam[3 * j + a] = fmin(fmax(S.lam[3 * j + a] + alpha * S.dl[3 * j + a], -maxf), maxf);
+        S.Y[3 * j + a] += alpha * S.Wd[3 * j + a];
+      }
+    __syncthreads();
+    if ((it & 7) == 7) {   // refresh Y from lambda to stop drift
+      apply_W(S.lam, S.Y);
+      for (int j = tid; j < c; j += kBlock)
+        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+      __syncthreads();
+    }
+  }
+  // ---- write back ----
+  for (int j = tid; j < c; j += kBlock) {
+    const T* F = Fr + 9 * j;
+    const T l0 = S.lam[3 * j], l1 = S.lam[3 * j + 1], l2 = S.lam[3 * j + 2];
+    for (int a = 0; a < 3; ++a) B.clam[3 * (cb + j) + a] = S.lam[3 * j + a];
+    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
+  }
+  for (int p = tid; p < nb; p += kBlock) B.base[cb + p] = S.bas[p];
+  if (tid == 0) {
+    B.nbase[e] = nb;
+    B.iters[e] += it;
+    B.refac[e] += nref;
+    if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
+  }
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+void launch_gather(const DevBatch<T>& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather<T>, dim3(B.n_envs), dim3(kBlock), 0, s, B);
+}
+template <class T>
+void launch_project(const DevBatch<T>& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_project<T>, dim3((B.NT + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B);
+}
+template <class T>
+void launch_assemble(const DevBatch<T>& B, hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble<T>, dim3((B.NV + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B);
+}
+template <class T>
+void launch_apply(const DevBatch<T>& B, int max_ld, hipStream_t s) {
+  constexpr int TILE = 64 * (16 / sizeof(T));
+  hipLaunchKernelGGL((k_gemv<T, false>), dim3((max_ld + TILE - 1) / TILE, B.n_envs), dim3(kBlock), 0, s, B);
+}
+template <class T>
+void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s) {
+  constexpr int TILE = 64 * (16 / sizeof(T));
+  hipLaunchKernelGGL((k_gemv<T, true>), dim3((max_ld + TILE - 1) / TILE, B.n_envs), dim3(kBlock), 0, s, B);
+}
+template <class T>
+void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
+  size_t sm = csp_smem_bytes<T>(B.cap);
+  hipLaunchKernelGGL(k_csp<T>, dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+}
+
+template <class T>
+void prepare_csp(int cap) {
+  size_t sm = csp_smem_bytes<T>(cap);
+  hipError_t err = hipFuncSetAttribute((const void*)k_csp<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  (void)err;
+}
+
+#define INST(T)                                                          \
+  template void prepare_csp<T>(int);                                     \
+  template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
+  template void launch_project<T>(const DevBatch<T>&, hipStream_t);      \
+  template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \
+  template void launch_apply<T>(const DevBatch<T>&, int, hipStream_t);   \
+  template void launch_correct<T>(const DevBatch<T>&, int, hipStream_t); \
+  template void launch_csp<T>(const DevBatch<T>&, const T*, int, hipStream_t);
+INST(float)
+INST(double)
+
+}  // namespace flash

@@ -1,0 +1,310 @@
+"""ctypes binding of the C ABI in include/flash.h (argument marshalling only).
+
+Every step of the simulation runs inside the HIP library; this module only
+converts numpy arrays to the C structures and back.  The library must be
+built (paper_2604_17513_amd/build.py); importing the binding without it
+raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import scenes
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libflash_mi355x.so")
+
+FLASH_OK = 0
+FLASH_ERR_INVALID_ARG = 1
+FLASH_ERR_OUT_OF_MEMORY = 2
+FLASH_ERR_DEVICE = 3
+FLASH_ERR_CAPACITY = 4
+FLASH_ERR_NOT_CONVERGED = 5
+FLASH_ERR_NONFINITE = 6
+FLASH_ERR_UNSUPPORTED = 7
+FLASH_FP32, FLASH_FP64 = 0, 1
+FLASH_WS_ZERO, FLASH_WS_PREV, FLASH_WS_LEARNED = 0, 1, 2
+MAX_OBSTACLES = 4
+
+EXPORTED = [
+    "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
+    "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
+    "flash_contacts", "flash_residual", "flash_stats", "flash_set_kernel_timing",
+    "flash_kernel_times", "flash_kernel_name", "flash_ws_load", "flash_last_error", "flash_version",
+]
+
+
+class flash_env_desc(C.Structure):
+    _fields_ = [("elem", C.c_int32), ("n_vertices", C.c_int32), ("n_elements", C.c_int32),
+                ("reserved", C.c_int32), ("rest_x", C.POINTER(C.c_double)),
+                ("elements", C.POINTER(C.c_int32)), ("density", C.c_double), ("thickness", C.c_double),
+                ("young", C.c_double), ("poisson", C.c_double), ("bending", C.c_double), ("mu", C.c_double)]
+
+
+class flash_obstacle(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("move_steps", C.c_int32), ("center", C.c_double * 3),
+                ("rot", C.c_double * 9), ("size", C.c_double * 3), ("lin_vel", C.c_double * 3)]
+
+
+class flash_params(C.Structure):
+    _fields_ = [("h", C.c_double), ("gravity", C.c_double * 3), ("lg_iterations", C.c_int32),
+                ("max_inner_iterations", C.c_int32), ("ncp_tol", C.c_double), ("contact_margin", C.c_double),
+                ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
+                ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double)]
+
+
+class flash_contact(C.Structure):
+    _fields_ = [("env", C.c_int32), ("vertex", C.c_int32), ("obstacle", C.c_int32), ("mode", C.c_int32),
+                ("normal", C.c_double * 3), ("tangent1", C.c_double * 3), ("gap", C.c_double),
+                ("impulse", C.c_double * 3), ("lambda_", C.c_double * 3)]
+
+
+class flash_env_stats(C.Structure):
+    _fields_ = [("inner_iterations", C.c_int32), ("refactorizations", C.c_int32), ("contacts", C.c_int32),
+                ("fp64_polar", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32),
+                ("residual", C.c_double)]
+
+
+class FlashError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"flash status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with paper_2604_17513_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, I32, D = C.c_void_p, C.c_int32, C.POINTER(C.c_double)
+        L.flash_create_batch.argtypes = [C.POINTER(flash_env_desc), I32, C.POINTER(flash_params), P, C.POINTER(P)]
+        L.flash_destroy_batch.argtypes = [P]
+        L.flash_set_state.argtypes = [P, I32, D, D]
+        L.flash_get_state.argtypes = [P, I32, D, D]
+        L.flash_set_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32]
+        L.flash_get_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32, C.POINTER(I32)]
+        L.flash_step.argtypes = [P, I32]
+        L.flash_synchronize.argtypes = [P]
+        L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
+        L.flash_residual.argtypes = [P, D, D, C.POINTER(I32)]
+        L.flash_stats.argtypes = [P, C.POINTER(flash_env_stats)]
+        L.flash_set_kernel_timing.argtypes = [P, I32]
+        L.flash_kernel_times.argtypes = [P, D, C.POINTER(C.c_int64), I32, C.POINTER(I32)]
+        L.flash_kernel_name.argtypes = [I32]
+        L.flash_kernel_name.restype = C.c_char_p
+        L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, C.POINTER(C.c_float)]
+        L.flash_last_error.restype = C.c_char_p
+        L.flash_version.restype = C.c_char_p
+        for name in EXPORTED:
+            fn = getattr(L, name)
+            if name not in ("flash_kernel_name", "flash_last_error", "flash_version"):
+                fn.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int, allow=()):
+    if st != FLASH_OK and st not in allow:
+        raise FlashError(st, lib().flash_last_error().decode())
+    return st
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
+                  use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0) -> flash_params:
+    s = flash_params()
+    s.h = p.h
+    for k in range(3):
+        s.gravity[k] = p.gravity[k]
+    s.lg_iterations = p.lg_iterations
+    s.max_inner_iterations = p.max_inner_iterations
+    s.ncp_tol = p.ncp_tol
+    s.contact_margin = p.contact_margin
+    s.max_force = p.max_force
+    s.precision = precision
+    s.warm_start = warm_start
+    s.use_graph = 1 if use_graph else 0
+    s.max_contacts_per_env = max_contacts
+    s.inner_tol = inner_tol
+    return s
+
+
+def obstacle_struct(o: scenes.Obstacle) -> flash_obstacle:
+    s = flash_obstacle()
+    s.kind = o.kind
+    s.move_steps = o.move_steps
+    for k in range(3):
+        s.center[k] = o.center[k]
+        s.size[k] = o.size[k]
+        s.lin_vel[k] = o.lin_vel[k]
+    R = np.asarray(o.rot, dtype=np.float64).reshape(3, 3)
+    for k in range(9):
+        s.rot[k] = R.reshape(-1)[k]
+    return s
+
+
+class Batch:
+    """A batch of environments living on the GPU (wraps flash_create_batch)."""
+
+    def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
+                 warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
+                 stream: Optional[int] = None, inner_tol: float = 0.0):
+        L = lib()
+        self.n_envs = len(envs)
+        self.params = params
+        self.nv = [e.n_vertices for e in envs]
+        self._keep = []
+        descs = (flash_env_desc * self.n_envs)()
+        for i, e in enumerate(envs):
+            rest = np.ascontiguousarray(e.rest_x, dtype=np.float64)
+            el = np.ascontiguousarray(e.elements, dtype=np.int32)
+            self._keep += [rest, el]
+            d = descs[i]
+            d.elem = e.elem
+            d.n_vertices = e.n_vertices
+            d.n_elements = e.n_elements
+            d.rest_x = _dptr(rest)
+            d.elements = el.ctypes.data_as(C.POINTER(C.c_int32))
+            d.density, d.thickness, d.young = e.density, e.thickness, e.young
+            d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
+        self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol)
+        h = C.c_void_p()
+        _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self._keep = []
+
+    # -- lifecycle -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().flash_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- state -----------------------------------------------------------------------
+    def set_state(self, x, v=None, env: int = -1):
+        xa = np.ascontiguousarray(np.concatenate(x) if isinstance(x, (list, tuple)) else x, dtype=np.float64)
+        va = None
+        if v is not None:
+            va = np.ascontiguousarray(np.concatenate(v) if isinstance(v, (list, tuple)) else v, dtype=np.float64)
+        _check(lib().flash_set_state(self._h, env, _dptr(xa), _dptr(va) if va is not None else None))
+
+    def get_state(self, env: int = -1):
+        n = sum(self.nv) if env < 0 else self.nv[env]
+        x = np.empty((n, 3))
+        v = np.empty((n, 3))
+        _check(lib().flash_get_state(self._h, env, _dptr(x), _dptr(v)))
+        return x, v
+
+    def split(self, a: np.ndarray) -> List[np.ndarray]:
+        return np.split(a, np.cumsum(self.nv)[:-1])
+
+    def set_obstacles(self, obstacles, env: int = -1):
+        if env < 0:
+            n = len(obstacles[0])
+            arr = (flash_obstacle * (self.n_envs * n))()
+            for e, lst in enumerate(obstacles):
+                assert len(lst) == n
+                for q, o in enumerate(lst):
+                    arr[e * n + q] = obstacle_struct(o)
+        else:
+            n = len(obstacles)
+            arr = (flash_obstacle * max(n, 1))()
+            for q, o in enumerate(obstacles):
+                arr[q] = obstacle_struct(o)
+        _check(lib().flash_set_obstacles(self._h, env, arr, n))
+
+    def get_obstacles(self, env: int):
+        arr = (flash_obstacle * MAX_OBSTACLES)()
+        n = C.c_int32()
+        _check(lib().flash_get_obstacles(self._h, env, arr, MAX_OBSTACLES, C.byref(n)))
+        out = []
+        for q in range(n.value):
+            s = arr[q]
+            out.append(scenes.Obstacle(s.kind, np.array(s.center[:]), np.array(s.rot[:]).reshape(3, 3),
+                                       np.array(s.size[:]), np.array(s.lin_vel[:]), s.move_steps))
+        return out
+
+    # -- stepping --------------------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(lib().flash_step(self._h, n))
+
+    def synchronize(self):
+        _check(lib().flash_synchronize(self._h))
+
+    # -- queries -----------------------------------------------------------------------
+    def contacts(self, env: int = -1):
+        n = C.c_int32()
+        _check(lib().flash_contacts(self._h, env, None, 0, C.byref(n)), allow=(FLASH_ERR_CAPACITY,))
+        cap = max(n.value, 1)
+        arr = (flash_contact * cap)()
+        _check(lib().flash_contacts(self._h, env, arr, cap, C.byref(n)))
+        k = n.value
+        out = {
+            "env": np.array([arr[i].env for i in range(k)], dtype=np.int64),
+            "vertex": np.array([arr[i].vertex for i in range(k)], dtype=np.int64),
+            "obstacle": np.array([arr[i].obstacle for i in range(k)], dtype=np.int64),
+            "mode": np.array([arr[i].mode for i in range(k)], dtype=np.int64),
+            "normal": np.array([arr[i].normal[:] for i in range(k)]).reshape(k, 3),
+            "tangent1": np.array([arr[i].tangent1[:] for i in range(k)]).reshape(k, 3),
+            "gap": np.array([arr[i].gap for i in range(k)]),
+            "impulse": np.array([arr[i].impulse[:] for i in range(k)]).reshape(k, 3),
+            "lambda": np.array([arr[i].lambda_[:] for i in range(k)]).reshape(k, 3),
+        }
+        return out
+
+    def residual(self):
+        per = np.empty(self.n_envs)
+        mx = C.c_double()
+        its = np.empty(self.n_envs, dtype=np.int32)
+        st = lib().flash_residual(self._h, _dptr(per), C.byref(mx), its.ctypes.data_as(C.POINTER(C.c_int32)))
+        _check(st, allow=(FLASH_ERR_NOT_CONVERGED, FLASH_ERR_NONFINITE))
+        return per, mx.value, its, st
+
+    def stats(self):
+        arr = (flash_env_stats * self.n_envs)()
+        _check(lib().flash_stats(self._h, arr))
+        return [dict(inner_iterations=s.inner_iterations, refactorizations=s.refactorizations,
+                     contacts=s.contacts, fp64_polar=s.fp64_polar, flags=s.flags, residual=s.residual)
+                for s in arr]
+
+    def set_kernel_timing(self, on: bool):
+        _check(lib().flash_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_times(self):
+        ms = np.zeros(16)
+        cnt = np.zeros(16, dtype=np.int64)
+        n = C.c_int32()
+        _check(lib().flash_kernel_times(self._h, _dptr(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)), 16,
+                                        C.byref(n)))
+        return {lib().flash_kernel_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n.value)}
+
+
+def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
+               use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0) -> Batch:
+    """Creates a batch for a scene and uploads its initial state and obstacles."""
+    b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol)
+    b.set_state(sc.x0, sc.v0)
+    n_obs = {len(o) for o in sc.obstacles}
+    if len(n_obs) == 1:
+        b.set_obstacles(sc.obstacles)
+    else:
+        for e, lst in enumerate(sc.obstacles):
+            b.set_obstacles(lst, env=e)
+    return b

@@ -1,0 +1,65 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2604_17513_amd import flash as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "flash.h")).read()
+    names = set(re.findall(r"^\s*(?:flash_status|const char\s*\*)\s*(flash_\w+)\s*\(", src, re.M))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    L = F.lib()
+    declared = _declared()
+    assert {"flash_create_batch", "flash_set_state", "flash_step", "flash_contacts", "flash_residual"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert declared <= set(F.EXPORTED)
+
+
+def test_version_and_kernel_names():
+    L = F.lib()
+    assert b"gfx950" in L.flash_version()
+    names = [L.flash_kernel_name(i).decode() for i in range(9)]
+    assert names[:8] == ["detect", "gather", "project", "assemble", "apply", "csp", "correct", "finalize"]
+    assert L.flash_kernel_name(99) == b""
+
+
+def test_invalid_arguments_are_rejected_without_device():
+    L = F.lib()
+    h = C.c_void_p()
+    p = F.flash_params()
+    assert L.flash_create_batch(None, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
+    assert b"null" in L.flash_last_error()
+    d = (F.flash_env_desc * 1)()
+    assert L.flash_create_batch(d, 0, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
+    p.h = 1.0 / 60
+    p.lg_iterations = 0
+    p.ncp_tol = 1e-6
+    assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
+    p.lg_iterations = 5
+    d[0].elem = 1      # triangles are not built in this library
+    d[0].n_vertices = 3
+    d[0].n_elements = 1
+    assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_UNSUPPORTED
+    assert L.flash_step(None, 1) == F.FLASH_ERR_INVALID_ARG
+    assert L.flash_destroy_batch(None) == F.FLASH_ERR_INVALID_ARG
+    assert L.flash_residual(None, None, None, None) == F.FLASH_ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_header_field_order():
+    # the ctypes mirrors follow the header's field order; sizes are those of the C structs on LP64
+    assert C.sizeof(F.flash_obstacle) == 8 + 8 * (3 + 9 + 3 + 3)
+    assert C.sizeof(F.flash_env_desc) == 16 + 16 + 8 * 6
+    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8
+    assert C.sizeof(F.flash_contact) == 16 + 8 * (3 + 3 + 1 + 3 + 3)
+    assert C.sizeof(F.flash_env_stats) == 24 + 8

@@ -1,0 +1,164 @@
+"""GPU parity: the HIP step against the FP64 oracle from identical states.
+
+For each checked step the GPU state at the step start (FP32 or FP64, promoted
+exactly to FP64) and the GPU's own obstacle poses are handed to the oracle;
+the GPU's end-of-step positions must match within
+1e-5 * max(|q|_inf, L_env) (FP32) or 1e-9 * ... (FP64), the contact
+(vertex, obstacle) lists must be identical, and the NCP residual recomputed by
+the oracle from the GPU's positions and multipliers must be <= 1e-6 m.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import flash_oracle as O
+from paper_2604_17513_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _flash():
+    from paper_2604_17513_amd import flash as F
+    return F
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _compare_step(b, sc, oes, env_ids, rel, label=""):
+    """Runs one GPU step and the oracle step for env_ids from the GPU's start state."""
+    x0, v0 = b.get_state()
+    xs, vs = b.split(x0), b.split(v0)
+    obs = {e: b.get_obstacles(e) for e in env_ids}
+    b.step(1)
+    b.synchronize()
+    x1, v1 = b.get_state()
+    x1s, v1s = b.split(x1), b.split(v1)
+    out = []
+    for e in env_ids:
+        ref = O.step(oes[e], xs[e], vs[e], obs[e], sc.params, tol=1e-12)
+        L = np.linalg.norm(sc.envs[e].rest_x.max(0) - sc.envs[e].rest_x.min(0))
+        scale = max(np.abs(ref.x).max(), L)
+        err = np.abs(x1s[e] - ref.x).max()
+        gc = b.contacts(e)
+        pairs_gpu = list(zip(gc["vertex"].tolist(), gc["obstacle"].tolist()))
+        pairs_ref = list(zip(ref.contacts.vertex.tolist(), ref.contacts.obstacle.tolist()))
+        # oracle residual from the GPU end positions and multipliers
+        r_gpu = O.contact_residual(oes[e], xs[e], x1s[e], ref.contacts, gc["lambda"], sc.params.h) \
+            if pairs_gpu == pairs_ref else float("inf")
+        _say(f"{label} env {e}: contacts {len(pairs_gpu)} max|dq| {err:.3e} (tol {rel * scale:.3e}) "
+             f"resid(gpu pos, oracle metric) {r_gpu:.3e} oracle resid {ref.residual:.2e}")
+        out.append((err, rel * scale, pairs_gpu == pairs_ref, r_gpu, ref))
+    return out
+
+
+def test_fp64_drop_cube_matches_oracle():
+    F = _flash()
+    sc = scenes.drop_cube(seed=0)
+    oe = O.precompute(sc.envs[0], sc.params.h)
+    b = F.from_scene(sc, precision=F.FLASH_FP64, max_contacts=128)
+    checked = 0
+    for s in range(40):
+        if s in (0, 9, 10, 11, 12, 13, 15, 20, 30, 39):
+            (err, tol, same, r, ref), = _compare_step(b, sc, {0: oe}, [0], 1e-9, f"step {s}")
+            assert same
+            assert err <= tol
+            assert r <= 1e-6
+            checked += 1
+        else:
+            b.step(1)
+    per, mx, its, st = b.residual()
+    assert mx <= 1e-6
+    assert checked == 10
+
+
+def test_fp32_squeeze_blocks_match_oracle():
+    F = _flash()
+    sc = scenes.squeeze_blocks(3, seed=1, hexes=6)
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in range(3)}
+    b = F.from_scene(sc, precision=F.FLASH_FP32)
+    for s in range(24):
+        if s in (0, 3, 12, 23):
+            for err, tol, same, r, ref in _compare_step(b, sc, oes, [0, 1, 2], 1e-5, f"step {s}"):
+                assert same
+                assert err <= tol
+                assert r <= 1e-6
+        else:
+            b.step(1)
+
+
+def test_fp32_full_size_block_sampled_envs():
+    """Full-size 10x10x10-hex blocks (1331 vertices, 6000 tets) squeezed by fingers."""
+    F = _flash()
+    sc = scenes.squeeze_blocks(8, seed=2)
+    b = F.from_scene(sc, precision=F.FLASH_FP32)
+    b.step(6)
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in (0, 5)}
+    for err, tol, same, r, ref in _compare_step(b, sc, oes, [0, 5], 1e-5, "full"):
+        assert same
+        assert err <= tol
+        assert r <= 1e-6
+    per, mx, its, st = b.residual()
+    _say("residuals", per, "iters", its)
+    assert mx <= 1e-6
+
+
+def test_free_flight_no_contacts_closed_form():
+    F = _flash()
+    sc = scenes.drop_cube(jitter=0.0, drop_height=5.0)
+    sc.params.lg_iterations = 3
+    v0 = np.tile([0.3, 1.0, -0.2], (sc.envs[0].n_vertices, 1))
+    sc.v0[0] = v0
+    b = F.from_scene(sc, precision=F.FLASH_FP64)
+    b.step(5)
+    x, v = b.get_state()
+    h, g = sc.params.h, np.array(sc.params.gravity)
+    n = 5
+    assert np.allclose(x, sc.x0[0] + n * h * v0 + h * h * g * n * (n + 1) / 2, rtol=0, atol=1e-11)
+    assert np.allclose(v, v0 + n * h * g, rtol=0, atol=1e-9)
+    assert b.contacts(0)["vertex"].shape[0] == 0
+
+
+def test_determinism_graph_and_batch_invariance():
+    F = _flash()
+    sc = scenes.squeeze_blocks(4, seed=3, hexes=5)
+    a = F.from_scene(sc)
+    g = F.from_scene(sc, use_graph=True)
+    a.step(8)
+    g.step(8)
+    xa, va = a.get_state()
+    xg, vg = g.get_state()
+    assert np.array_equal(xa, xg) and np.array_equal(va, vg)
+    # env 2 alone equals env 2 inside the batch
+    one = scenes.Scene([sc.envs[2]], [sc.x0[2]], [sc.v0[2]], [sc.obstacles[2]], sc.params)
+    s1 = F.from_scene(one)
+    s1.step(8)
+    x1, v1 = s1.get_state()
+    assert np.array_equal(x1, a.split(xa)[2]) and np.array_equal(v1, a.split(va)[2])
+    # repeated run
+    r = F.from_scene(sc)
+    r.step(8)
+    xr, vr = r.get_state()
+    assert np.array_equal(xa, xr)
+
+
+def test_ragged_batch_and_capacity_flag():
+    F = _flash()
+    envs, xs, vs, obs = [], [], [], []
+    for k, hx in enumerate((2, 3, 5, 7)):
+        sc = scenes.drop_cube(seed=k, hexes=hx, drop_height=0.0005, jitter=0.0)
+        envs += sc.envs; xs += sc.x0; vs += sc.v0; obs += sc.obstacles
+    sc = scenes.Scene(envs, xs, vs, obs, scenes.Params(lg_iterations=4))
+    b = F.from_scene(sc, max_contacts=32)
+    b.step(2)
+    st = b.stats()
+    counts = [s["contacts"] for s in st]
+    _say("ragged counts", counts, [s["flags"] for s in st])
+    # bottom layers hold 9, 16, 36 and 64 vertices; the last two exceed the capacity of 32
+    assert counts == [9, 16, 32, 32]
+    assert all(s["flags"] & 4 for s in st[2:])
+    assert all((s["flags"] & 4) == 0 for s in st[:2])
