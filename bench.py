@@ -1,0 +1,228 @@
+"""Throughput benchmark: env-steps/s at NCP residual 1e-6 on one MI355X.
+
+Workload: 1024 environments, each a 10x10x10-hex block (1331 vertices, 6000
+tets, E ~ U(5e4, 5e5) Pa, nu ~ U(0.30, 0.45), mu ~ U(0.3, 0.8)) resting on the
+ground and squeezed by two kinematic box fingers closing at 2 cm/s, about 220
+contacts per env, h = 1/60 s, 20 local-global iterations per step, FP32, every
+contact solve run to the NCP tolerance.  Inputs are seeded and synthetic and
+stand in for the paper's garment and towel scenes.
+
+A step is one pass of the whole hot path over all environments (detection,
+prediction, K x (projection, assembly, global apply, contact solve, position
+update), finalisation).  The state is resident in HBM before the timed region.
+
+Prints one JSON line (rank 0).  The roofline object covers the dominant kernel
+(the explicit-inverse global apply), timed with HIP events on the batch's
+stream inside the timed region; cpu_baseline times the FP64 oracle on the
+host on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "env-steps/sec at NCP residual 1e-6: plain vs batched+learned warm-start, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+K_APPLY = 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def apply_bytes_per_launch(nv):
+    """Algorithmic bytes of one global-apply launch: the n x n inverse of every
+    env (FP32) read once, the 3 right-hand sides read and the 3 results written."""
+    nv = np.asarray(nv, dtype=np.float64)
+    return float(np.sum(4.0 * nv * nv + 2 * 12.0 * nv))
+
+
+def cpu_baseline(sc, n_steps, procs):
+    """FP64 oracle on host cores: `procs` envs in parallel processes, n_steps each."""
+    import multiprocessing as mp
+    t0 = time.time()
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        res = pool.starmap(_oracle_env, [(e, n_steps) for e in range(procs)])
+    dt = time.time() - t0
+    return procs * n_steps / dt, dt, res
+
+
+def _oracle_env(e, n_steps):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
+    from oracle import flash_oracle as O
+    from paper_2604_17513_amd import scenes
+    with threadpool_limits(limits=1):
+        sc = scenes.squeeze_blocks(e + 1, seed=0)
+        oe = O.precompute(sc.envs[e], sc.params.h)
+        x, v, obs = sc.x0[e], sc.v0[e], sc.obstacles[e]
+        t0 = time.time()
+        for _ in range(n_steps):
+            r = O.step(oe, x, v, obs, sc.params)
+            x, v, obs = r.x, r.v, r.obstacles
+        return time.time() - t0, r.residual
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--envs", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: environments are independent and this build "
+              "measures one GPU's share; see the design notes for how envs shard.", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2604_17513_amd import scenes
+
+    # the host-side oracle baseline runs first, before this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        procs = min(16, os.cpu_count() or 1)
+        sc0 = scenes.squeeze_blocks(procs, seed=0)
+        v_cpu, t_cpu, res = cpu_baseline(sc0, args.cpu_steps, procs)
+        cpu = {
+            "value": round(v_cpu, 3),
+            "unit": "env-steps/s",
+            "cores": procs,
+            "kind": "oracle",
+            "sample": f"{procs} envs x {args.cpu_steps} steps of the same workload from its initial state, "
+                      f"one FP64 oracle process per env, 1 BLAS thread each ({t_cpu:.1f}s wall)",
+        }
+        log(f"cpu baseline: {v_cpu:.3f} env-steps/s on {procs} processes")
+
+    import torch
+    from paper_2604_17513_amd import flash as F
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.set_device(0)
+
+    sc = scenes.squeeze_blocks(args.envs, seed=0)
+    nv = [e.n_vertices for e in sc.envs]
+    t0 = time.time()
+    b = F.from_scene(sc)
+    precompute_s = time.time() - t0
+    log(f"created {args.envs} envs in {precompute_s:.1f}s")
+
+    b.step(args.warmup)
+    b.synchronize()
+
+    # timed region: events around every global-apply launch (the dominant kernel)
+    b.set_kernel_timing(1 << K_APPLY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    b.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = b.kernel_times()
+    b.set_kernel_timing(0)
+    per, mx, its, st = b.residual()
+    stats = b.stats()
+    value = args.envs * args.steps / dt
+    ms_step = 1000.0 * dt / args.steps
+    apply_ms, apply_n = kt["apply"]
+    apply_avg = apply_ms / max(apply_n, 1)
+    bpl = apply_bytes_per_launch(nv)
+    achieved = bpl / (apply_avg * 1e-3) / 1e9
+    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.0f} env-steps/s; apply avg {apply_avg:.3f} ms")
+
+    # per-kernel breakdown (separate pass, every class timed)
+    b.set_kernel_timing(True)
+    b.step(2)
+    b.synchronize()
+    breakdown = {k: round(v[0] / 2, 3) for k, v in b.kernel_times().items() if v[1]}
+    b.set_kernel_timing(0)
+
+    # graph-captured variant of the same step
+    g = F.from_scene(scenes.squeeze_blocks(args.envs, seed=0), use_graph=True)
+    g.step(args.warmup)
+    g.synchronize()
+    t0 = time.perf_counter()
+    g.step(args.steps)
+    g.synchronize()
+    dt_g = time.perf_counter() - t0
+    _, mx_g, _, _ = g.residual()
+    value_g = args.envs * args.steps / dt_g
+    log(f"graph arm: {1000 * dt_g / args.steps:.2f} ms/step, {value_g:.0f} env-steps/s")
+    del g
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "env-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "squeeze_blocks: 1024 envs x 10^3-hex block (1331 v, 6000 tets), two box fingers + ground, "
+                        "h=1/60, K=20 local-global iterations, FP32, every contact solve to NCP residual <= 1e-6",
+            "n_envs": args.envs,
+            "vertices_per_env": nv[0],
+            "tets_per_env": int(sc.envs[0].n_elements),
+            "contacts_per_env_mean": round(float(np.mean([s["contacts"] for s in stats])), 1),
+            "lg_iterations": sc.params.lg_iterations,
+            "ncp_tol": sc.params.ncp_tol,
+            "warm_start": "previous-step",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "apply (explicit-inverse global solve, k_gemv)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "bytes_per_launch": bpl,
+            "avg_launch_ms": round(apply_avg, 4),
+            "launches": apply_n,
+        },
+        "max_residual": mx,
+        "residual_ok": bool(mx <= sc.params.ncp_tol),
+        "newton_iters_per_step_mean": round(float(np.mean(its)), 2),
+        "arms": {
+            "plain_eager": {"env_steps_per_s": round(value, 2), "ms_per_step": round(ms_step, 3),
+                            "max_residual": mx},
+            "graph": {"env_steps_per_s": round(value_g, 2), "ms_per_step": round(1000 * dt_g / args.steps, 3),
+                      "max_residual": mx_g},
+        },
+        "kernel_ms_per_step": breakdown,
+        "precompute_s": round(precompute_s, 2),
+    }
+
+    if args.copy_probe:
+        n = 1 << 28
+        a = torch.empty(n, dtype=torch.float32, device="cuda")
+        c = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * 4 * n
+
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -106,7 +106,7 @@ typedef struct {
   int32_t precision;              /* FLASH_FP32 or FLASH_FP64 */
   int32_t warm_start;             /* FLASH_WS_* */
   int32_t use_graph;              /* capture the step in a HIP graph */
-  int32_t max_contacts_per_env;   /* contact capacity per env (0: default 512) */
+  int32_t max_contacts_per_env;   /* contact capacity per env (0: default 320) */
   double inner_tol;               /* stopping tolerance of every contact solve, metres
                                      (0: 0.25 * ncp_tol in FP32, 1e-12 in FP64) */
 } flash_params;
@@ -175,12 +175,24 @@ flash_status flash_residual(flash_batch *b, double *per_env, double *max_out, in
 flash_status flash_stats(flash_batch *b, flash_env_stats *per_env);
 
 /* Per-kernel timing with HIP events recorded on the batch's stream around each
- * launch (off by default).  flash_kernel_times fills up to cap entries of
- * total milliseconds and launch counts, in the order of flash_kernel_name. */
+ * launch of the kernel classes selected by `enable` (bit k = class k in the
+ * order of flash_kernel_name; 0 = off, the default).  A graph-captured step
+ * is replayed without events while timing is on.  flash_kernel_times fills up
+ * to cap entries of total milliseconds and launch counts since the last
+ * flash_set_kernel_timing call. */
 flash_status flash_set_kernel_timing(flash_batch *b, int32_t enable);
 flash_status flash_kernel_times(flash_batch *b, double *total_ms, int64_t *launches, int32_t cap,
                                 int32_t *n_out);
 const char *flash_kernel_name(int32_t i);
+
+/* Diagnostic: ms_out[0..7] = wall-clock milliseconds per env spent in the 8
+ * phases of the contact solve (setup, residual/classification, base inverse,
+ * right-hand sides, capacitance build, capacitance LU, direction, line
+ * search); ms_out[8..11] = per-env counts of capacitance factorisations,
+ * factorisation reuses, line-search failures and solves ended above the
+ * inner tolerance.  Averaged over envs, accumulated since the previous call
+ * (then reset).  ms_out holds 12 doubles. */
+flash_status flash_phase_times(flash_batch *b, double *ms_out);
 
 /* Learned warm start: a 16 -> 128 -> 128 -> 128 -> 3 ReLU MLP predicts the
  * initial multipliers of each contact from local features; BF16 weights,

@@ -150,7 +150,10 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
       sh_c[threadIdx.x][k] = B.obs_c[3 * o + k] + dob;
     }
   }
-  if (threadIdx.x == 0) B.nbase[e] = 0;
+  if (threadIdx.x == 0) {
+    B.nbase[e] = 0;
+    B.lust[4 * e] = 0;
+  }
   __syncthreads();
   const int cur = *B.stamp;
   int count = 0;

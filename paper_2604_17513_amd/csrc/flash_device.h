@@ -86,7 +86,9 @@ struct DevBatch {
   T* Ginv;                    // [cap*cap per env] inverse on the base set
   T* Cm;                      // [rmax*rmax per env] capacitance matrix
   int* base;                  // [cap per env] base-set contact ids (ordered)
+  T* scr;                     // [cap*16 per env] panel scratch of the blocked inverse
   int* nbase;                 // [n_envs]
+  int* lust;                  // [4 per env] stored capacitance factorisation: valid, rows, base version x2
 
   // warm-start cache [NV * kMaxObs]
   T* cache_f;                 // [3 per entry] world force
@@ -99,6 +101,7 @@ struct DevBatch {
   int* refac;                 // [n_envs]
   int* flags;                 // [n_envs]
   int* fp64_polar;            // [n_envs]
+  unsigned long long* phase;  // [n_envs * 12] contact-solve phase ticks and event counts (nullptr: off)
 
   // learned warm start (optional)
   const uint16_t* mlp_w;      // bf16 weights (nullptr: off)

@@ -203,6 +203,7 @@ struct flash_batch {
   std::vector<int> nobs;
   // timing
   bool timing = false;
+  uint32_t timing_mask = 0;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
   std::vector<hipEvent_t> pool;
   double tot_ms[K_COUNT] = {};
@@ -230,7 +231,7 @@ struct flash_batch {
 
   template <class F>
   void launch(int kid, F&& f) {
-    if (!timing) { f(); return; }
+    if (!timing || !((timing_mask >> kid) & 1u)) { f(); return; }
     hipEvent_t a = ev(), b = ev();
     HIPCHK(hipEventRecord(a, stream));
     f();
@@ -302,8 +303,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.n_envs = ne;
   B.NV = b->NV;
   B.NT = b->NT;
-  B.cap = b->p.max_contacts_per_env > 0 ? b->p.max_contacts_per_env : 512;
-  B.rmax = std::min(3 * B.cap, 768);
+  B.cap = b->p.max_contacts_per_env > 0 ? b->p.max_contacts_per_env : 320;
+  B.rmax = std::min(3 * B.cap, 480);
   B.max_newton = b->p.max_inner_iterations > 0 ? b->p.max_inner_iterations : 50;
   B.lg_iterations = b->p.lg_iterations;
   B.h = b->p.h;
@@ -421,10 +422,13 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.Ginv = dalloc<T>(ne * cap * cap, own);
   {
     const size_t rm = (size_t)B.rmax;
-    const size_t tcount = ne * (rm * rm + 8 * rm) + (ne * rm * sizeof(int) + sizeof(T) - 1) / sizeof(T);
+    const size_t tcount = ne * (rm * rm + 16 * rm) + (3 * ne * rm * sizeof(int) + sizeof(T) - 1) / sizeof(T);
     B.Cm = dalloc<T>(tcount, own);
   }
   B.base = dalloc<int>(ne * cap, own);
+  B.scr = dalloc<T>(ne * cap * 16, own);
+  B.lust = dalloc<int>(4 * ne, own);
+  HIPCHK(hipMemset(B.lust, 0, 4 * ne * sizeof(int)));
   B.nbase = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.nbase, 0, ne * sizeof(int)));
   B.cache_f = dalloc<T>(3 * (size_t)NV * kMaxObs, own);
@@ -445,6 +449,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   HIPCHK(hipMemset(B.refac, 0, ne * sizeof(int)));
   HIPCHK(hipMemset(B.flags, 0, ne * sizeof(int)));
   HIPCHK(hipMemset(B.fp64_polar, 0, ne * sizeof(int)));
+  B.phase = dalloc<unsigned long long>((size_t)ne * 12, own);
+  HIPCHK(hipMemset(B.phase, 0, (size_t)ne * 12 * sizeof(unsigned long long)));
   B.mlp_w = nullptr;
   B.mlp_norm = nullptr;
   std::vector<T> mu(ne);
@@ -670,7 +676,7 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS of the contact solve above the default limit
-    if (b->fp64) prepare_csp<double>(b->bd.cap); else prepare_csp<float>(b->bf.cap);
+    if (b->fp64) prepare_csp<double>(b->bd.cap, b->bd.rmax); else prepare_csp<float>(b->bf.cap, b->bf.rmax);
     *out = b;
     return FLASH_OK;
   } catch (const FlashError& ex) {
@@ -779,6 +785,7 @@ flash_status flash_set_kernel_timing(flash_batch* b, int32_t enable) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
   GUARD(b->collect_timing());
   b->timing = enable != 0;
+  b->timing_mask = (uint32_t)enable;
   for (int k = 0; k < K_COUNT; ++k) { b->tot_ms[k] = 0; b->cnt[k] = 0; }
   return FLASH_OK;
 }
@@ -790,6 +797,33 @@ flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launc
   for (int k = 0; k < K_COUNT && k < cap; ++k) {
     if (total_ms) total_ms[k] = b->tot_ms[k];
     if (launches) launches[k] = b->cnt[k];
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_phase_times(flash_batch* b, double* ms_out) {
+  if (!b || !ms_out) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  try {
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int ne = b->n_envs;
+    unsigned long long* dp = b->fp64 ? b->bd.phase : b->bf.phase;
+    std::vector<unsigned long long> h((size_t)ne * 12);
+    HIPCHK(hipMemcpy(h.data(), dp, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    int khz = 0;
+    HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
+    for (int k = 0; k < 8; ++k) {
+      double t = 0;
+      for (int e = 0; e < ne; ++e) t += (double)h[(size_t)e * 8 + k];
+      ms_out[k] = khz > 0 ? t / (double)khz / ne : 0.0;
+    }
+    for (int k = 0; k < 4; ++k) {
+      double t = 0;
+      for (int e = 0; e < ne; ++e) t += (double)h[(size_t)ne * 8 + 4 * e + k];
+      ms_out[8 + k] = t / ne;
+    }
+    HIPCHK(hipMemset(dp, 0, h.size() * sizeof(unsigned long long)));
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
   }
   return FLASH_OK;
 }

@@ -373,6 +373,287 @@ __global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
 }
 
 // ---------------------------------------------------------------------------
+// Workgroup-cooperative dense kernels for the contact solve.  Panels of kBK
+// columns; pivot blocks are staged in LDS; trailing updates use 4x4 register
+// tiles and read the panels from global memory (L1/L2 resident).
+// ---------------------------------------------------------------------------
+constexpr int kBK = 16;
+
+// In-place inverse of a symmetric positive definite n x n matrix (ld n) by
+// blocked Gauss-Jordan sweeps.  CP: global scratch of n x kBK; P: LDS kBK x kBK;
+// v: LDS 2 * kBK.
+template <class T>
+__device__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < n; k0 += kBK) {
+    const int kb = min(kBK, n - k0);
+    __syncthreads();
+    for (int idx = tid; idx < kb * kb; idx += kBlock) {
+      const int i = idx / kb, j = idx - i * kb;
+      P[i * kBK + j] = M[(size_t)(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    for (int k = 0; k < kb; ++k) {
+      const T piv = P[k * kBK + k];
+      if (tid < kb) {
+        v[tid] = P[tid * kBK + k];
+        v[kBK + tid] = P[k * kBK + tid] / piv;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < kb * kb; idx += kBlock) {
+        const int i = idx / kb, j = idx - i * kb;
+        T val;
+        if (i == k) val = (j == k) ? T(1) / piv : v[kBK + j];
+        else val = (j == k) ? -v[i] / piv : P[i * kBK + j] - v[i] * v[kBK + j];
+        P[i * kBK + j] = val;
+      }
+      __syncthreads();
+    }
+    for (int idx = tid; idx < n * kb; idx += kBlock) {
+      const int i = idx / kb, t = idx - i * kb;
+      CP[(size_t)i * kBK + t] = M[(size_t)i * n + k0 + t];
+    }
+    __syncthreads();
+    // row panel: M[k0+t][j] <- sum_s Pinv[t][s] M[k0+s][j] for j outside the block
+    for (int j = tid; j < n; j += kBlock) {
+      if (j >= k0 && j < k0 + kb) continue;
+      T col[kBK];
+      for (int s2 = 0; s2 < kb; ++s2) col[s2] = M[(size_t)(k0 + s2) * n + j];
+      for (int t = 0; t < kb; ++t) {
+        T acc = 0;
+        for (int s2 = 0; s2 < kb; ++s2) acc += P[t * kBK + s2] * col[s2];
+        M[(size_t)(k0 + t) * n + j] = acc;
+      }
+    }
+    __syncthreads();
+    // trailing update M[i][j] -= sum_t M_old[i][k0+t] * M_new[k0+t][j]
+    const int nt = (n + 3) / 4;
+    for (int tile = tid; tile < nt * nt; tile += kBlock) {
+      const int i0 = (tile / nt) * 4, j0 = (tile - (tile / nt) * nt) * 4;
+      T acc[4][4];
+      for (int p = 0; p < 4; ++p)
+        for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+      for (int t = 0; t < kb; ++t) {
+        T a[4], r[4];
+        for (int q = 0; q < 4; ++q) {
+          a[q] = (i0 + q < n) ? CP[(size_t)(i0 + q) * kBK + t] : T(0);
+          r[q] = (j0 + q < n) ? M[(size_t)(k0 + t) * n + j0 + q] : T(0);
+        }
+        for (int p = 0; p < 4; ++p)
+          for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * r[q];
+      }
+      for (int p = 0; p < 4; ++p) {
+        const int i = i0 + p;
+        if (i >= n || (i >= k0 && i < k0 + kb)) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int j = j0 + q;
+          if (j >= n || (j >= k0 && j < k0 + kb)) continue;
+          M[(size_t)i * n + j] -= acc[p][q];
+        }
+      }
+    }
+    // column panel: M[i][k0+t] <- -sum_s M_old[i][k0+s] Pinv[s][t]
+    for (int idx = tid; idx < n * kb; idx += kBlock) {
+      const int i = idx / kb, t = idx - i * kb;
+      if (i >= k0 && i < k0 + kb) continue;
+      T acc = 0;
+      for (int s2 = 0; s2 < kb; ++s2) acc += CP[(size_t)i * kBK + s2] * P[s2 * kBK + t];
+      M[(size_t)i * n + k0 + t] = -acc;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < kb * kb; idx += kBlock) {
+      const int i = idx / kb, j = idx - i * kb;
+      M[(size_t)(k0 + i) * n + k0 + j] = P[i * kBK + j];
+    }
+  }
+  __syncthreads();
+}
+
+// Factors a general n x n matrix A (ld n, overwritten) by a blocked
+// right-looking LU with partial pivoting: rows are swapped across the whole
+// matrix (ties to the lowest row) and the pivot row of step k is stored in
+// piv[k].  Each kBK-column panel is factored in LDS (pan: n * kBK values).
+template <class T>
+__device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
+  const int tid = threadIdx.x;
+  for (int k0 = 0; k0 < n; k0 += kBK) {
+    const int kb = min(kBK, n - k0);
+    const int pr_rows = n - k0;
+    __syncthreads();
+    for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
+      const int i = idx / kb, t = idx - i * kb;
+      pan[i * kBK + t] = A[(size_t)(k0 + i) * n + k0 + t];
+    }
+    __syncthreads();
+    for (int t = 0; t < kb; ++t) {
+      // pivot in panel column t over panel rows t..
+      double best = -1.0;
+      int bi = pr_rows;
+      for (int i = t + tid; i < pr_rows; i += kBlock) {
+        const double a = fabs((double)pan[i * kBK + t]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int d = 32; d > 0; d >>= 1) {
+        const double ob = __shfl_xor(best, d, 64);
+        const int oi = __shfl_xor(bi, d, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (lane_id() == 0) { sh_red[wave_id()] = best; sh_i[wave_id()] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double bb = sh_red[0];
+        int ii = sh_i[0];
+        for (int w = 1; w < kBlock / 64; ++w)
+          if (sh_red[w] > bb || (sh_red[w] == bb && sh_i[w] < ii)) { bb = sh_red[w]; ii = sh_i[w]; }
+        ii = ii < pr_rows ? ii : t;
+        *sh_piv = ii;
+        piv[k0 + t] = k0 + ii;
+      }
+      __syncthreads();
+      const int pr = *sh_piv;
+      if (pr != t && tid < kb) {
+        const T t0 = pan[t * kBK + tid];
+        pan[t * kBK + tid] = pan[pr * kBK + tid];
+        pan[pr * kBK + tid] = t0;
+      }
+      __syncthreads();
+      const T pv = pan[t * kBK + t];
+      const int w = kb - t - 1;
+      for (int i = t + 1 + tid; i < pr_rows; i += kBlock) {
+        const T l = pv != T(0) ? pan[i * kBK + t] / pv : T(0);
+        pan[i * kBK + t] = l;
+        for (int q = 0; q < w; ++q) pan[i * kBK + t + 1 + q] -= l * pan[t * kBK + t + 1 + q];
+      }
+      __syncthreads();
+    }
+    // write the factored panel back; apply the block's row swaps to the other columns
+    for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
+      const int i = idx / kb, t = idx - i * kb;
+      A[(size_t)(k0 + i) * n + k0 + t] = pan[i * kBK + t];
+    }
+    for (int j = tid; j < n; j += kBlock) {
+      if (j >= k0 && j < k0 + kb) continue;
+      for (int t = 0; t < kb; ++t) {
+        const int pr = piv[k0 + t];
+        if (pr != k0 + t) {
+          const T t0 = A[(size_t)(k0 + t) * n + j];
+          A[(size_t)(k0 + t) * n + j] = A[(size_t)pr * n + j];
+          A[(size_t)pr * n + j] = t0;
+        }
+      }
+    }
+    for (int idx = tid; idx < kb * kb; idx += kBlock) {
+      const int i = idx / kb, j = idx - i * kb;
+      L11[i * kBK + j] = pan[i * kBK + j];
+    }
+    __syncthreads();
+    // U12 = L11^-1 A12 (unit lower)
+    for (int j = k0 + kb + tid; j < n; j += kBlock) {
+      T col[kBK];
+      for (int t = 0; t < kb; ++t) col[t] = A[(size_t)(k0 + t) * n + j];
+      for (int t = 0; t < kb; ++t) {
+        T v = col[t];
+        for (int s2 = 0; s2 < t; ++s2) v -= L11[t * kBK + s2] * col[s2];
+        col[t] = v;
+      }
+      for (int t = 0; t < kb; ++t) A[(size_t)(k0 + t) * n + j] = col[t];
+    }
+    __syncthreads();
+    // A22 -= L21 U12 (L21 read from the LDS panel)
+    const int m0 = k0 + kb, mm = n - m0;
+    if (mm > 0) {
+      const int nt = (mm + 3) / 4;
+      for (int tile = tid; tile < nt * nt; tile += kBlock) {
+        const int i0 = m0 + (tile / nt) * 4, j0 = m0 + (tile - (tile / nt) * nt) * 4;
+        T acc[4][4];
+        for (int p = 0; p < 4; ++p)
+          for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+        for (int t = 0; t < kb; ++t) {
+          T a[4], b[4];
+          for (int q = 0; q < 4; ++q) {
+            a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * kBK + t] : T(0);
+            b[q] = (j0 + q < n) ? A[(size_t)(k0 + t) * n + j0 + q] : T(0);
+          }
+          for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+        }
+        for (int p = 0; p < 4; ++p) {
+          if (i0 + p >= n) continue;
+          for (int q = 0; q < 4; ++q)
+            if (j0 + q < n) A[(size_t)(i0 + p) * n + j0 + q] -= acc[p][q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Solves A y = r with the factors of wg_lu_factor.  r[16 q + 6] holds the
+// right-hand side; the solution goes to r[16 q + 7].  ys: LDS of n values;
+// D: LDS kBK * kBK.
+template <class T>
+__device__ void wg_lu_apply(const T* A, int n, const int* piv, T* r, T* ys, T* D) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * q + 6];
+  __syncthreads();
+  if (tid == 0)
+    for (int k = 0; k < n; ++k) {
+      const int pr = piv[k];
+      if (pr != k) { const T t0 = ys[k]; ys[k] = ys[pr]; ys[pr] = t0; }
+    }
+  __syncthreads();
+  // forward substitution with the unit lower factor
+  for (int k0 = 0; k0 < n; k0 += kBK) {
+    const int kb = min(kBK, n - k0);
+    for (int idx = tid; idx < kb * kb; idx += kBlock) {
+      const int i = idx / kb, j = idx - i * kb;
+      D[i * kBK + j] = A[(size_t)(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int t = 0; t < kb; ++t) {
+        T y = ys[k0 + t];
+        for (int s2 = 0; s2 < t; ++s2) y -= D[t * kBK + s2] * ys[k0 + s2];
+        ys[k0 + t] = y;
+      }
+    __syncthreads();
+    for (int i = k0 + kb + tid; i < n; i += kBlock) {
+      T acc = 0;
+      for (int t = 0; t < kb; ++t) acc += A[(size_t)i * n + k0 + t] * ys[k0 + t];
+      ys[i] -= acc;
+    }
+    __syncthreads();
+  }
+  // back substitution with the upper factor
+  const int nblk = (n + kBK - 1) / kBK;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int k0 = bk * kBK, kb = min(kBK, n - k0);
+    for (int idx = tid; idx < kb * kb; idx += kBlock) {
+      const int i = idx / kb, j = idx - i * kb;
+      D[i * kBK + j] = A[(size_t)(k0 + i) * n + k0 + j];
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int t = kb - 1; t >= 0; --t) {
+        T y = ys[k0 + t];
+        for (int s2 = t + 1; s2 < kb; ++s2) y -= D[t * kBK + s2] * ys[k0 + s2];
+        const T d = D[t * kBK + t];
+        ys[k0 + t] = d != T(0) ? y / d : T(0);
+      }
+    __syncthreads();
+    for (int i = tid; i < k0; i += kBlock) {
+      T acc = 0;
+      for (int t = 0; t < kb; ++t) acc += A[(size_t)i * n + k0 + t] * ys[k0 + t];
+      ys[i] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < n; q += kBlock) r[16 * q + 7] = ys[q];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Contact subproblem (Eq. 2b with Eq. 4 at fixed projections): find lambda
 // with Phi(lambda) = 0 for Y(lambda) = y_free + W lambda,
 // W = h^2 F^T (Gc (x) I3) F the exact Delassus operator of the env.
@@ -385,13 +666,15 @@ __global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
 template <class T>
 struct CspSmem {
   T *lam, *Y, *yf, *dl, *Wd, *rv, *x0, *fw;   // [3*cap]
-  T *sp, *kap, *yh0, *yh1, *colk, *rowk;      // [cap]
+  T *sp, *kap, *yh0, *yh1;                    // [cap]
+  T *pan, *ys;                                // [rmax*kBK], [rmax]
   int *cls, *pos, *bas;                       // [cap]
 };
 
 template <class T>
-__host__ __device__ size_t csp_smem_bytes(int cap) {
-  return (size_t)cap * (24 + 6) * sizeof(T) + (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
+__host__ __device__ size_t csp_smem_bytes(int cap, int rmax) {
+  return (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 1) * sizeof(T) +
+         (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
 }
 
 // class bits: 1 normal active, 2 tangential stick, 4 tangential slip (neither: rho = 0)
@@ -425,14 +708,15 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     S.lam = p; p += 3 * cap; S.Y = p; p += 3 * cap; S.yf = p; p += 3 * cap; S.dl = p; p += 3 * cap;
     S.Wd = p; p += 3 * cap; S.rv = p; p += 3 * cap; S.x0 = p; p += 3 * cap; S.fw = p; p += 3 * cap;
     S.sp = p; p += cap; S.kap = p; p += cap; S.yh0 = p; p += cap; S.yh1 = p; p += cap;
-    S.colk = p; p += cap; S.rowk = p; p += cap;
+    S.pan = p; p += (size_t)B.rmax * kBK; S.ys = p; p += B.rmax;
     int* ip = reinterpret_cast<int*>(p);
     S.cls = ip; ip += cap; S.pos = ip; ip += cap; S.bas = ip; ip += cap;
   }
   __shared__ double sh_red[kBlock / 64];
   __shared__ int sh_i[kBlock / 64];
   __shared__ int sh_nb, sh_nR, sh_piv;
-  __shared__ T sh_pivv;
+  __shared__ T sh_blk[kBK * kBK];
+  __shared__ T sh_vv[2 * kBK];
 
   const size_t cb = (size_t)e * cap;
   const T* Gc = B.Gc + cb * cap;           // ld c
@@ -444,11 +728,24 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   const T maxf = (T)B.max_force;
   const T* Fr = B.cframe + 9 * cb;
   const int tid = threadIdx.x;
+  // per-phase wall-clock accounting (thread 0, when enabled)
+  unsigned long long t_mark = (B.phase && tid == 0) ? wall_clock64() : 0ull;
+  auto mark = [&](int ph) {
+    if (B.phase && tid == 0) {
+      const unsigned long long now = wall_clock64();
+      B.phase[(size_t)e * 8 + ph] += now - t_mark;
+      t_mark = now;
+    }
+  };
 
-  // per-R-row data in global scratch (after the rmax*rmax matrix)
-  T* Rv = B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 8;  // vR(3) uR(3) rhs y
-  int* Rj = reinterpret_cast<int*>(B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 8) +
-            (size_t)e * B.rmax;
+  // per-R-row data in global scratch (after the rmax*rmax matrices):
+  // vR(3) uR(3) rhs y Krow(3) Erow(3) -- 16 values per row
+  T* Rv = B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 16;
+  int* Rj = reinterpret_cast<int*>(B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 16) +
+            (size_t)e * B.rmax * 3;
+  int* RjF = Rj + B.rmax;      // row list of the stored factorisation
+  int* piv = Rj + 2 * B.rmax;  // its pivots
+  int* lust = B.lust + 4 * e;  // valid, nR, base version at factorisation, current base version
 
   // ---- load state ----
   if (tid == 0) sh_nb = B.nbase[e];
@@ -517,9 +814,10 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     }
   }
 
-  int it = 0, nref = 0;
+  int it = 0, nref = 0, nfact = 0, nreuse = 0, nlsfail = 0;
   const int maxit = B.max_newton;
   double r = 0.0;
+  mark(0);
   for (;; ++it) {
     // ---- Phi (inner scale), classification, residual (residual scale, FP64) ----
     double rloc = 0.0, psil = 0.0;
@@ -561,6 +859,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     }
     r = block_max(rloc, sh_red);
     const double psi = 0.5 * block_sum(psil, sh_red);
+    mark(1);
     if (r <= B.tol || it >= maxit) break;
 
     // ---- base set: refactor when a coupled contact lies outside it ----
@@ -591,26 +890,13 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
         if (p == q && p > 0 && B.cvert[cb + jp] == B.cvert[cb + S.bas[p - 1]]) g *= T(1.0001);
         Ginv[idx] = g;
       }
-      for (int k = 0; k < nb; ++k) {
-        __syncthreads();
-        const T piv = Ginv[(size_t)k * nb + k];
-        for (int i = tid; i < nb; i += kBlock) {
-          S.colk[i] = Ginv[(size_t)i * nb + k];
-          S.rowk[i] = Ginv[(size_t)k * nb + i] / piv;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < nb * nb; idx += kBlock) {
-          const int i = idx / nb, jj = idx - i * nb;
-          T v;
-          if (i == k) v = (jj == k) ? T(1) / piv : S.rowk[jj];
-          else v = (jj == k) ? -S.colk[i] / piv : Ginv[idx] - S.colk[i] * S.rowk[jj];
-          Ginv[idx] = v;
-        }
-      }
+      wg_spd_inverse(Ginv, nb, B.scr + cb * kBK, sh_blk, sh_vv);
+      if (tid == 0) lust[3] += 1;
       __syncthreads();
       ++nref;
     }
 
+    mark(2);
     // ---- decoupled contacts (outside the base): local rows E = sp I ----
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) {
@@ -652,6 +938,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     }
     __syncthreads();
 
+    mark(3);
     // ---- capacitance rows R: base rows whose (K, E) differ from (I, 0) ----
     if (tid == 0) sh_nR = 0;
     __syncthreads();
@@ -683,111 +970,68 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       }
     }
     const int nR = min(sh_nR, B.rmax);
+    bool reused = false;
     if (nR > 0) {
-      // per-row vectors: vR = F E^T[:, a] (world), uR = F[:, a]; rhs
+      // reuse the stored factorisation when its row set and base are unchanged
+      int diff = 0;
+      if (lust[0] && lust[1] == nR && lust[2] == lust[3]) {
+        for (int q = tid; q < nR; q += kBlock) diff |= Rj[q] != RjF[q];
+      } else {
+        diff = 1;
+      }
+      reused = block_max((double)diff, sh_red) == 0.0;
+      if (!reused) {
+        // per-row vectors: vR = F E^T[:, a] (world), uR = F[:, a], K and E rows (contact frame)
+        for (int q = tid; q < nR; q += kBlock) {
+          const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
+          T K[3][3], E[3][3];
+          contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
+          const T* F = Fr + 9 * j;
+          T* rv = Rv + 16 * q;
+          for (int k = 0; k < 3; ++k) {
+            rv[k] = E[a][0] * F[k] + E[a][1] * F[3 + k] + E[a][2] * F[6 + k];
+            rv[3 + k] = F[3 * a + k];
+            rv[8 + k] = K[a][k];
+            rv[11 + k] = E[a][k];
+          }
+          RjF[q] = ja;
+        }
+        __syncthreads();
+        // C[q][s] = [same contact] K[a][b] + h^-2 Ginv[pj][pk] (vR_q . uR_s)
+        for (int idx = tid; idx < nR * nR; idx += kBlock) {
+          const int q = idx / nR, s2 = idx - q * nR;
+          const int jaq = Rj[q], jas = Rj[s2];
+          const int jq = jaq / 3, js = jas / 3, as = jas - 3 * js;
+          const T* vq = Rv + 16 * q;
+          const T* us = Rv + 16 * s2 + 3;
+          T v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
+          if (jq == js) v += vq[8 + as];
+          Cm[idx] = v;
+        }
+        __syncthreads();
+        mark(4);
+        wg_lu_factor(Cm, nR, piv, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
+        if (tid == 0) { lust[0] = 1; lust[1] = nR; lust[2] = lust[3]; ++nfact; }
+      } else if (tid == 0) {
+        ++nreuse;
+      }
+      // rhs of the capacitance system from the stored K and E rows
       for (int q = tid; q < nR; q += kBlock) {
         const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
-        T K[3][3], E[3][3];
-        contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
-        const T* F = Fr + 9 * j;
-        T* rv = Rv + 8 * q;
-        for (int k = 0; k < 3; ++k) {
-          rv[k] = E[a][0] * F[k] + E[a][1] * F[3 + k] + E[a][2] * F[6 + k];
-          rv[3 + k] = F[3 * a + k];
-        }
+        T* rv = Rv + 16 * q;
         T rr = -S.rv[3 * j + a];
-        for (int b = 0; b < 3; ++b) rr += K[a][b] * S.rv[3 * j + b] + E[a][b] * S.x0[3 * j + b];
+        for (int b = 0; b < 3; ++b) rr += rv[8 + b] * S.rv[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
         rv[6] = rr;
       }
-      __syncthreads();
-      // C[q][s] = [same contact] K[a][b] + h^-2 Ginv[pj][pk] (vR_q . uR_s)
-      for (int idx = tid; idx < nR * nR; idx += kBlock) {
-        const int q = idx / nR, s = idx - q * nR;
-        const int jaq = Rj[q], jas = Rj[s];
-        const int jq = jaq / 3, aq = jaq - 3 * jq, js = jas / 3, as = jas - 3 * js;
-        const T* vq = Rv + 8 * q;
-        const T* us = Rv + 8 * s + 3;
-        T v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
-        if (jq == js) {
-          T K[3][3], E[3][3];
-          contact_KE(S.cls[jq], S.sp[jq], mu, S.kap[jq], S.yh0[jq], S.yh1[jq], K, E);
-          v += K[aq][as];
-        }
-        Cm[idx] = v;
-      }
-      // LU with partial pivoting; rhs in Rv[8q+6]
-      for (int k = 0; k < nR; ++k) {
-        __syncthreads();
-        // pivot search
-        double best = -1.0;
-        int bi = k;
-        for (int i = k + tid; i < nR; i += kBlock) {
-          const double a = fabs((double)Cm[(size_t)i * nR + k]);
-          if (a > best) { best = a; bi = i; }
-        }
-        // block argmax (ties -> lowest row)
-        for (int d = 32; d > 0; d >>= 1) {
-          double ob = __shfl_xor(best, d, 64);
-          int oi = __shfl_xor(bi, d, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        __syncthreads();
-        if (lane_id() == 0) { sh_red[wave_id()] = best; sh_i[wave_id()] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-          double bb = sh_red[0];
-          int ii = sh_i[0];
-          for (int w = 1; w < kBlock / 64; ++w)
-            if (sh_red[w] > bb || (sh_red[w] == bb && sh_i[w] < ii)) { bb = sh_red[w]; ii = sh_i[w]; }
-          sh_piv = ii;
-        }
-        __syncthreads();
-        const int pr = sh_piv;
-        if (pr != k) {
-          for (int jj = tid; jj < nR; jj += kBlock) {
-            T t0 = Cm[(size_t)k * nR + jj];
-            Cm[(size_t)k * nR + jj] = Cm[(size_t)pr * nR + jj];
-            Cm[(size_t)pr * nR + jj] = t0;
-          }
-          if (tid == 0) { T t0 = Rv[8 * k + 6]; Rv[8 * k + 6] = Rv[8 * pr + 6]; Rv[8 * pr + 6] = t0; }
-        }
-        __syncthreads();
-        if (tid == 0) sh_pivv = Cm[(size_t)k * nR + k];
-        __syncthreads();
-        const T pv = sh_pivv;
-        for (int i = k + 1 + tid; i < nR; i += kBlock) {
-          const T l = pv != T(0) ? Cm[(size_t)i * nR + k] / pv : T(0);
-          Cm[(size_t)i * nR + k] = l;
-        }
-        __syncthreads();
-        for (int idx = tid; idx < (nR - k - 1) * (nR - k); idx += kBlock) {
-          const int i = k + 1 + idx / (nR - k), jj = k + idx % (nR - k);
-          const T l = Cm[(size_t)i * nR + k];
-          if (jj == k) continue;
-          Cm[(size_t)i * nR + jj] -= l * Cm[(size_t)k * nR + jj];
-        }
-        __syncthreads();
-        for (int i = k + 1 + tid; i < nR; i += kBlock) Rv[8 * i + 6] -= Cm[(size_t)i * nR + k] * Rv[8 * k + 6];
-      }
-      // back substitution -> y in Rv[8q+7]
-      for (int k = nR - 1; k >= 0; --k) {
-        __syncthreads();
-        if (tid == 0) {
-          const T d = Cm[(size_t)k * nR + k];
-          Rv[8 * k + 7] = d != T(0) ? Rv[8 * k + 6] / d : T(0);
-        }
-        __syncthreads();
-        const T yk = Rv[8 * k + 7];
-        for (int i = tid; i < k; i += kBlock) Rv[8 * i + 6] -= Cm[(size_t)i * nR + k] * yk;
-      }
-      __syncthreads();
+      wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
+      mark(5);
       // dl_base = x0 - h^-2 F^T sum_s Ginv[ps][p] (uR_s y_s)
       for (int p = tid; p < nb; p += kBlock) {
         T w0 = 0, w1 = 0, w2 = 0;
         for (int s = 0; s < nR; ++s) {
           const int js = Rj[s] / 3;
-          const T g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[8 * s + 7];
-          const T* us = Rv + 8 * s + 3;
+          const T g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[16 * s + 7];
+          const T* us = Rv + 16 * s + 3;
           w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
         }
         const int j = S.bas[p];
@@ -805,6 +1049,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     // undo the decoupled part's effect: Wd currently = W dl_D; recompute W dl (all)
     apply_W(S.dl, S.Wd);
 
+    mark(6);
     // ---- backtracking line search on 1/2 |Phi|^2 (inner scale) ----
     T alpha = 1;
     bool ok = false;
@@ -835,12 +1080,17 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       alpha *= T(0.5);
     }
     if (!ok) alpha = alpha * T(2);   // smallest tried step: keep moving
+    if (tid == 0) {
+      if (!ok) ++nlsfail;
+      if (reused && (!ok || alpha < T(1))) lust[0] = 0;   // frozen rows too far off: refactor next
+    }
     for (int j = tid; j < c; j += kBlock)
       for (int a = 0; a < 3; ++a) {
         S.lam[3 * j + a] = fmin(fmax(S.lam[3 * j + a] + alpha * S.dl[3 * j + a], -maxf), maxf);
         S.Y[3 * j + a] += alpha * S.Wd[3 * j + a];
       }
     __syncthreads();
+    mark(7);
     if ((it & 7) == 7) {   // refresh Y from lambda to stop drift
       apply_W(S.lam, S.Y);
       for (int j = tid; j < c; j += kBlock)
@@ -848,6 +1098,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       __syncthreads();
     }
   }
+  mark(7);
   // ---- write back ----
   for (int j = tid; j < c; j += kBlock) {
     const T* F = Fr + 9 * j;
@@ -860,6 +1111,12 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     B.nbase[e] = nb;
     B.iters[e] += it;
     B.refac[e] += nref;
+    if (B.phase) {
+      B.phase[(size_t)B.n_envs * 8 + 4 * e + 0] += nfact;
+      B.phase[(size_t)B.n_envs * 8 + 4 * e + 1] += nreuse;
+      B.phase[(size_t)B.n_envs * 8 + 4 * e + 2] += nlsfail;
+      B.phase[(size_t)B.n_envs * 8 + 4 * e + 3] += (r > B.tol) ? 1 : 0;
+    }
     if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
   }
 }
@@ -889,19 +1146,19 @@ void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s) {
 }
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
-  size_t sm = csp_smem_bytes<T>(B.cap);
+  size_t sm = csp_smem_bytes<T>(B.cap, B.rmax);
   hipLaunchKernelGGL(k_csp<T>, dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
 }
 
 template <class T>
-void prepare_csp(int cap) {
-  size_t sm = csp_smem_bytes<T>(cap);
+void prepare_csp(int cap, int rmax) {
+  size_t sm = csp_smem_bytes<T>(cap, rmax);
   hipError_t err = hipFuncSetAttribute((const void*)k_csp<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
   (void)err;
 }
 
 #define INST(T)                                                          \
-  template void prepare_csp<T>(int);                                     \
+  template void prepare_csp<T>(int, int);                                \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
   template void launch_project<T>(const DevBatch<T>&, hipStream_t);      \
   template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \

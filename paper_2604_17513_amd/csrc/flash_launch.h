@@ -13,6 +13,6 @@ template <class T> void launch_apply(const DevBatch<T>& B, int max_ld, hipStream
 template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s);
 template <class T> void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s);
 // Raises the dynamic LDS limit of the contact-solve kernel for `cap` contacts per env.
-template <class T> void prepare_csp(int cap);
+template <class T> void prepare_csp(int cap, int rmax);
 
 }  // namespace flash

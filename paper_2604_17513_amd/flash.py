@@ -34,7 +34,8 @@ EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_stats", "flash_set_kernel_timing",
-    "flash_kernel_times", "flash_kernel_name", "flash_ws_load", "flash_last_error", "flash_version",
+    "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_ws_load", "flash_last_error",
+    "flash_version",
 ]
 
 
@@ -101,6 +102,7 @@ def lib():
         L.flash_kernel_times.argtypes = [P, D, C.POINTER(C.c_int64), I32, C.POINTER(I32)]
         L.flash_kernel_name.argtypes = [I32]
         L.flash_kernel_name.restype = C.c_char_p
+        L.flash_phase_times.argtypes = [P, D]
         L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, C.POINTER(C.c_float)]
         L.flash_last_error.restype = C.c_char_p
         L.flash_version.restype = C.c_char_p
@@ -284,8 +286,20 @@ class Batch:
                      contacts=s.contacts, fp64_polar=s.fp64_polar, flags=s.flags, residual=s.residual)
                 for s in arr]
 
-    def set_kernel_timing(self, on: bool):
-        _check(lib().flash_set_kernel_timing(self._h, 1 if on else 0))
+    def set_kernel_timing(self, mask):
+        """mask: True (every kernel class), False (off) or a bitmask of kernel classes."""
+        if mask is True:
+            mask = 0xFFFF
+        elif mask is False:
+            mask = 0
+        _check(lib().flash_set_kernel_timing(self._h, int(mask)))
+
+    def phase_times(self):
+        out = np.zeros(12)
+        _check(lib().flash_phase_times(self._h, _dptr(out)))
+        names = ["setup", "residual", "base_inverse", "rhs", "cap_build", "cap_lu", "direction", "line_search",
+                 "n_factor", "n_reuse", "n_ls_fail", "n_unconverged"]
+        return dict(zip(names, out.tolist()))
 
     def kernel_times(self):
         ms = np.zeros(16)
