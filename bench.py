@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
+    ap.add_argument("--quick", action="store_true", help="skip the graph arm and the per-kernel breakdown")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: environments are independent and this build "
@@ -139,25 +140,26 @@ def main():
     achieved = bpl / (apply_avg * 1e-3) / 1e9
     log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.0f} env-steps/s; apply avg {apply_avg:.3f} ms")
 
-    # per-kernel breakdown (separate pass, every class timed)
-    b.set_kernel_timing(True)
-    b.step(2)
-    b.synchronize()
-    breakdown = {k: round(v[0] / 2, 3) for k, v in b.kernel_times().items() if v[1]}
-    b.set_kernel_timing(0)
-
-    # graph-captured variant of the same step
-    g = F.from_scene(scenes.squeeze_blocks(args.envs, seed=0), use_graph=True)
-    g.step(args.warmup)
-    g.synchronize()
-    t0 = time.perf_counter()
-    g.step(args.steps)
-    g.synchronize()
-    dt_g = time.perf_counter() - t0
-    _, mx_g, _, _ = g.residual()
-    value_g = args.envs * args.steps / dt_g
-    log(f"graph arm: {1000 * dt_g / args.steps:.2f} ms/step, {value_g:.0f} env-steps/s")
-    del g
+    breakdown, value_g, dt_g, mx_g = {}, None, None, None
+    if not args.quick:
+        # per-kernel breakdown (separate pass, every class timed)
+        b.set_kernel_timing(True)
+        b.step(2)
+        b.synchronize()
+        breakdown = {k: round(v[0] / 2, 3) for k, v in b.kernel_times().items() if v[1]}
+        b.set_kernel_timing(0)
+        # graph-captured variant of the same step
+        g = F.from_scene(scenes.squeeze_blocks(args.envs, seed=0), use_graph=True)
+        g.step(args.warmup)
+        g.synchronize()
+        t0 = time.perf_counter()
+        g.step(args.steps)
+        g.synchronize()
+        dt_g = time.perf_counter() - t0
+        _, mx_g, _, _ = g.residual()
+        value_g = args.envs * args.steps / dt_g
+        log(f"graph arm: {1000 * dt_g / args.steps:.2f} ms/step, {value_g:.0f} env-steps/s")
+        del g
 
     out = {
         "metric": METRIC,
@@ -201,8 +203,9 @@ def main():
         "arms": {
             "plain_eager": {"env_steps_per_s": round(value, 2), "ms_per_step": round(ms_step, 3),
                             "max_residual": mx},
-            "graph": {"env_steps_per_s": round(value_g, 2), "ms_per_step": round(1000 * dt_g / args.steps, 3),
-                      "max_residual": mx_g},
+            "graph": None if value_g is None else {
+                "env_steps_per_s": round(value_g, 2), "ms_per_step": round(1000 * dt_g / args.steps, 3),
+                "max_residual": mx_g},
         },
         "kernel_ms_per_step": breakdown,
         "precompute_s": round(precompute_s, 2),

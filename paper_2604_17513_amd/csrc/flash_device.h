@@ -4,7 +4,8 @@
 // all environments: component c of vertex i lives at [c * NV + i].  Per-tet
 // data is SoA the same way over all tets.  Per-contact data lives in one slab
 // of `cap` records per environment.  The explicit inverse Gbar = Abar^-1 of
-// each environment is a dense row-major n x ld block (ld = n rounded up to 4).
+// each environment is a dense row-major n x ld block (ld = n rounded up to 32,
+// so that every row starts on a 128-byte line).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -51,9 +52,9 @@ struct DevBatch {
   const int* tet_idx;         // [4*NT] global vertex ids
   const T* tet_B;             // [9*NT] D_m^-1 row-major (B[r][c] at (3r+c)*NT)
   const T* tet_w;             // [NT]
-  T* fel;                     // [12*NT] per-tet vertex forces w (p - F_x) gradN_a
-  const int* inc_off;         // [NV+1]
-  const int* inc;             // [4*NT] entries t*4+a
+  T* fel;                     // [3 per incidence] vertex forces w (p - F_x) gradN_a, vertex-ordered
+  const int* inc_off;         // [NV+1] incidence ranges per vertex
+  const int* slot;            // [4*NT] incidence slot of (tet t, local vertex a) at t*4+a
 
   const T* G;                 // dense inverses
   const int64_t* goff;        // [n_envs] element offset of env block

@@ -323,7 +323,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   }
   std::vector<T> x(3 * (size_t)NV), mass(NV), tB(9 * (size_t)NT), tw(NT);
   std::vector<int> tidx(4 * (size_t)NT);
-  std::vector<int> inc_off(NV + 1, 0), inc(4 * (size_t)NT);
+  std::vector<int> inc_off(NV + 1, 0), slot(4 * (size_t)NT);
   for (int e = 0; e < ne; ++e) {
     const HostEnv& h = H[e];
     const int vo = b->voff[e], to = b->toff[e];
@@ -342,7 +342,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   {
     std::vector<int> fillp(inc_off.begin(), inc_off.end() - 1);
     for (int t = 0; t < NT; ++t)
-      for (int a = 0; a < 4; ++a) inc[fillp[tidx[(size_t)a * NT + t]]++] = t * 4 + a;
+      for (int a = 0; a < 4; ++a) slot[(size_t)t * 4 + a] = fillp[tidx[(size_t)a * NT + t]]++;
   }
   // dense inverses
   std::vector<int64_t> goff(ne);
@@ -351,7 +351,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   int max_ld = 0;
   for (int e = 0; e < ne; ++e) {
     const int n = H[e].n;
-    const int ld = (n + 3) / 4 * 4;
+    const int ld = (n + 31) / 32 * 32;   // 128-byte aligned rows
     goff[e] = gtot;
     gld[e] = ld;
     gtot += (int64_t)n * ld;
@@ -391,7 +391,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   T* d_tw = dalloc<T>(NT, own); up(d_tw, tw); B.tet_w = d_tw;
   B.fel = dalloc<T>(12 * (size_t)NT, own);
   int* d_io = dalloc<int>(NV + 1, own); up(d_io, inc_off); B.inc_off = d_io;
-  int* d_inc = dalloc<int>(4 * (size_t)NT, own); up(d_inc, inc); B.inc = d_inc;
+  int* d_slot = dalloc<int>(4 * (size_t)NT, own); up(d_slot, slot); B.slot = d_slot;
   B.G = G;
   int64_t* d_goff = dalloc<int64_t>(ne, own); up(d_goff, goff); B.goff = d_goff;
   int* d_gld = dalloc<int>(ne, own); up(d_gld, gld); B.gld = d_gld;

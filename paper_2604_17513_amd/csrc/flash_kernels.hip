@@ -233,31 +233,34 @@ __global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
   const T w = B.tet_w[t];
   T P[9];
   for (int k = 0; k < 9; ++k) P[k] = w * (R[k] - Fx[k]);
+  // vertex forces go to their slots in the vertex-ordered incidence list
   T f0[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) {
+    T* dst = B.fel + 3 * (size_t)B.slot[4 * (size_t)t + a + 1];
     for (int r = 0; r < 3; ++r) {
       T fa = P[3 * r] * Bm[3 * a] + P[3 * r + 1] * Bm[3 * a + 1] + P[3 * r + 2] * Bm[3 * a + 2];
-      B.fel[((a + 1) * 3 + r) * (size_t)NT + t] = fa;
+      dst[r] = fa;
       f0[r] -= fa;
     }
   }
-  for (int r = 0; r < 3; ++r) B.fel[(size_t)r * NT + t] = f0[r];
+  T* dst0 = B.fel + 3 * (size_t)B.slot[4 * (size_t)t];
+  for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
 }
 
-// b = M u~ + h^2 sum over incident tets (fixed incidence order).
+// b = M u~ + h^2 sum over incident tets (fixed incidence order; the forces of
+// vertex i occupy the contiguous slots inc_off[i] .. inc_off[i+1]-1).
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
   const int i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= B.NV) return;
-  const int NT = B.NT, NV = B.NV;
+  const int NV = B.NV;
   T s0 = 0, s1 = 0, s2 = 0;
   const int p1 = B.inc_off[i + 1];
   for (int p = B.inc_off[i]; p < p1; ++p) {
-    const int ea = B.inc[p];
-    const int t = ea >> 2, a = ea & 3;
-    s0 += B.fel[(size_t)(a * 3 + 0) * NT + t];
-    s1 += B.fel[(size_t)(a * 3 + 1) * NT + t];
-    s2 += B.fel[(size_t)(a * 3 + 2) * NT + t];
+    const T* f = B.fel + 3 * (size_t)p;
+    s0 += f[0];
+    s1 += f[1];
+    s2 += f[2];
   }
   const T hh = (T)(B.h * B.h);
   const T m = B.mass[i];
