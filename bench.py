@@ -119,6 +119,7 @@ def main():
 
     b.step(args.warmup)
     b.synchronize()
+    b.residual_history(reset=True)
 
     # timed region: events around every global-apply launch (the dominant kernel)
     b.set_kernel_timing(1 << K_APPLY)
@@ -131,6 +132,7 @@ def main():
     kt = b.kernel_times()
     b.set_kernel_timing(0)
     per, mx, its, st = b.residual()
+    hist_max, hist_over = b.residual_history(reset=True)
     stats = b.stats()
     value = args.envs * args.steps / dt
     ms_step = 1000.0 * dt / args.steps
@@ -197,8 +199,9 @@ def main():
             "avg_launch_ms": round(apply_avg, 4),
             "launches": apply_n,
         },
-        "max_residual": mx,
-        "residual_ok": bool(mx <= sc.params.ncp_tol),
+        "max_residual": hist_max,
+        "env_steps_above_tol": hist_over,
+        "residual_ok": bool(hist_max <= sc.params.ncp_tol),
         "newton_iters_per_step_mean": round(float(np.mean(its)), 2),
         "arms": {
             "plain_eager": {"env_steps_per_s": round(value, 2), "ms_per_step": round(ms_step, 3),

@@ -109,6 +109,10 @@ typedef struct {
   int32_t max_contacts_per_env;   /* contact capacity per env (0: default 320) */
   double inner_tol;               /* stopping tolerance of every contact solve, metres
                                      (0: 0.25 * ncp_tol in FP32, 1e-12 in FP64) */
+  int32_t contact_fp32;           /* FP32 batches: 0 (default) runs the per-env contact-space
+                                     solve in FP64, 1 in FP32 (stalls on stiff, high-friction
+                                     contact sets); FP64 batches ignore it */
+  int32_t reserved_params;
 } flash_params;
 
 /* One contact of the last step.  impulse = h F lambda in the world frame (N s);
@@ -173,6 +177,11 @@ flash_status flash_contacts(flash_batch *b, int32_t env, flash_contact *out, int
  * non-finite state, FLASH_ERR_NOT_CONVERGED if an env ended above ncp_tol. */
 flash_status flash_residual(flash_batch *b, double *per_env, double *max_out, int32_t *inner_iters);
 flash_status flash_stats(flash_batch *b, flash_env_stats *per_env);
+
+/* Worst end-of-step NCP residual over all envs and steps since the previous
+ * reset (*max_out, metres) and the number of env-steps that ended above
+ * ncp_tol (*over_out).  reset != 0 clears both after reading. */
+flash_status flash_residual_history(flash_batch *b, double *max_out, int64_t *over_out, int32_t reset);
 
 /* Per-kernel timing with HIP events recorded on the batch's stream around each
  * launch of the kernel classes selected by `enable` (bit k = class k in the

@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
             }
             fresh = 0;
           }
-          B.clam[3 * j] = l0; B.clam[3 * j + 1] = l1; B.clam[3 * j + 2] = l2;
+          B.clam[3 * j] = (double)l0; B.clam[3 * j + 1] = (double)l1; B.clam[3 * j + 2] = (double)l2;
           B.cnew[j] = fresh;
         }
         ++slot;
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     for (int a = 0; a < 3; ++a)
       Y[a] = (double)F[3 * a] * uw[0] + (double)F[3 * a + 1] * uw[1] + (double)F[3 * a + 2] * uw[2];
     double s = h * h / (double)B.mass[vi];
-    double ln = (double)B.clam[3 * j], l1 = (double)B.clam[3 * j + 1], l2 = (double)B.clam[3 * j + 2];
+    double ln = B.clam[3 * j], l1 = B.clam[3 * j + 1], l2 = B.clam[3 * j + 2];
     double cn = B.cd0d[j] + Y[0];
     double pn = fmin(cn, s * ln);
     double ut1 = Y[1] - (double)B.cdob[2 * j], ut2 = Y[2] - (double)B.cdob[2 * j + 1];
@@ -303,6 +303,9 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     double m = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, sh_red[w]);
     B.resid[e] = m;
+    // worst residual and over-tolerance step count since the last statistics reset
+    B.resid_hist[2 * e] = fmax(B.resid_hist[2 * e], m);
+    if (!(m <= B.ncp_tol)) B.resid_hist[2 * e + 1] += 1.0;
   }
   if (bad) atomicOr(&B.flags[e], 1);
   __syncthreads();

@@ -35,6 +35,7 @@ struct DevBatch {
   double tol;
   double max_force;
   int warm_start;             // FLASH_WS_*
+  int reuse;                  // reuse capacitance factorisations across Newton iterations
 
   const int* voff;            // [n_envs+1]
   const int* toff;            // [n_envs+1]
@@ -77,17 +78,20 @@ struct DevBatch {
   T* cd0;
   T* cdob;                    // [2 per contact] T^T dobs
   T* cs;                      // residual scale h^2/m_v
-  T* clam;                    // [3 per contact] multipliers (n, t1, t2)
+  double* clam;               // [3 per contact] multipliers (n, t1, t2), FP64: the residual scale
+                              // h^2/m_v maps FP32 rounding of lambda to ~1e-7 m
   T* cforce;                  // [3 per contact] world force F lambda
+  void* cyf;                  // [3 per contact] free displacement in the contact frame (solve scratch)
   int* cnew;                  // 1: no warm start available
   double* cd0d;               // FP64 gap (kept for exact reporting)
 
-  // contact-space scratch
-  T* Gc;                      // [cap*cap per env] Gbar restricted to contacts
-  T* Ginv;                    // [cap*cap per env] inverse on the base set
-  T* Cm;                      // [rmax*rmax per env] capacitance matrix
+  // contact-space scratch, in the contact-solve precision (double when csp64, else T)
+  int csp64;                  // 1: the contact-space solve runs in FP64
+  void* Gc;                   // [cap*cap per env] Gbar restricted to contacts
+  void* Ginv;                 // [cap*cap per env] inverse on the base set
+  void* Cm;                   // [rmax*rmax per env] capacitance matrix + row data
   int* base;                  // [cap per env] base-set contact ids (ordered)
-  T* scr;                     // [cap*16 per env] panel scratch of the blocked inverse
+  void* scr;                  // [cap*16 per env] panel scratch of the blocked inverse
   int* nbase;                 // [n_envs]
   int* lust;                  // [4 per env] stored capacitance factorisation: valid, rows, base version x2
 
@@ -98,6 +102,8 @@ struct DevBatch {
 
   // per env outputs
   double* resid;              // [n_envs]
+  double* resid_hist;         // [2 per env] max residual and count of steps above ncp_tol since reset
+  double ncp_tol;             // acceptance tolerance of the end-of-step residual
   int* iters;                 // [n_envs] Newton iterations this step
   int* refac;                 // [n_envs]
   int* flags;                 // [n_envs]

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -313,6 +314,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.tol = b->p.inner_tol > 0 ? b->p.inner_tol : (sizeof(T) == 4 ? 0.25 * b->p.ncp_tol : 1e-12);
   B.max_force = b->p.max_force;
   B.warm_start = b->p.warm_start;
+  B.reuse = getenv("FLASH_CSP_NOREUSE") ? 0 : 1;
   const int NV = b->NV, NT = b->NT;
   const size_t cap = (size_t)B.cap;
 
@@ -414,19 +416,21 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.cd0 = dalloc<T>(ne * cap, own);
   B.cdob = dalloc<T>(2 * ne * cap, own);
   B.cs = dalloc<T>(ne * cap, own);
-  B.clam = dalloc<T>(3 * ne * cap, own);
+  B.clam = dalloc<double>(3 * ne * cap, own);
   B.cforce = dalloc<T>(3 * ne * cap, own);
   B.cnew = dalloc<int>(ne * cap, own);
   B.cd0d = dalloc<double>(ne * cap, own);
-  B.Gc = dalloc<T>(ne * cap * cap, own);
-  B.Ginv = dalloc<T>(ne * cap * cap, own);
+  B.csp64 = (sizeof(T) == 8 || !b->p.contact_fp32) ? 1 : 0;
+  const size_t cts = B.csp64 ? sizeof(double) : sizeof(T);
+  B.Gc = dalloc<unsigned char>(ne * cap * cap * cts, own);
+  B.Ginv = dalloc<unsigned char>(ne * cap * cap * cts, own);
   {
     const size_t rm = (size_t)B.rmax;
-    const size_t tcount = ne * (rm * rm + 16 * rm) + (3 * ne * rm * sizeof(int) + sizeof(T) - 1) / sizeof(T);
-    B.Cm = dalloc<T>(tcount, own);
+    B.Cm = dalloc<unsigned char>(ne * (rm * rm + 16 * rm) * cts + 3 * ne * rm * sizeof(int), own);
   }
   B.base = dalloc<int>(ne * cap, own);
-  B.scr = dalloc<T>(ne * cap * 16, own);
+  B.scr = dalloc<unsigned char>(ne * cap * 16 * cts, own);
+  B.cyf = dalloc<unsigned char>(3 * ne * cap * cts, own);
   B.lust = dalloc<int>(4 * ne, own);
   HIPCHK(hipMemset(B.lust, 0, 4 * ne * sizeof(int)));
   B.nbase = dalloc<int>(ne, own);
@@ -441,6 +445,9 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   }
   B.resid = dalloc<double>(ne, own);
   HIPCHK(hipMemset(B.resid, 0, ne * sizeof(double)));
+  B.resid_hist = dalloc<double>(2 * (size_t)ne, own);
+  HIPCHK(hipMemset(B.resid_hist, 0, 2 * (size_t)ne * sizeof(double)));
+  B.ncp_tol = b->p.ncp_tol;
   B.iters = dalloc<int>(ne, own);
   B.refac = dalloc<int>(ne, own);
   B.flags = dalloc<int>(ne, own);
@@ -518,7 +525,8 @@ int contacts_t(flash_batch* b, int env, flash_contact* out, int capacity, int* n
   if (total > capacity || !out) return total > capacity ? 1 : 0;
   int o = 0;
   std::vector<int> cv(cap), co(cap);
-  std::vector<T> fr(9 * (size_t)cap), lam(3 * (size_t)cap), frc(3 * (size_t)cap);
+  std::vector<T> fr(9 * (size_t)cap), frc(3 * (size_t)cap);
+  std::vector<double> lam(3 * (size_t)cap);
   std::vector<double> d0(cap);
   for (int e = e0; e < e1; ++e) {
     const int c = cnt[e];
@@ -527,7 +535,7 @@ int contacts_t(flash_batch* b, int env, flash_contact* out, int capacity, int* n
     HIPCHK(hipMemcpy(cv.data(), B.cvert + base, c * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(co.data(), B.cobs + base, c * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(fr.data(), B.cframe + 9 * base, 9 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(lam.data(), B.clam + 3 * base, 3 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(lam.data(), B.clam + 3 * base, 3 * (size_t)c * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(frc.data(), B.cforce + 3 * base, 3 * (size_t)c * sizeof(T), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(d0.data(), B.cd0d + base, c * sizeof(double), hipMemcpyDeviceToHost));
     for (int j = 0; j < c; ++j) {
@@ -538,7 +546,7 @@ int contacts_t(flash_batch* b, int env, flash_contact* out, int capacity, int* n
       for (int k = 0; k < 3; ++k) {
         r.normal[k] = (double)fr[9 * j + k];
         r.tangent1[k] = (double)fr[9 * j + 3 + k];
-        r.lambda[k] = (double)lam[3 * j + k];
+        r.lambda[k] = lam[3 * j + k];
         r.impulse[k] = b->p.h * (double)frc[3 * j + k];
       }
       r.gap = d0[j];
@@ -797,6 +805,29 @@ flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launc
   for (int k = 0; k < K_COUNT && k < cap; ++k) {
     if (total_ms) total_ms[k] = b->tot_ms[k];
     if (launches) launches[k] = b->cnt[k];
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* over_out, int32_t reset) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  try {
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int ne = b->n_envs;
+    double* dp = b->fp64 ? b->bd.resid_hist : b->bf.resid_hist;
+    std::vector<double> h(2 * (size_t)ne);
+    HIPCHK(hipMemcpy(h.data(), dp, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double m = 0.0;
+    int64_t over = 0;
+    for (int e = 0; e < ne; ++e) {
+      m = (h[2 * e] > m || !(h[2 * e] == h[2 * e])) ? h[2 * e] : m;
+      over += (int64_t)h[2 * e + 1];
+    }
+    if (max_out) *max_out = m;
+    if (over_out) *over_out = over;
+    if (reset) HIPCHK(hipMemset(dp, 0, h.size() * sizeof(double)));
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
   }
   return FLASH_OK;
 }

@@ -360,18 +360,19 @@ __global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B) {
   }
 }
 
-// Gbar restricted to the contacts of each env: Gc[j][k] = Gbar[v_j][v_k].
-template <class T>
+// Gbar restricted to the contacts of each env: Gc[j][k] = Gbar[v_j][v_k]
+// (stored in the contact-solve precision CT).
+template <class T, class CT>
 __global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
   const int e = blockIdx.x;
   const int c = B.ccount[e];
   const T* G = B.G + B.goff[e];
   const int ld = B.gld[e];
-  T* Gc = B.Gc + (size_t)e * B.cap * B.cap;
+  CT* Gc = static_cast<CT*>(B.Gc) + (size_t)e * B.cap * B.cap;
   const int* cv = B.cvert + (size_t)e * B.cap;
   for (int idx = threadIdx.x; idx < c * c; idx += kBlock) {
     const int j = idx / c, k = idx - j * c;
-    Gc[idx] = G[(size_t)cv[j] * ld + cv[k]];
+    Gc[idx] = (CT)G[(size_t)cv[j] * ld + cv[k]];
   }
 }
 
@@ -396,21 +397,24 @@ __device__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
       P[i * kBK + j] = M[(size_t)(k0 + i) * n + k0 + j];
     }
     __syncthreads();
-    for (int k = 0; k < kb; ++k) {
-      const T piv = P[k * kBK + k];
-      if (tid < kb) {
-        v[tid] = P[tid * kBK + k];
-        v[kBK + tid] = P[k * kBK + tid] / piv;
+    if (tid < 64) {
+      // Gauss-Jordan on the pivot block by one wave (lane l owns rows l, l + 16 ... of column l % 16)
+      for (int k = 0; k < kb; ++k) {
+        const T piv = P[k * kBK + k];
+        const T colv = tid < kb ? P[tid * kBK + k] : T(0);
+        const T rowv = tid < kb ? P[k * kBK + tid] / piv : T(0);
+        __builtin_amdgcn_wave_barrier();
+        for (int idx = tid; idx < kb * kb; idx += 64) {
+          const int i = idx / kb, j = idx - i * kb;
+          const T ci = __shfl(colv, i, 64);
+          const T rj = __shfl(rowv, j, 64);
+          T val;
+          if (i == k) val = (j == k) ? T(1) / piv : rj;
+          else val = (j == k) ? -ci / piv : P[i * kBK + j] - ci * rj;
+          P[i * kBK + j] = val;
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      __syncthreads();
-      for (int idx = tid; idx < kb * kb; idx += kBlock) {
-        const int i = idx / kb, j = idx - i * kb;
-        T val;
-        if (i == k) val = (j == k) ? T(1) / piv : v[kBK + j];
-        else val = (j == k) ? -v[i] / piv : P[i * kBK + j] - v[i] * v[kBK + j];
-        P[i * kBK + j] = val;
-      }
-      __syncthreads();
     }
     for (int idx = tid; idx < n * kb; idx += kBlock) {
       const int i = idx / kb, t = idx - i * kb;
@@ -488,47 +492,41 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
       pan[i * kBK + t] = A[(size_t)(k0 + i) * n + k0 + t];
     }
     __syncthreads();
-    for (int t = 0; t < kb; ++t) {
-      // pivot in panel column t over panel rows t..
-      double best = -1.0;
-      int bi = pr_rows;
-      for (int i = t + tid; i < pr_rows; i += kBlock) {
-        const double a = fabs((double)pan[i * kBK + t]);
-        if (a > best) { best = a; bi = i; }
+    if (tid < 64) {
+      // panel factorisation by one wave: lane l owns panel rows l, l + 64, ...
+      for (int t = 0; t < kb; ++t) {
+        double best = -1.0;
+        int bi = pr_rows;
+        for (int i = t + tid; i < pr_rows; i += 64) {
+          const double a = fabs((double)pan[i * kBK + t]);
+          if (a > best) { best = a; bi = i; }
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+          const double ob = __shfl_xor(best, d, 64);
+          const int oi = __shfl_xor(bi, d, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const int pr = bi < pr_rows ? bi : t;
+        if (tid == 0) piv[k0 + t] = k0 + pr;
+        if (pr != t && tid < kb) {
+          const T t0 = pan[t * kBK + tid];
+          pan[t * kBK + tid] = pan[pr * kBK + tid];
+          pan[pr * kBK + tid] = t0;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const T pv = pan[t * kBK + t];
+        const int w = kb - t - 1;
+        T urow[kBK];
+        for (int q = 0; q < w; ++q) urow[q] = pan[t * kBK + t + 1 + q];
+        for (int i = t + 1 + tid; i < pr_rows; i += 64) {
+          const T l = pv != T(0) ? pan[i * kBK + t] / pv : T(0);
+          pan[i * kBK + t] = l;
+          for (int q = 0; q < w; ++q) pan[i * kBK + t + 1 + q] -= l * urow[q];
+        }
+        __builtin_amdgcn_wave_barrier();
       }
-      for (int d = 32; d > 0; d >>= 1) {
-        const double ob = __shfl_xor(best, d, 64);
-        const int oi = __shfl_xor(bi, d, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-      }
-      if (lane_id() == 0) { sh_red[wave_id()] = best; sh_i[wave_id()] = bi; }
-      __syncthreads();
-      if (tid == 0) {
-        double bb = sh_red[0];
-        int ii = sh_i[0];
-        for (int w = 1; w < kBlock / 64; ++w)
-          if (sh_red[w] > bb || (sh_red[w] == bb && sh_i[w] < ii)) { bb = sh_red[w]; ii = sh_i[w]; }
-        ii = ii < pr_rows ? ii : t;
-        *sh_piv = ii;
-        piv[k0 + t] = k0 + ii;
-      }
-      __syncthreads();
-      const int pr = *sh_piv;
-      if (pr != t && tid < kb) {
-        const T t0 = pan[t * kBK + tid];
-        pan[t * kBK + tid] = pan[pr * kBK + tid];
-        pan[pr * kBK + tid] = t0;
-      }
-      __syncthreads();
-      const T pv = pan[t * kBK + t];
-      const int w = kb - t - 1;
-      for (int i = t + 1 + tid; i < pr_rows; i += kBlock) {
-        const T l = pv != T(0) ? pan[i * kBK + t] / pv : T(0);
-        pan[i * kBK + t] = l;
-        for (int q = 0; q < w; ++q) pan[i * kBK + t + 1 + q] -= l * pan[t * kBK + t + 1 + q];
-      }
-      __syncthreads();
     }
+    __syncthreads();
     // write the factored panel back; apply the block's row swaps to the other columns
     for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
       const int i = idx / kb, t = idx - i * kb;
@@ -668,7 +666,8 @@ __device__ void wg_lu_apply(const T* A, int n, const int* piv, T* r, T* ys, T* D
 // ---------------------------------------------------------------------------
 template <class T>
 struct CspSmem {
-  T *lam, *Y, *yf, *dl, *Wd, *rv, *x0, *fw;   // [3*cap]
+  double* lam;                                 // [3*cap] multipliers, FP64
+  T *Y, *dl, *Wd, *rv, *x0, *fw, *ph, *tmp;    // [3*cap]
   T *sp, *kap, *yh0, *yh1;                    // [cap]
   T *pan, *ys;                                // [rmax*kBK], [rmax]
   int *cls, *pos, *bas;                       // [cap]
@@ -676,7 +675,7 @@ struct CspSmem {
 
 template <class T>
 __host__ __device__ size_t csp_smem_bytes(int cap, int rmax) {
-  return (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 1) * sizeof(T) +
+  return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 1) * sizeof(T) +
          (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
 }
 
@@ -698,18 +697,20 @@ __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y
   }
 }
 
-template <class T>
+template <class T, class CT>
 __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int e = blockIdx.x;
   const int c = B.ccount[e];
   if (c == 0) return;
   const int cap = B.cap;
-  CspSmem<T> S;
+  CspSmem<CT> S;
   {
-    T* p = reinterpret_cast<T*>(smem_raw);
-    S.lam = p; p += 3 * cap; S.Y = p; p += 3 * cap; S.yf = p; p += 3 * cap; S.dl = p; p += 3 * cap;
+    S.lam = reinterpret_cast<double*>(smem_raw);
+    CT* p = reinterpret_cast<CT*>(S.lam + 3 * cap);
+    S.Y = p; p += 3 * cap; S.dl = p; p += 3 * cap;
     S.Wd = p; p += 3 * cap; S.rv = p; p += 3 * cap; S.x0 = p; p += 3 * cap; S.fw = p; p += 3 * cap;
+    S.ph = p; p += 3 * cap; S.tmp = p; p += 3 * cap;
     S.sp = p; p += cap; S.kap = p; p += cap; S.yh0 = p; p += cap; S.yh1 = p; p += cap;
     S.pan = p; p += (size_t)B.rmax * kBK; S.ys = p; p += B.rmax;
     int* ip = reinterpret_cast<int*>(p);
@@ -718,18 +719,19 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   __shared__ double sh_red[kBlock / 64];
   __shared__ int sh_i[kBlock / 64];
   __shared__ int sh_nb, sh_nR, sh_piv;
-  __shared__ T sh_blk[kBK * kBK];
-  __shared__ T sh_vv[2 * kBK];
+  __shared__ CT sh_blk[kBK * kBK];
+  __shared__ CT sh_vv[2 * kBK];
 
   const size_t cb = (size_t)e * cap;
-  const T* Gc = B.Gc + cb * cap;           // ld c
-  T* Ginv = B.Ginv + cb * cap;             // ld nb
-  T* Cm = B.Cm + (size_t)e * B.rmax * B.rmax;
+  const CT* Gc = static_cast<const CT*>(B.Gc) + cb * cap;   // ld c
+  CT* Ginv = static_cast<CT*>(B.Ginv) + cb * cap;            // ld nb
+  CT* Cm = static_cast<CT*>(B.Cm) + (size_t)e * B.rmax * B.rmax;
   const int v0 = B.voff[e];
-  const T hh = (T)(B.h * B.h), ihh = T(1) / hh;
-  const T mu = mu_env[e];
-  const T maxf = (T)B.max_force;
+  const CT hh = (CT)(B.h * B.h), ihh = CT(1) / hh;
+  const CT mu = mu_env[e];
+  const double dmaxf = B.max_force;
   const T* Fr = B.cframe + 9 * cb;
+  CT* yfg = static_cast<CT*>(B.cyf) + 3 * cb;     // free displacement y_free in contact frames
   const int tid = threadIdx.x;
   // per-phase wall-clock accounting (thread 0, when enabled)
   unsigned long long t_mark = (B.phase && tid == 0) ? wall_clock64() : 0ull;
@@ -743,8 +745,8 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
 
   // per-R-row data in global scratch (after the rmax*rmax matrices):
   // vR(3) uR(3) rhs y Krow(3) Erow(3) -- 16 values per row
-  T* Rv = B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 16;
-  int* Rj = reinterpret_cast<int*>(B.Cm + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 16) +
+  CT* Rv = static_cast<CT*>(B.Cm) + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 16;
+  int* Rj = reinterpret_cast<int*>(static_cast<CT*>(B.Cm) + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 16) +
             (size_t)e * B.rmax * 3;
   int* RjF = Rj + B.rmax;      // row list of the stored factorisation
   int* piv = Rj + 2 * B.rmax;  // its pivots
@@ -758,9 +760,9 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     S.pos[j] = -1;
     const T* F = Fr + 9 * j;
     const int vi = v0 + B.cvert[cb + j];
-    T zw0 = B.z[vi], zw1 = B.z[B.NV + vi], zw2 = B.z[2 * B.NV + vi];
+    CT zw0 = B.z[vi], zw1 = B.z[B.NV + vi], zw2 = B.z[2 * B.NV + vi];
     for (int a = 0; a < 3; ++a) {
-      S.yf[3 * j + a] = F[3 * a] * zw0 + F[3 * a + 1] * zw1 + F[3 * a + 2] * zw2;
+      yfg[3 * j + a] = F[3 * a] * zw0 + F[3 * a + 1] * zw1 + F[3 * a + 2] * zw2;
       S.lam[3 * j + a] = B.clam[3 * (cb + j) + a];
     }
     S.sp[j] = hh * Gc[(size_t)j * c + j];
@@ -774,17 +776,17 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   __syncthreads();
 
   // Y = y_free + W lambda (fw = F lambda world; Gc symmetric -> coalesced column reads)
-  auto apply_W = [&](const T* vin, T* vout) {
+  auto apply_W = [&](const auto* vin, CT* vout) {
     for (int j = tid; j < c; j += kBlock) {
       const T* F = Fr + 9 * j;
-      const T l0 = vin[3 * j], l1 = vin[3 * j + 1], l2 = vin[3 * j + 2];
+      const CT l0 = (CT)vin[3 * j], l1 = (CT)vin[3 * j + 1], l2 = (CT)vin[3 * j + 2];
       for (int k = 0; k < 3; ++k) S.fw[3 * j + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
     }
     __syncthreads();
     for (int j = tid; j < c; j += kBlock) {
-      T d0 = 0, d1 = 0, d2 = 0;
+      CT d0 = 0, d1 = 0, d2 = 0;
       for (int k = 0; k < c; ++k) {
-        const T g = Gc[(size_t)k * c + j];
+        const CT g = Gc[(size_t)k * c + j];
         d0 += g * S.fw[3 * k]; d1 += g * S.fw[3 * k + 1]; d2 += g * S.fw[3 * k + 2];
       }
       const T* F = Fr + 9 * j;
@@ -795,15 +797,15 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
 
   apply_W(S.lam, S.Y);
   for (int j = tid; j < c; j += kBlock)
-    for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+    for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
   __syncthreads();
   if (first_lg) {
     // contacts without a warm start: Jacobi estimate of lambda_n
     int any = 0;
     for (int j = tid; j < c; j += kBlock) {
       if (B.cnew[cb + j]) {
-        const T cn = B.cd0[cb + j] + S.Y[3 * j];
-        S.lam[3 * j] = cn < T(0) ? -cn / S.sp[j] : T(0);
+        const CT cn = B.cd0[cb + j] + S.Y[3 * j];
+        S.lam[3 * j] = cn < CT(0) ? (double)(-cn / S.sp[j]) : 0.0;
         S.lam[3 * j + 1] = 0;
         S.lam[3 * j + 2] = 0;
         any = 1;
@@ -812,7 +814,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     if (block_max((double)any, sh_red) > 0) {
       apply_W(S.lam, S.Y);
       for (int j = tid; j < c; j += kBlock)
-        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
       __syncthreads();
     }
   }
@@ -825,17 +827,18 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     // ---- Phi (inner scale), classification, residual (residual scale, FP64) ----
     double rloc = 0.0, psil = 0.0;
     for (int j = tid; j < c; j += kBlock) {
-      const T sp = S.sp[j];
-      const T l0 = S.lam[3 * j], l1 = S.lam[3 * j + 1], l2 = S.lam[3 * j + 2];
-      const T cn = B.cd0[cb + j] + S.Y[3 * j];
-      const T ut1 = S.Y[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = S.Y[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-      const T phn = fmin(cn, sp * l0);
-      const T y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
-      const T rho = mu * fmax(l0, T(0));
-      const T ny = sqrt(y1 * y1 + y2 * y2);
+      const CT sp = S.sp[j];
+      const double ld0 = S.lam[3 * j], ld1 = S.lam[3 * j + 1], ld2 = S.lam[3 * j + 2];
+      const CT l0 = (CT)ld0, l1 = (CT)ld1, l2 = (CT)ld2;
+      const CT cn = B.cd0[cb + j] + S.Y[3 * j];
+      const CT ut1 = S.Y[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = S.Y[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+      const CT phn = fmin(cn, sp * l0);
+      const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+      const CT rho = mu * fmax(l0, CT(0));
+      const CT ny = sqrt(y1 * y1 + y2 * y2);
       int cls = (cn <= sp * l0) ? 1 : 0;
-      T p1 = y1, p2 = y2, kap = 0, yh0 = 0, yh1 = 0;
-      if (rho > T(0)) {
+      CT p1 = y1, p2 = y2, kap = 0, yh0 = 0, yh1 = 0;
+      if (rho > CT(0)) {
         if (ny <= rho) cls |= 2;
         else {
           cls |= 4;
@@ -843,19 +846,20 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
           p1 = rho * yh0; p2 = rho * yh1;
         }
       } else { p1 = 0; p2 = 0; }
-      const T ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
-      S.rv[3 * j] = phn; S.rv[3 * j + 1] = ph1; S.rv[3 * j + 2] = ph2;
+      const CT ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+      S.ph[3 * j] = phn; S.ph[3 * j + 1] = ph1; S.ph[3 * j + 2] = ph2;
       S.cls[j] = cls; S.kap[j] = kap; S.yh0[j] = yh0; S.yh1[j] = yh1;
       psil += (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
       // residual scale
       const double s = (double)B.cs[cb + j];
-      const double pn = fmin((double)cn, s * (double)l0);
-      const double z1 = (double)l1 - (double)ut1 / s, z2 = (double)l2 - (double)ut2 / s;
+      const double cnd = B.cd0d[cb + j] + (double)S.Y[3 * j];
+      const double pn = fmin(cnd, s * ld0);
+      const double z1 = ld1 - (double)ut1 / s, z2 = ld2 - (double)ut2 / s;
       const double nz = sqrt(z1 * z1 + z2 * z2);
-      const double rh = (double)mu * fmax((double)l0, 0.0);
+      const double rh = (double)mu * fmax(ld0, 0.0);
       double q1 = z1, q2 = z2;
       if (nz > rh) { double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
-      const double t1 = s * ((double)l1 - q1), t2 = s * ((double)l2 - q2);
+      const double t1 = s * (ld1 - q1), t2 = s * (ld2 - q2);
       double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
       if (!(rj == rj)) rj = INFINITY;
       rloc = fmax(rloc, rj);
@@ -889,11 +893,11 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       for (int idx = tid; idx < nb * nb; idx += kBlock) {
         const int p = idx / nb, q = idx - p * nb;
         const int jp = S.bas[p], jq = S.bas[q];
-        T g = Gc[(size_t)jp * c + jq];
-        if (p == q && p > 0 && B.cvert[cb + jp] == B.cvert[cb + S.bas[p - 1]]) g *= T(1.0001);
+        CT g = Gc[(size_t)jp * c + jq];
+        if (p == q && p > 0 && B.cvert[cb + jp] == B.cvert[cb + S.bas[p - 1]]) g *= CT(1.0001);
         Ginv[idx] = g;
       }
-      wg_spd_inverse(Ginv, nb, B.scr + cb * kBK, sh_blk, sh_vv);
+      wg_spd_inverse(Ginv, nb, static_cast<CT*>(B.scr) + cb * kBK, sh_blk, sh_vv);
       if (tid == 0) lust[3] += 1;
       __syncthreads();
       ++nref;
@@ -903,8 +907,8 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     // ---- decoupled contacts (outside the base): local rows E = sp I ----
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) {
-        const T isp = T(1) / S.sp[j];
-        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = -S.rv[3 * j + a] * isp;
+        const CT isp = CT(1) / S.sp[j];
+        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = -S.ph[3 * j + a] * isp;
       } else {
         for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = 0;
       }
@@ -914,30 +918,11 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     // rhs on base rows: r = -Phi - K (W dl_D)
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) continue;
-      T K[3][3], E[3][3];
+      CT K[3][3], E[3][3];
       contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
-      T w0 = S.Wd[3 * j], w1 = S.Wd[3 * j + 1], w2 = S.Wd[3 * j + 2];
+      CT w0 = S.Wd[3 * j], w1 = S.Wd[3 * j + 1], w2 = S.Wd[3 * j + 2];
       for (int a = 0; a < 3; ++a)
-        S.rv[3 * j + a] = -S.rv[3 * j + a] - (K[a][0] * w0 + K[a][1] * w1 + K[a][2] * w2);
-    }
-    __syncthreads();
-    // x0 = W_base^-1 r : g = F r (world), w = Ginv g, x0 = h^-2 F^T w
-    for (int p = tid; p < nb; p += kBlock) {
-      const int j = S.bas[p];
-      const T* F = Fr + 9 * j;
-      const T r0 = S.rv[3 * j], r1 = S.rv[3 * j + 1], r2 = S.rv[3 * j + 2];
-      for (int k = 0; k < 3; ++k) S.fw[3 * p + k] = F[k] * r0 + F[3 + k] * r1 + F[6 + k] * r2;
-    }
-    __syncthreads();
-    for (int p = tid; p < nb; p += kBlock) {
-      T w0 = 0, w1 = 0, w2 = 0;
-      for (int q = 0; q < nb; ++q) {
-        const T g = Ginv[(size_t)q * nb + p];
-        w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
-      }
-      const int j = S.bas[p];
-      const T* F = Fr + 9 * j;
-      for (int a = 0; a < 3; ++a) S.x0[3 * j + a] = ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+        S.rv[3 * j + a] = -S.ph[3 * j + a] - (K[a][0] * w0 + K[a][1] * w1 + K[a][2] * w2);
     }
     __syncthreads();
 
@@ -977,20 +962,20 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     if (nR > 0) {
       // reuse the stored factorisation when its row set and base are unchanged
       int diff = 0;
-      if (lust[0] && lust[1] == nR && lust[2] == lust[3]) {
+      if (B.reuse && lust[0] && lust[1] == nR && lust[2] == lust[3]) {
         for (int q = tid; q < nR; q += kBlock) diff |= Rj[q] != RjF[q];
       } else {
         diff = 1;
       }
       reused = block_max((double)diff, sh_red) == 0.0;
       if (!reused) {
-        // per-row vectors: vR = F E^T[:, a] (world), uR = F[:, a], K and E rows (contact frame)
+        // per-row vectors: vR = F E^CT[:, a] (world), uR = F[:, a], K and E rows (contact frame)
         for (int q = tid; q < nR; q += kBlock) {
           const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
-          T K[3][3], E[3][3];
+          CT K[3][3], E[3][3];
           contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
           const T* F = Fr + 9 * j;
-          T* rv = Rv + 16 * q;
+          CT* rv = Rv + 16 * q;
           for (int k = 0; k < 3; ++k) {
             rv[k] = E[a][0] * F[k] + E[a][1] * F[3 + k] + E[a][2] * F[6 + k];
             rv[3 + k] = F[3 * a + k];
@@ -1005,9 +990,9 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
           const int q = idx / nR, s2 = idx - q * nR;
           const int jaq = Rj[q], jas = Rj[s2];
           const int jq = jaq / 3, js = jas / 3, as = jas - 3 * js;
-          const T* vq = Rv + 16 * q;
-          const T* us = Rv + 16 * s2 + 3;
-          T v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
+          const CT* vq = Rv + 16 * q;
+          const CT* us = Rv + 16 * s2 + 3;
+          CT v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
           if (jq == js) v += vq[8 + as];
           Cm[idx] = v;
         }
@@ -1018,78 +1003,123 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       } else if (tid == 0) {
         ++nreuse;
       }
-      // rhs of the capacitance system from the stored K and E rows
-      for (int q = tid; q < nR; q += kBlock) {
-        const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
-        T* rv = Rv + 16 * q;
-        T rr = -S.rv[3 * j + a];
-        for (int b = 0; b < 3; ++b) rr += rv[8 + b] * S.rv[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
-        rv[6] = rr;
-      }
-      wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
-      mark(5);
-      // dl_base = x0 - h^-2 F^T sum_s Ginv[ps][p] (uR_s y_s)
+    }
+
+    // Woodbury solve on the base rows with the stored factorisation:
+    // dout_B = W_B^-1 rin - W_B^-1 U C^-1 (K_R rin - rin_R + E_R W_B^-1 rin)
+    auto wsolve = [&](const CT* rin, CT* dout) {
       for (int p = tid; p < nb; p += kBlock) {
-        T w0 = 0, w1 = 0, w2 = 0;
-        for (int s = 0; s < nR; ++s) {
-          const int js = Rj[s] / 3;
-          const T g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[16 * s + 7];
-          const T* us = Rv + 16 * s + 3;
-          w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
+        const int j = S.bas[p];
+        const T* F = Fr + 9 * j;
+        const CT r0 = rin[3 * j], r1 = rin[3 * j + 1], r2 = rin[3 * j + 2];
+        for (int k = 0; k < 3; ++k) S.fw[3 * p + k] = F[k] * r0 + F[3 + k] * r1 + F[6 + k] * r2;
+      }
+      __syncthreads();
+      for (int p = tid; p < nb; p += kBlock) {
+        CT w0 = 0, w1 = 0, w2 = 0;
+        for (int q = 0; q < nb; ++q) {
+          const CT g = Ginv[(size_t)q * nb + p];
+          w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
         }
         const int j = S.bas[p];
         const T* F = Fr + 9 * j;
-        for (int a = 0; a < 3; ++a)
-          S.dl[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+        for (int a = 0; a < 3; ++a) S.x0[3 * j + a] = ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
       }
-    } else {
-      for (int p = tid; p < nb; p += kBlock) {
-        const int j = S.bas[p];
-        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = S.x0[3 * j + a];
+      __syncthreads();
+      if (nR > 0) {
+        for (int q = tid; q < nR; q += kBlock) {
+          const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
+          CT* rv = Rv + 16 * q;
+          CT rr = -rin[3 * j + a];
+          for (int b = 0; b < 3; ++b) rr += rv[8 + b] * rin[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
+          rv[6] = rr;
+        }
+        wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
+        for (int p = tid; p < nb; p += kBlock) {
+          CT w0 = 0, w1 = 0, w2 = 0;
+          for (int s = 0; s < nR; ++s) {
+            const int js = Rj[s] / 3;
+            const CT g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[16 * s + 7];
+            const CT* us = Rv + 16 * s + 3;
+            w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
+          }
+          const int j = S.bas[p];
+          const T* F = Fr + 9 * j;
+          for (int a = 0; a < 3; ++a)
+            dout[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+        }
+      } else {
+        for (int p = tid; p < nb; p += kBlock) {
+          const int j = S.bas[p];
+          for (int a = 0; a < 3; ++a) dout[3 * j + a] = S.x0[3 * j + a];
+        }
       }
+      __syncthreads();
+    };
+    wsolve(S.rv, S.dl);
+    mark(5);
+    // one step of iterative refinement against the current Jacobian (exact W products):
+    // res_B = -Phi_B - K (W dl) - E dl_B ; dl_B += Z^-1 res_B
+    apply_W(S.dl, S.Wd);
+    for (int j = tid; j < c; j += kBlock) {
+      if (S.pos[j] < 0) continue;
+      CT K[3][3], E[3][3];
+      contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
+      const CT w0 = S.Wd[3 * j], w1 = S.Wd[3 * j + 1], w2 = S.Wd[3 * j + 2];
+      const CT d0 = S.dl[3 * j], d1 = S.dl[3 * j + 1], d2 = S.dl[3 * j + 2];
+      for (int a = 0; a < 3; ++a)
+        S.rv[3 * j + a] = -S.ph[3 * j + a] - (K[a][0] * w0 + K[a][1] * w1 + K[a][2] * w2) -
+                          (E[a][0] * d0 + E[a][1] * d1 + E[a][2] * d2);
     }
     __syncthreads();
-    // undo the decoupled part's effect: Wd currently = W dl_D; recompute W dl (all)
+    wsolve(S.rv, S.tmp);
+    for (int p = tid; p < nb; p += kBlock) {
+      const int j = S.bas[p];
+      for (int a = 0; a < 3; ++a) S.dl[3 * j + a] += S.tmp[3 * j + a];
+    }
+    __syncthreads();
     apply_W(S.dl, S.Wd);
 
     mark(6);
     // ---- backtracking line search on 1/2 |Phi|^2 (inner scale) ----
-    T alpha = 1;
+    CT alpha = 1;
     bool ok = false;
+    double psit = psi;
     for (int ls = 0; ls < 30; ++ls) {
       double pl = 0.0;
       for (int j = tid; j < c; j += kBlock) {
-        const T sp = S.sp[j];
-        const T l0 = fmin(fmax(S.lam[3 * j] + alpha * S.dl[3 * j], -maxf), maxf);
-        const T l1 = fmin(fmax(S.lam[3 * j + 1] + alpha * S.dl[3 * j + 1], -maxf), maxf);
-        const T l2 = fmin(fmax(S.lam[3 * j + 2] + alpha * S.dl[3 * j + 2], -maxf), maxf);
-        const T cn = B.cd0[cb + j] + S.Y[3 * j] + alpha * S.Wd[3 * j];
-        const T ut1 = S.Y[3 * j + 1] + alpha * S.Wd[3 * j + 1] - B.cdob[2 * (cb + j)];
-        const T ut2 = S.Y[3 * j + 2] + alpha * S.Wd[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-        const T phn = fmin(cn, sp * l0);
-        const T y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
-        const T rho = mu * fmax(l0, T(0));
-        const T ny = sqrt(y1 * y1 + y2 * y2);
-        T p1 = 0, p2 = 0;
-        if (rho > T(0)) {
+        const CT sp = S.sp[j];
+        const CT l0 = (CT)fmin(fmax(S.lam[3 * j] + (double)(alpha * S.dl[3 * j]), -dmaxf), dmaxf);
+        const CT l1 = (CT)fmin(fmax(S.lam[3 * j + 1] + (double)(alpha * S.dl[3 * j + 1]), -dmaxf), dmaxf);
+        const CT l2 = (CT)fmin(fmax(S.lam[3 * j + 2] + (double)(alpha * S.dl[3 * j + 2]), -dmaxf), dmaxf);
+        const CT cn = B.cd0[cb + j] + S.Y[3 * j] + alpha * S.Wd[3 * j];
+        const CT ut1 = S.Y[3 * j + 1] + alpha * S.Wd[3 * j + 1] - B.cdob[2 * (cb + j)];
+        const CT ut2 = S.Y[3 * j + 2] + alpha * S.Wd[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+        const CT phn = fmin(cn, sp * l0);
+        const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+        const CT rho = mu * fmax(l0, CT(0));
+        const CT ny = sqrt(y1 * y1 + y2 * y2);
+        CT p1 = 0, p2 = 0;
+        if (rho > CT(0)) {
           if (ny <= rho) { p1 = y1; p2 = y2; }
           else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
         }
-        const T ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+        const CT ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
         pl += (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
       }
-      const double psit = 0.5 * block_sum(pl, sh_red);
+      psit = 0.5 * block_sum(pl, sh_red);
       if (psit <= (1.0 - 2e-4 * (double)alpha) * psi) { ok = true; break; }
-      alpha *= T(0.5);
+      alpha *= CT(0.5);
     }
-    if (!ok) alpha = alpha * T(2);   // smallest tried step: keep moving
+    if (!ok) alpha = alpha * CT(2);   // smallest tried step: keep moving
     if (tid == 0) {
       if (!ok) ++nlsfail;
-      if (reused && (!ok || alpha < T(1))) lust[0] = 0;   // frozen rows too far off: refactor next
+      // a chord step on frozen capacitance rows must at least halve |Phi|; otherwise refactor next
+      if (reused && (!ok || alpha < CT(1))) lust[0] = 0;
     }
     for (int j = tid; j < c; j += kBlock)
       for (int a = 0; a < 3; ++a) {
-        S.lam[3 * j + a] = fmin(fmax(S.lam[3 * j + a] + alpha * S.dl[3 * j + a], -maxf), maxf);
+        S.lam[3 * j + a] = fmin(fmax(S.lam[3 * j + a] + (double)(alpha * S.dl[3 * j + a]), -dmaxf), dmaxf);
         S.Y[3 * j + a] += alpha * S.Wd[3 * j + a];
       }
     __syncthreads();
@@ -1097,7 +1127,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     if ((it & 7) == 7) {   // refresh Y from lambda to stop drift
       apply_W(S.lam, S.Y);
       for (int j = tid; j < c; j += kBlock)
-        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += S.yf[3 * j + a];
+        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
       __syncthreads();
     }
   }
@@ -1105,9 +1135,9 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   // ---- write back ----
   for (int j = tid; j < c; j += kBlock) {
     const T* F = Fr + 9 * j;
-    const T l0 = S.lam[3 * j], l1 = S.lam[3 * j + 1], l2 = S.lam[3 * j + 2];
+    const CT l0 = (CT)S.lam[3 * j], l1 = (CT)S.lam[3 * j + 1], l2 = (CT)S.lam[3 * j + 2];
     for (int a = 0; a < 3; ++a) B.clam[3 * (cb + j) + a] = S.lam[3 * j + a];
-    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
+    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
   }
   for (int p = tid; p < nb; p += kBlock) B.base[cb + p] = S.bas[p];
   if (tid == 0) {
@@ -1127,7 +1157,8 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
 // ---------------------------------------------------------------------------
 template <class T>
 void launch_gather(const DevBatch<T>& B, hipStream_t s) {
-  hipLaunchKernelGGL(k_gather<T>, dim3(B.n_envs), dim3(kBlock), 0, s, B);
+  if (B.csp64) hipLaunchKernelGGL((k_gather<T, double>), dim3(B.n_envs), dim3(kBlock), 0, s, B);
+  else hipLaunchKernelGGL((k_gather<T, T>), dim3(B.n_envs), dim3(kBlock), 0, s, B);
 }
 template <class T>
 void launch_project(const DevBatch<T>& B, hipStream_t s) {
@@ -1149,14 +1180,21 @@ void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s) {
 }
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
-  size_t sm = csp_smem_bytes<T>(B.cap, B.rmax);
-  hipLaunchKernelGGL(k_csp<T>, dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+  if (B.csp64) {
+    size_t sm = csp_smem_bytes<double>(B.cap, B.rmax);
+    hipLaunchKernelGGL((k_csp<T, double>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+  } else {
+    size_t sm = csp_smem_bytes<T>(B.cap, B.rmax);
+    hipLaunchKernelGGL((k_csp<T, T>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+  }
 }
 
 template <class T>
 void prepare_csp(int cap, int rmax) {
-  size_t sm = csp_smem_bytes<T>(cap, rmax);
-  hipError_t err = hipFuncSetAttribute((const void*)k_csp<T>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
+  hipError_t err = hipFuncSetAttribute((const void*)k_csp<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)csp_smem_bytes<double>(cap, rmax));
+  err = hipFuncSetAttribute((const void*)k_csp<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)csp_smem_bytes<T>(cap, rmax));
   (void)err;
 }
 

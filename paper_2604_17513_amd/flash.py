@@ -33,7 +33,7 @@ MAX_OBSTACLES = 4
 EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
-    "flash_contacts", "flash_residual", "flash_stats", "flash_set_kernel_timing",
+    "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_ws_load", "flash_last_error",
     "flash_version",
 ]
@@ -55,7 +55,8 @@ class flash_params(C.Structure):
     _fields_ = [("h", C.c_double), ("gravity", C.c_double * 3), ("lg_iterations", C.c_int32),
                 ("max_inner_iterations", C.c_int32), ("ncp_tol", C.c_double), ("contact_margin", C.c_double),
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
-                ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double)]
+                ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
+                ("contact_fp32", C.c_int32), ("reserved_params", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -98,6 +99,7 @@ def lib():
         L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
         L.flash_residual.argtypes = [P, D, D, C.POINTER(I32)]
         L.flash_stats.argtypes = [P, C.POINTER(flash_env_stats)]
+        L.flash_residual_history.argtypes = [P, D, C.POINTER(C.c_int64), I32]
         L.flash_set_kernel_timing.argtypes = [P, I32]
         L.flash_kernel_times.argtypes = [P, D, C.POINTER(C.c_int64), I32, C.POINTER(I32)]
         L.flash_kernel_name.argtypes = [I32]
@@ -278,6 +280,13 @@ class Batch:
         st = lib().flash_residual(self._h, _dptr(per), C.byref(mx), its.ctypes.data_as(C.POINTER(C.c_int32)))
         _check(st, allow=(FLASH_ERR_NOT_CONVERGED, FLASH_ERR_NONFINITE))
         return per, mx.value, its, st
+
+    def residual_history(self, reset: bool = True):
+        """(worst residual, number of env-steps above ncp_tol) since the last reset."""
+        mx = C.c_double()
+        over = C.c_int64()
+        _check(lib().flash_residual_history(self._h, C.byref(mx), C.byref(over), 1 if reset else 0))
+        return mx.value, over.value
 
     def stats(self):
         arr = (flash_env_stats * self.n_envs)()
