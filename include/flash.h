@@ -133,7 +133,9 @@ typedef struct {
   int32_t contacts;
   int32_t fp64_polar;             /* tets routed to the FP64 polar decomposition */
   int32_t flags;                  /* bit 0: non-finite state, bit 1: not converged, bit 2: capacity */
-  int32_t reserved;
+  int32_t ws_state;               /* learned warm start: bit 0 the step's first contact solve started
+                                     from the network's prediction; bit 1 the prediction is disabled for
+                                     this env (a solve started from it hit the iteration cap) */
   double residual;                /* NCP residual at the end of the step, m (FP64) */
 } flash_env_stats;
 
@@ -203,13 +205,92 @@ const char *flash_kernel_name(int32_t i);
  * (then reset).  ms_out holds 12 doubles. */
 flash_status flash_phase_times(flash_batch *b, double *ms_out);
 
-/* Learned warm start: a 16 -> 128 -> 128 -> 128 -> 3 ReLU MLP predicts the
- * initial multipliers of each contact from local features; BF16 weights,
- * FP32 accumulation.  weights_bf16 holds W1,b1,W2,b2,W3,b3,W4,b4 row-major
- * (out x in), n_params = 35587.  The feature scaling vectors (16 means and
- * 16 inverse scales) and the label scale come in norm[33]. */
+/* ---------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method, whose contact solve
+ * starts from the previous iterate).  A 16 -> 128 -> 128 -> 128 -> 3 ReLU MLP
+ * maps features of each contact at the step start to a prediction of its
+ * converged multipliers.  Every GEMM of inference and training rounds its
+ * operands to bfloat16 (nearest even) and accumulates in FP32 on the matrix
+ * cores.  The previous-step warm start stays the fallback and the judge: the
+ * first contact solve of a step starts from the prediction only where its
+ * merit 0.5 |Phi|^2 is lower, and an env whose solve from a prediction hits
+ * the iteration cap goes back to the previous-step start.  Every solve still
+ * runs to the same tolerance, so results agree with the plain method within
+ * that tolerance and only iteration counts change.
+ *
+ * Parameters: W1[128x16] b1[128] W2[128x128] b2[128] W3[128x128] b3[128]
+ * W4[3x128] b4[3], each W row-major (out x in): FLASH_MLP_PARAMS values.
+ * Normalisation norm[FLASH_MLP_NORM]: 16 feature means, 16 feature inverse
+ * scales, 3 label scales.  The network sees (f - mean) * inv_scale and
+ * predicts label * label_scale.
+ * Features per contact (delta_c = contact margin, s = h^2 / m_v):
+ *   d0/delta_c; n.(h v + h^2 g)/delta_c; (h v - obstacle displacement) along
+ *   n, t1, t2 over delta_c; s lambda_prev / delta_c (3, previous-step warm
+ *   start in the new frame); had-previous flag; mu; log10(m_v Gbar_vv);
+ *   log10(m_v / 1 g); contacts on the vertex (1 or 2 of the neighbours in the
+ *   sorted list); (g.n) h^2/delta_c; (obstacle displacement . n)/delta_c; 1.
+ * Label: s (lambda_1 - lambda_prev) / delta_c in the contact frame, where
+ * lambda_1 solves the step's first contact subproblem (first local-global
+ * iteration) and lambda_prev is the previous-step warm start in the features;
+ * the candidate start is lambda_prev + output * delta_c / s on the cone.
+ * ------------------------------------------------------------------------- */
+enum { FLASH_MLP_FEATURES = 16, FLASH_MLP_HIDDEN = 128, FLASH_MLP_OUTPUTS = 3,
+       FLASH_MLP_PARAMS = 35587, FLASH_MLP_NORM = 35 };
+
+/* Loads bf16 weights (host, FLASH_MLP_PARAMS values) and norm (host,
+ * FLASH_MLP_NORM floats) into the batch; they are used when the batch was
+ * created with warm_start = FLASH_WS_LEARNED.  Clears every env's fallback
+ * bit.  A captured step graph is re-captured at the next flash_step. */
 flash_status flash_ws_load(flash_batch *b, const uint16_t *weights_bf16, size_t n_params,
                            const float *norm);
+
+/* Training-pair recording.  on != 0: each step also evaluates the features
+ * of its contacts at the step start (a captured graph is re-captured).
+ * flash_ws_collect, called after a flash_step of one step, appends one row per
+ * contact of that step, env by env in contact order, to the device arrays
+ * feat_dev [capacity x 16] and lab_dev [capacity x 3] starting at row
+ * *n_inout, and advances *n_inout.  FLASH_ERR_CAPACITY (nothing written) if
+ * the rows do not fit; FLASH_ERR_INVALID_ARG if recording is off. */
+flash_status flash_ws_record(flash_batch *b, int32_t on);
+flash_status flash_ws_collect(flash_batch *b, float *feat_dev, float *lab_dev, int64_t capacity,
+                              int64_t *n_inout);
+
+/* Network trainer, independent of batches.  Device-resident FP32 master
+ * weights, Adam moments (beta 0.9 / 0.999, eps 1e-8) and scratch for
+ * max_rows rows.  flash_mlp_create draws He-uniform weights (bound
+ * sqrt(6/fan_in)) and zero biases from splitmix64(seed); hip_stream: a
+ * hipStream_t or NULL for an owned one.  Arrays named *_dev are device
+ * pointers; everything else is host memory.  Deterministic: a fixed seed and
+ * data give bitwise identical weights. */
+typedef struct flash_mlp flash_mlp;
+flash_status flash_mlp_create(int64_t max_rows, uint64_t seed, void *hip_stream, flash_mlp **out);
+flash_status flash_mlp_destroy(flash_mlp *m);
+/* FP32 master parameters (set also resets the Adam state). */
+flash_status flash_mlp_set_params(flash_mlp *m, const float *w, int64_t n);
+flash_status flash_mlp_get_params(flash_mlp *m, float *w, int64_t n);
+/* Parameters rounded to bf16 (nearest even), ready for flash_ws_load. */
+flash_status flash_mlp_get_params_bf16(flash_mlp *m, uint16_t *w, int64_t n);
+flash_status flash_mlp_set_norm(flash_mlp *m, const float *norm);
+flash_status flash_mlp_get_norm(flash_mlp *m, float *norm);
+/* Sets norm from raw data: feature means and 1/std (1 for constant columns,
+ * the bias column passes through as 1), label scales 1/rms. */
+flash_status flash_mlp_fit_norm(flash_mlp *m, const float *feat_dev, const float *lab_dev, int64_t n);
+/* y_dev[n x 3] = network(x_dev[n x 16]) on already-normalised inputs. */
+flash_status flash_mlp_forward(flash_mlp *m, const float *x_dev, int64_t n, float *y_dev);
+/* Mean-squared loss L = sum (network(x) - target)^2 / (3 n) of normalised
+ * inputs and targets (device, n <= max_rows) and its gradient with respect
+ * to every parameter (host grad[FLASH_MLP_PARAMS], *loss may be NULL). */
+flash_status flash_mlp_grad(flash_mlp *m, const float *x_dev, const float *target_dev, int64_t n,
+                            float *grad, float *loss);
+/* Adam on raw (feature, label) rows: per epoch a splitmix64(seed) shuffle,
+ * floor(n / batch) minibatches, normalisation by the trainer's norm.
+ * epoch_loss (host, epochs entries, may be NULL) receives the mean
+ * minibatch loss of each epoch. */
+flash_status flash_mlp_train(flash_mlp *m, const float *feat_dev, const float *lab_dev, int64_t n,
+                             int32_t epochs, int32_t batch, float lr, uint64_t seed, float *epoch_loss);
+/* Mean-squared loss of raw rows under the current weights and norm. */
+flash_status flash_mlp_eval(flash_mlp *m, const float *feat_dev, const float *lab_dev, int64_t n,
+                            float *loss);
 
 const char *flash_last_error(void);
 const char *flash_version(void);

@@ -684,6 +684,8 @@ def step(oe: OracleEnv, x, v, obstacles, params, tol: float = 1e-12, lam_warm=No
         if c:
             csp, Gcols, inv = build_csp(oe, x, qb, contacts, h, params.max_force)
             lam, r, inf = solve_csp(csp, lam, tol=tol)
+            if k == 0:
+                info["lam_first"] = lam.copy()
             info["newton"] += inf["newton"]
             info["pgs"] += inf["pgs"]
             info["fallback"] |= inf["fallback"]

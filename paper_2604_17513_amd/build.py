@@ -15,20 +15,28 @@ SOURCES = {
     "flash_detect.hip": ["-ffp-contract=off"],
     "flash_kernels.hip": [],
     "flash_host.hip": [],
+    "flash_mlp.hip": [],
+    "flash_mlp_host.hip": [],
 }
 
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ, exist_ok=True)
-    objs = []
+    jobs = []
     for src, extra in SOURCES.items():
         obj = os.path.join(OBJ, src.replace(".hip", ".o"))
-        cmd = [hipcc, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
+        jobs.append(([hipcc, *COMMON, *extra, "-c", os.path.join(CSRC, src), "-o", obj], obj))
+
+    def compile_one(job):
         if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+            print(" ".join(job[0]), flush=True)
+        subprocess.run(job[0], check=True)
+        return job[1]
+
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, jobs))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

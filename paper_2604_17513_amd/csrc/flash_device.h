@@ -111,8 +111,10 @@ struct DevBatch {
   unsigned long long* phase;  // [n_envs * 12] contact-solve phase ticks and event counts (nullptr: off)
 
   // learned warm start (optional)
-  const uint16_t* mlp_w;      // bf16 weights (nullptr: off)
-  const float* mlp_norm;      // [33]
+  const double* lam_ml;       // [3 per contact] predicted multipliers (nullptr: off)
+  int ws_mode;                // candidate / judge variant of the learned start
+  int* ws_state;              // [n_envs] bit 0: this step started from the prediction,
+                              //          bit 1: prediction disabled (a solve started from it hit the cap)
 };
 
 }  // namespace flash

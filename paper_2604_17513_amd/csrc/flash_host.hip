@@ -14,32 +14,25 @@
 #include <vector>
 
 #include "../../include/flash.h"
+#include "flash_common.h"
 #include "flash_device.h"
 #include "flash_launch.h"
+#include "flash_mlp.h"
 
 using namespace flash;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-struct FlashError : std::runtime_error {
-  flash_status st;
-  FlashError(flash_status s, const std::string& m) : std::runtime_error(m), st(s) {}
-};
-
-#define HIPCHK(x)                                                                         \
-  do {                                                                                    \
-    hipError_t _e = (x);                                                                  \
-    if (_e != hipSuccess)                                                                 \
-      throw FlashError(_e == hipErrorOutOfMemory ? FLASH_ERR_OUT_OF_MEMORY : FLASH_ERR_DEVICE, \
-                       std::string(#x) + ": " + hipGetErrorString(_e));                   \
-  } while (0)
-
-flash_status fail(flash_status s, const std::string& m) {
+flash_status flash::record_error(flash_status s, const std::string& m) {
   g_err = m;
   return s;
 }
+
+namespace {
+
+flash_status fail(flash_status s, const std::string& m) { return record_error(s, m); }
 
 // ----------------------------------------------------------------------------
 // Create-time precompute (FP64, host).  Per env: oriented elements, D_m^-1,
@@ -213,6 +206,11 @@ struct flash_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int device = 0;
+  // learned warm start: network weights, per-slot inference buffers, training-pair recording
+  bool ws_loaded = false, ws_record = false;
+  MlpBuffers mlp{};
+  float* ws_lab = nullptr;
+  int* ws_coff = nullptr;
 
   ~flash_batch() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -258,16 +256,47 @@ struct flash_batch {
   void enqueue_step(const DevBatch<T>& B) {
     const T* mu_d = static_cast<const T*>(mu_dev);
     launch(K_DETECT, [&] { launch_detect<T>(B, mu_d, stream); });
+    const bool infer = ws_loaded && p.warm_start == FLASH_WS_LEARNED;
+    if (infer || ws_record) {
+      launch(K_MLP, [&] {
+        launch_ws_features<T>(B, mu_d, mlp.feat, stream);
+        if (infer) launch_ws_infer<T>(B, mu_d, mlp, stream);
+      });
+    }
     launch(K_GATHER, [&] { launch_gather<T>(B, stream); });
     for (int k = 0; k < p.lg_iterations; ++k) {
       launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
       launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });
       launch(K_APPLY, [&] { launch_apply<T>(B, max_ld, stream); });
       launch(K_CSP, [&] { launch_csp<T>(B, mu_d, k == 0 ? 1 : 0, stream); });
+      if (k == 0 && ws_record) launch(K_MLP, [&] { launch_ws_labels<T>(B, mlp.feat, ws_lab, stream); });
       launch(K_CORRECT, [&] { launch_correct<T>(B, max_ld, stream); });
     }
     launch(K_FINALIZE, [&] { launch_finalize<T>(B, mu_d, stream); });
     HIPCHK(hipGetLastError());
+  }
+
+  void drop_graph() {
+    if (gexec) { (void)hipGraphExecDestroy(gexec); gexec = nullptr; }
+    if (graph) { (void)hipGraphDestroy(graph); graph = nullptr; }
+  }
+
+  // per-slot buffers of the learned warm start (allocated on first use)
+  void ensure_ws_buffers() {
+    if (mlp.feat) return;
+    const size_t rows = (size_t)n_envs * (size_t)(fp64 ? bd.cap : bf.cap);
+    mlp.W = dalloc<float>(MlpLayout::total, owned);
+    mlp.norm = dalloc<float>(kNorm, owned);
+    mlp.feat = dalloc<float>(rows * kFeat, owned);
+    mlp.X = dalloc<float>(rows * kFeat, owned);
+    mlp.H1 = dalloc<float>(rows * kHidden, owned);
+    mlp.H2 = dalloc<float>(rows * kHidden, owned);
+    mlp.H3 = dalloc<float>(rows * kHidden, owned);
+    mlp.Y = dalloc<float>(rows * kOut, owned);
+    mlp.lam_ml = dalloc<double>(rows * 3, owned);
+    ws_lab = dalloc<float>(rows * kOut, owned);
+    ws_coff = dalloc<int>((size_t)n_envs + 1, owned);
+    HIPCHK(hipMemset(mlp.feat, 0, rows * kFeat * sizeof(float)));
   }
 
   void step(int n) {
@@ -458,8 +487,10 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   HIPCHK(hipMemset(B.fp64_polar, 0, ne * sizeof(int)));
   B.phase = dalloc<unsigned long long>((size_t)ne * 12, own);
   HIPCHK(hipMemset(B.phase, 0, (size_t)ne * 12 * sizeof(unsigned long long)));
-  B.mlp_w = nullptr;
-  B.mlp_norm = nullptr;
+  B.lam_ml = nullptr;
+  B.ws_mode = getenv("FLASH_WS_MODE") ? atoi(getenv("FLASH_WS_MODE")) : 0;
+  B.ws_state = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.ws_state, 0, ne * sizeof(int)));
   std::vector<T> mu(ne);
   for (int e = 0; e < ne; ++e) mu[e] = (T)b->mu[e];
   T* d_mu = dalloc<T>(ne, own); up(d_mu, mu);
@@ -489,6 +520,7 @@ void set_state_t(flash_batch* b, int env, const double* x, const double* v) {
     }
   }
   HIPCHK(hipMemsetAsync(B.cache_stamp + (size_t)vo * kMaxObs, 0xFF, (size_t)n * kMaxObs * sizeof(int), b->stream));
+  HIPCHK(hipMemsetAsync(B.ws_state + e0, 0, (size_t)(e1 - e0) * sizeof(int), b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
 }
 
@@ -570,13 +602,15 @@ void stats_t(flash_batch* b, flash_env_stats* st) {
   HIPCHK(hipMemcpy(fl.data(), B.flags, ne * sizeof(int), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(fp.data(), B.fp64_polar, ne * sizeof(int), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(cc.data(), B.ccount, ne * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int> ws(ne);
+  HIPCHK(hipMemcpy(ws.data(), B.ws_state, ne * sizeof(int), hipMemcpyDeviceToHost));
   for (int e = 0; e < ne; ++e) {
     st[e].inner_iterations = it[e];
     st[e].refactorizations = rf[e];
     st[e].contacts = cc[e];
     st[e].fp64_polar = fp[e];
     st[e].flags = fl[e] | (r[e] > b->p.ncp_tol ? 2 : 0);
-    st[e].reserved = 0;
+    st[e].ws_state = ws[e];
     st[e].residual = r[e];
   }
 }
@@ -860,9 +894,72 @@ flash_status flash_phase_times(flash_batch* b, double* ms_out) {
 }
 
 flash_status flash_ws_load(flash_batch* b, const uint16_t* w, size_t n_params, const float* norm) {
-  (void)w; (void)n_params; (void)norm;
+  if (!b || !w || !norm) return fail(FLASH_ERR_INVALID_ARG, "null argument");
+  if (n_params != (size_t)MlpLayout::total) return fail(FLASH_ERR_INVALID_ARG, "n_params must be 35587");
+  for (int k = 0; k < kNorm; ++k)
+    if (!std::isfinite(norm[k])) return fail(FLASH_ERR_INVALID_ARG, "non-finite normalisation");
+  try {
+    b->ensure_ws_buffers();
+    // bf16 -> FP32 is exact; the GEMM rounds its operands back to the same bf16 values
+    std::vector<float> wf(n_params);
+    for (size_t i = 0; i < n_params; ++i) {
+      uint32_t u = (uint32_t)w[i] << 16;
+      std::memcpy(&wf[i], &u, 4);
+    }
+    HIPCHK(hipMemcpyAsync((void*)b->mlp.W, wf.data(), n_params * sizeof(float), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync((void*)b->mlp.norm, norm, kNorm * sizeof(float), hipMemcpyHostToDevice, b->stream));
+    int* ws = b->fp64 ? b->bd.ws_state : b->bf.ws_state;
+    HIPCHK(hipMemsetAsync(ws, 0, b->n_envs * sizeof(int), b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->ws_loaded = true;
+    if (b->fp64) b->bd.lam_ml = b->mlp.lam_ml; else b->bf.lam_ml = b->mlp.lam_ml;
+    if (b->p.warm_start != FLASH_WS_LEARNED) { b->bd.lam_ml = nullptr; b->bf.lam_ml = nullptr; }
+    b->drop_graph();
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_ws_record(flash_batch* b, int32_t on) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
-  return fail(FLASH_ERR_UNSUPPORTED, "learned warm start not built in this library");
+  try {
+    if (on) b->ensure_ws_buffers();
+    b->ws_record = on != 0;
+    b->drop_graph();
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_ws_collect(flash_batch* b, float* feat_dev, float* lab_dev, int64_t capacity, int64_t* n_inout) {
+  if (!b || !feat_dev || !lab_dev || !n_inout || *n_inout < 0 || capacity < 0)
+    return fail(FLASH_ERR_INVALID_ARG, "null or negative argument");
+  if (!b->ws_record) return fail(FLASH_ERR_INVALID_ARG, "recording is off (flash_ws_record)");
+  try {
+    std::vector<int> cc(b->n_envs);
+    const int cap = b->fp64 ? b->bd.cap : b->bf.cap;
+    HIPCHK(hipStreamSynchronize(b->stream));
+    HIPCHK(hipMemcpy(cc.data(), b->fp64 ? b->bd.ccount : b->bf.ccount, b->n_envs * sizeof(int),
+                     hipMemcpyDeviceToHost));
+    int64_t rows = 0;
+    for (int c : cc) rows += std::min(c, cap);
+    if (*n_inout + rows > capacity) {
+      return fail(FLASH_ERR_CAPACITY, "collect needs " + std::to_string(*n_inout + rows) + " rows");
+    }
+    if (b->fp64) {
+      launch_ws_compact<double>(b->bd, b->mlp.feat, b->ws_lab, feat_dev, lab_dev, (long)*n_inout, b->ws_coff, b->stream);
+    } else {
+      launch_ws_compact<float>(b->bf, b->mlp.feat, b->ws_lab, feat_dev, lab_dev, (long)*n_inout, b->ws_coff, b->stream);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(b->stream));
+    *n_inout += rows;
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
 }
 
 }  // extern "C"

@@ -702,7 +702,10 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int e = blockIdx.x;
   const int c = B.ccount[e];
-  if (c == 0) return;
+  if (c == 0) {
+    if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~1;
+    return;
+  }
   const int cap = B.cap;
   CspSmem<CT> S;
   {
@@ -795,34 +798,111 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     __syncthreads();
   };
 
-  apply_W(S.lam, S.Y);
-  for (int j = tid; j < c; j += kBlock)
-    for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
-  __syncthreads();
-  if (first_lg) {
-    // contacts without a warm start: Jacobi estimate of lambda_n
-    int any = 0;
-    for (int j = tid; j < c; j += kBlock) {
-      if (B.cnew[cb + j]) {
-        const CT cn = B.cd0[cb + j] + S.Y[3 * j];
-        S.lam[3 * j] = cn < CT(0) ? (double)(-cn / S.sp[j]) : 0.0;
-        S.lam[3 * j + 1] = 0;
-        S.lam[3 * j + 2] = 0;
-        any = 1;
-      }
-    }
-    if (block_max((double)any, sh_red) > 0) {
-      apply_W(S.lam, S.Y);
+  // previous-iterate start: the multipliers in clam (the previous-step warm start
+  // in the first local-global iteration), new contacts get a Jacobi estimate of lambda_n
+  auto load_prev = [&](bool reload) {
+    if (reload) {
       for (int j = tid; j < c; j += kBlock)
-        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
+        for (int a = 0; a < 3; ++a) S.lam[3 * j + a] = B.clam[3 * (cb + j) + a];
       __syncthreads();
     }
+    apply_W(S.lam, S.Y);
+    for (int j = tid; j < c; j += kBlock)
+      for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
+    __syncthreads();
+    if (first_lg) {
+      int any = 0;
+      for (int j = tid; j < c; j += kBlock) {
+        if (B.cnew[cb + j]) {
+          const CT cn = B.cd0[cb + j] + S.Y[3 * j];
+          S.lam[3 * j] = cn < CT(0) ? (double)(-cn / S.sp[j]) : 0.0;
+          S.lam[3 * j + 1] = 0;
+          S.lam[3 * j + 2] = 0;
+          any = 1;
+        }
+      }
+      if (block_max((double)any, sh_red) > 0) {
+        apply_W(S.lam, S.Y);
+        for (int j = tid; j < c; j += kBlock)
+          for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
+        __syncthreads();
+      }
+    }
+  };
+  load_prev(false);
+
+  // learned warm start: a candidate built from the network's prediction replaces the
+  // previous-iterate start only when the judge prefers it; non-finite candidates never win
+  bool learned = false;
+  if (first_lg && B.lam_ml && !(B.ws_state[e] & 2)) {
+    // merit of a start: (0.5 |Phi|^2, max |Phi_j|) with the inner scale
+    auto merit = [&](const auto* L, const CT* Yv, double* mx) {
+      double ps = 0.0, pm = 0.0;
+      for (int j = tid; j < c; j += kBlock) {
+        const CT sp = S.sp[j];
+        const CT l0 = (CT)L[3 * j], l1 = (CT)L[3 * j + 1], l2 = (CT)L[3 * j + 2];
+        const CT cn = B.cd0[cb + j] + Yv[3 * j];
+        const CT ut1 = Yv[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = Yv[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+        const CT phn = fmin(cn, sp * l0);
+        const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+        const CT rho = mu * fmax(l0, CT(0));
+        const CT ny = sqrt(y1 * y1 + y2 * y2);
+        CT p1 = 0, p2 = 0;
+        if (rho > CT(0)) {
+          if (ny <= rho) { p1 = y1; p2 = y2; }
+          else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
+        }
+        const CT ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+        double q = (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
+        if (!(q == q)) q = INFINITY;
+        ps += q;
+        pm = fmax(pm, q);
+      }
+      *mx = sqrt(block_max(pm, sh_red));
+      return 0.5 * block_sum(ps, sh_red);
+    };
+    double m_prev;
+    double psi_best = merit(S.lam, S.Y, &m_prev);
+    const int mode = B.ws_mode;
+    const int ncand = mode == 3 ? 2 : 1;
+    for (int q = 0; q < ncand; ++q) {
+      const double alpha = (mode == 3 && q == 0) ? 0.5 : 1.0;
+      for (int j = tid; j < c; j += kBlock) {
+        const bool take = mode != 1 || B.cnew[cb + j];
+        for (int a = 0; a < 3; ++a) {
+          const double lp = S.lam[3 * j + a], lm = B.lam_ml[3 * (cb + j) + a];
+          S.dl[3 * j + a] = (CT)(take ? lp + alpha * (lm - lp) : lp);
+        }
+      }
+      __syncthreads();
+      apply_W(S.dl, S.tmp);
+      for (int j = tid; j < c; j += kBlock)
+        for (int a = 0; a < 3; ++a) S.tmp[3 * j + a] += yfg[3 * j + a];
+      __syncthreads();
+      double m_c;
+      const double psi_c = merit(S.dl, S.tmp, &m_c);
+      const bool win = mode == 2 ? (m_c < 0.5 * m_prev) : (psi_c < psi_best);
+      if (win) {
+        psi_best = psi_c;
+        m_prev = m_c;
+        learned = true;
+        for (int j = tid; j < c; j += kBlock)
+          for (int a = 0; a < 3; ++a) {
+            S.lam[3 * j + a] = (double)S.dl[3 * j + a];
+            S.Y[3 * j + a] = S.tmp[3 * j + a];
+          }
+        __syncthreads();
+      }
+    }
   }
+  bool learned_failed = false;
 
   int it = 0, nref = 0, nfact = 0, nreuse = 0, nlsfail = 0;
   const int maxit = B.max_newton;
   double r = 0.0;
   mark(0);
+  int it0 = 0;
+restart:
   for (;; ++it) {
     // ---- Phi (inner scale), classification, residual (residual scale, FP64) ----
     double rloc = 0.0, psil = 0.0;
@@ -867,7 +947,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     r = block_max(rloc, sh_red);
     const double psi = 0.5 * block_sum(psil, sh_red);
     mark(1);
-    if (r <= B.tol || it >= maxit) break;
+    if (r <= B.tol || it - it0 >= maxit) break;
 
     // ---- base set: refactor when a coupled contact lies outside it ----
     int need = 0;
@@ -1132,6 +1212,15 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     }
   }
   mark(7);
+  if (learned && !learned_failed && r > B.tol) {
+    // the solve from the prediction did not converge: start again from the previous iterate
+    learned_failed = true;
+    load_prev(true);
+    if (tid == 0) lust[0] = 0;
+    __syncthreads();
+    it0 = it;
+    goto restart;
+  }
   // ---- write back ----
   for (int j = tid; j < c; j += kBlock) {
     const T* F = Fr + 9 * j;
@@ -1151,6 +1240,12 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
       B.phase[(size_t)B.n_envs * 8 + 4 * e + 3] += (r > B.tol) ? 1 : 0;
     }
     if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
+    if (first_lg && B.ws_state) {
+      int w = B.ws_state[e] & ~1;
+      if (learned && !learned_failed) w |= 1;
+      if (learned_failed) w |= 2;   // fall back to the previous-step start from now on
+      B.ws_state[e] = w;
+    }
   }
 }
 

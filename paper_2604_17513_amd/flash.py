@@ -34,9 +34,13 @@ EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
-    "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_ws_load", "flash_last_error",
+    "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_ws_load", "flash_ws_record",
+    "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
+    "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
+    "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_train", "flash_mlp_eval", "flash_last_error",
     "flash_version",
 ]
+MLP_FEATURES, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS, MLP_NORM = 16, 128, 3, 35587, 35
 
 
 class flash_env_desc(C.Structure):
@@ -67,7 +71,7 @@ class flash_contact(C.Structure):
 
 class flash_env_stats(C.Structure):
     _fields_ = [("inner_iterations", C.c_int32), ("refactorizations", C.c_int32), ("contacts", C.c_int32),
-                ("fp64_polar", C.c_int32), ("flags", C.c_int32), ("reserved", C.c_int32),
+                ("fp64_polar", C.c_int32), ("flags", C.c_int32), ("ws_state", C.c_int32),
                 ("residual", C.c_double)]
 
 
@@ -105,7 +109,22 @@ def lib():
         L.flash_kernel_name.argtypes = [I32]
         L.flash_kernel_name.restype = C.c_char_p
         L.flash_phase_times.argtypes = [P, D]
-        L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, C.POINTER(C.c_float)]
+        F32, I64 = C.POINTER(C.c_float), C.c_int64
+        L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, F32]
+        L.flash_ws_record.argtypes = [P, I32]
+        L.flash_ws_collect.argtypes = [P, P, P, I64, C.POINTER(I64)]
+        L.flash_mlp_create.argtypes = [I64, C.c_uint64, P, C.POINTER(P)]
+        L.flash_mlp_destroy.argtypes = [P]
+        L.flash_mlp_set_params.argtypes = [P, F32, I64]
+        L.flash_mlp_get_params.argtypes = [P, F32, I64]
+        L.flash_mlp_get_params_bf16.argtypes = [P, C.POINTER(C.c_uint16), I64]
+        L.flash_mlp_set_norm.argtypes = [P, F32]
+        L.flash_mlp_get_norm.argtypes = [P, F32]
+        L.flash_mlp_fit_norm.argtypes = [P, P, P, I64]
+        L.flash_mlp_forward.argtypes = [P, P, I64, P]
+        L.flash_mlp_grad.argtypes = [P, P, P, I64, F32, F32]
+        L.flash_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, F32]
+        L.flash_mlp_eval.argtypes = [P, P, P, I64, F32]
         L.flash_last_error.restype = C.c_char_p
         L.flash_version.restype = C.c_char_p
         for name in EXPORTED:
@@ -292,7 +311,8 @@ class Batch:
         arr = (flash_env_stats * self.n_envs)()
         _check(lib().flash_stats(self._h, arr))
         return [dict(inner_iterations=s.inner_iterations, refactorizations=s.refactorizations,
-                     contacts=s.contacts, fp64_polar=s.fp64_polar, flags=s.flags, residual=s.residual)
+                     contacts=s.contacts, fp64_polar=s.fp64_polar, flags=s.flags, ws_state=s.ws_state,
+                     residual=s.residual)
                 for s in arr]
 
     def set_kernel_timing(self, mask):
@@ -317,6 +337,101 @@ class Batch:
         _check(lib().flash_kernel_times(self._h, _dptr(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)), 16,
                                         C.byref(n)))
         return {lib().flash_kernel_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n.value)}
+
+
+    # -- learned warm start ----------------------------------------------------------
+    def ws_load(self, weights_bf16: np.ndarray, norm: np.ndarray):
+        w = np.ascontiguousarray(weights_bf16, dtype=np.uint16)
+        nm = np.ascontiguousarray(norm, dtype=np.float32)
+        _check(lib().flash_ws_load(self._h, w.ctypes.data_as(C.POINTER(C.c_uint16)), w.size, _fptr(nm)))
+
+    def ws_record(self, on: bool = True):
+        _check(lib().flash_ws_record(self._h, 1 if on else 0))
+
+    def ws_collect(self, feat_dev, lab_dev, capacity: int, n: int) -> int:
+        """Appends the last step's (feature, label) rows at row n of device arrays; returns the new count."""
+        cnt = C.c_int64(n)
+        _check(lib().flash_ws_collect(self._h, C.c_void_p(_devptr(feat_dev)), C.c_void_p(_devptr(lab_dev)),
+                                      int(capacity), C.byref(cnt)))
+        return cnt.value
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _devptr(x) -> int:
+    """Device address of a tensor-like object (anything with data_ptr()) or an int."""
+    return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
+
+
+class Mlp:
+    """The warm-start network trainer (wraps flash_mlp_*); data arguments are device arrays."""
+
+    def __init__(self, max_rows: int, seed: int = 0, stream: Optional[int] = None):
+        h = C.c_void_p()
+        _check(lib().flash_mlp_create(int(max_rows), int(seed), C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+        self.max_rows = max_rows
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().flash_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, w: np.ndarray):
+        a = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().flash_mlp_set_params(self._h, _fptr(a), a.size))
+
+    def params(self) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(lib().flash_mlp_get_params(self._h, _fptr(a), a.size))
+        return a
+
+    def params_bf16(self) -> np.ndarray:
+        a = np.empty(MLP_PARAMS, dtype=np.uint16)
+        _check(lib().flash_mlp_get_params_bf16(self._h, a.ctypes.data_as(C.POINTER(C.c_uint16)), a.size))
+        return a
+
+    def set_norm(self, norm: np.ndarray):
+        a = np.ascontiguousarray(norm, dtype=np.float32)
+        _check(lib().flash_mlp_set_norm(self._h, _fptr(a)))
+
+    def norm(self) -> np.ndarray:
+        a = np.empty(MLP_NORM, dtype=np.float32)
+        _check(lib().flash_mlp_get_norm(self._h, _fptr(a)))
+        return a
+
+    def fit_norm(self, feat_dev, lab_dev, n: int):
+        _check(lib().flash_mlp_fit_norm(self._h, C.c_void_p(_devptr(feat_dev)), C.c_void_p(_devptr(lab_dev)), int(n)))
+
+    def forward(self, x_dev, n: int, y_dev):
+        _check(lib().flash_mlp_forward(self._h, C.c_void_p(_devptr(x_dev)), int(n), C.c_void_p(_devptr(y_dev))))
+
+    def grad(self, x_dev, target_dev, n: int):
+        g = np.empty(MLP_PARAMS, dtype=np.float32)
+        loss = np.zeros(1, dtype=np.float32)
+        _check(lib().flash_mlp_grad(self._h, C.c_void_p(_devptr(x_dev)), C.c_void_p(_devptr(target_dev)), int(n),
+                                    _fptr(g), _fptr(loss)))
+        return g, float(loss[0])
+
+    def train(self, feat_dev, lab_dev, n: int, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+        losses = np.zeros(epochs, dtype=np.float32)
+        _check(lib().flash_mlp_train(self._h, C.c_void_p(_devptr(feat_dev)), C.c_void_p(_devptr(lab_dev)), int(n),
+                                     int(epochs), int(batch), float(lr), int(seed), _fptr(losses)))
+        return losses
+
+    def eval(self, feat_dev, lab_dev, n: int) -> float:
+        loss = np.zeros(1, dtype=np.float32)
+        _check(lib().flash_mlp_eval(self._h, C.c_void_p(_devptr(feat_dev)), C.c_void_p(_devptr(lab_dev)), int(n),
+                                    _fptr(loss)))
+        return float(loss[0])
 
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
