@@ -132,10 +132,14 @@ typedef struct {
   int32_t refactorizations;       /* inverse rebuilds of the contact-space operator */
   int32_t contacts;
   int32_t fp64_polar;             /* tets routed to the FP64 polar decomposition */
-  int32_t flags;                  /* bit 0: non-finite state, bit 1: not converged, bit 2: capacity */
+  int32_t flags;                  /* bit 0: non-finite state, bit 1: not converged, bit 2: contact
+                                     capacity, bit 3: Newton system above its row capacity
+                                     (contact capacity above 512) */
   int32_t ws_state;               /* learned warm start: bit 0 the step's first contact solve started
-                                     from the network's prediction; bit 1 the prediction is disabled for
-                                     this env (a solve started from it hit the iteration cap) */
+                                     from the network's prediction; bits 8-15 count solves from a
+                                     prediction that missed the tolerance and were restarted from the
+                                     plain start; bit 1 the prediction is disabled for this env after 3
+                                     of them (cleared by flash_set_state and flash_ws_load) */
   double residual;                /* NCP residual at the end of the step, m (FP64) */
 } flash_env_stats;
 
@@ -208,15 +212,19 @@ flash_status flash_phase_times(flash_batch *b, double *ms_out);
 /* ---------------------------------------------------------------------------
  * Learned warm start (not part of the paper's method, whose contact solve
  * starts from the previous iterate).  A 16 -> 128 -> 128 -> 128 -> 3 ReLU MLP
- * maps features of each contact at the step start to a prediction of its
- * converged multipliers.  Every GEMM of inference and training rounds its
- * operands to bfloat16 (nearest even) and accumulates in FP32 on the matrix
- * cores.  The previous-step warm start stays the fallback and the judge: the
- * first contact solve of a step starts from the prediction only where its
- * merit 0.5 |Phi|^2 is lower, and an env whose solve from a prediction hits
- * the iteration cap goes back to the previous-step start.  Every solve still
- * runs to the same tolerance, so results agree with the plain method within
- * that tolerance and only iteration counts change.
+ * maps features of each contact at the step start to a prediction of the
+ * multipliers of the step's first contact solve.  Every GEMM of inference and
+ * training rounds its operands to bfloat16 (nearest even) and accumulates in
+ * FP32 on the matrix cores.  The prediction is used for the contacts that have
+ * no previous-step multiplier (new contacts; every contact after a reset),
+ * where the plain start is a Jacobi estimate of the normal multiplier.  The
+ * plain start stays the fallback and the judge: the first contact solve of a
+ * step starts from the prediction only if that lowers the merit 0.5 |Phi|^2 of
+ * its start, a solve from a prediction that misses the tolerance within the
+ * iteration cap is restarted from the plain start, and an env stops using the
+ * prediction after three such restarts.  Every solve runs to the same
+ * tolerance, so results agree with the plain method within that tolerance and
+ * only iteration counts change.
  *
  * Parameters: W1[128x16] b1[128] W2[128x128] b2[128] W3[128x128] b3[128]
  * W4[3x128] b4[3], each W row-major (out x in): FLASH_MLP_PARAMS values.

@@ -14,6 +14,8 @@ namespace flash {
 
 constexpr int kMaxObs = 4;
 constexpr int kBlock = 256;
+constexpr int kBK = 16;         // panel width of the blocked factorisations in the contact solve
+constexpr int kWsMaxFail = 3;   // learned-start failures after which an env keeps the plain start
 
 // Kernel classes for event timing (flash_kernel_name order).
 enum KernelId {
@@ -26,7 +28,8 @@ struct DevBatch {
   int n_envs;
   int NV, NT;                 // total vertices / tets (tets: 4-node; tris: 3-node use the same arrays)
   int cap;                    // contact capacity per env
-  int rmax;                   // capacity of the Woodbury capacitance system per env
+  int rmax;                   // capacity of the Woodbury capacitance system per env (3 rows per contact)
+  int rlds;                   // systems of up to rlds rows keep their LU panel in LDS, larger ones in lupan
   int max_newton;
   int lg_iterations;
   double h;
@@ -92,6 +95,7 @@ struct DevBatch {
   void* Cm;                   // [rmax*rmax per env] capacitance matrix + row data
   int* base;                  // [cap per env] base-set contact ids (ordered)
   void* scr;                  // [cap*16 per env] panel scratch of the blocked inverse
+  void* lupan;                // [rmax*(kBK+1) per env] LU panel and solve vector of systems above rlds rows
   int* nbase;                 // [n_envs]
   int* lust;                  // [4 per env] stored capacitance factorisation: valid, rows, base version x2
 
@@ -112,9 +116,9 @@ struct DevBatch {
 
   // learned warm start (optional)
   const double* lam_ml;       // [3 per contact] predicted multipliers (nullptr: off)
-  int ws_mode;                // candidate / judge variant of the learned start
-  int* ws_state;              // [n_envs] bit 0: this step started from the prediction,
-                              //          bit 1: prediction disabled (a solve started from it hit the cap)
+  int* ws_state;              // [n_envs] bit 0: this step started from the prediction; bits 8-15:
+                              // solves from a prediction that missed the tolerance (restarted);
+                              // bit 1: prediction disabled after kWsMaxFail of them
 };
 
 }  // namespace flash

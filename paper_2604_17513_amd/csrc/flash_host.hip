@@ -334,7 +334,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.NV = b->NV;
   B.NT = b->NT;
   B.cap = b->p.max_contacts_per_env > 0 ? b->p.max_contacts_per_env : 320;
-  B.rmax = std::min(3 * B.cap, 480);
+  B.rmax = std::min(3 * B.cap, 1536);
+  B.rlds = std::min(B.rmax, 480);
   B.max_newton = b->p.max_inner_iterations > 0 ? b->p.max_inner_iterations : 50;
   B.lg_iterations = b->p.lg_iterations;
   B.h = b->p.h;
@@ -456,6 +457,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   {
     const size_t rm = (size_t)B.rmax;
     B.Cm = dalloc<unsigned char>(ne * (rm * rm + 16 * rm) * cts + 3 * ne * rm * sizeof(int), own);
+    B.lupan = dalloc<unsigned char>(ne * rm * (kBK + 1) * cts, own);
   }
   B.base = dalloc<int>(ne * cap, own);
   B.scr = dalloc<unsigned char>(ne * cap * 16 * cts, own);
@@ -488,7 +490,6 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.phase = dalloc<unsigned long long>((size_t)ne * 12, own);
   HIPCHK(hipMemset(B.phase, 0, (size_t)ne * 12 * sizeof(unsigned long long)));
   B.lam_ml = nullptr;
-  B.ws_mode = getenv("FLASH_WS_MODE") ? atoi(getenv("FLASH_WS_MODE")) : 0;
   B.ws_state = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.ws_state, 0, ne * sizeof(int)));
   std::vector<T> mu(ne);
@@ -718,7 +719,7 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS of the contact solve above the default limit
-    if (b->fp64) prepare_csp<double>(b->bd.cap, b->bd.rmax); else prepare_csp<float>(b->bf.cap, b->bf.rmax);
+    if (b->fp64) prepare_csp<double>(b->bd.cap, b->bd.rlds); else prepare_csp<float>(b->bf.cap, b->bf.rlds);
     *out = b;
     return FLASH_OK;
   } catch (const FlashError& ex) {

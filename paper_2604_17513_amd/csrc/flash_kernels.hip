@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
 // columns; pivot blocks are staged in LDS; trailing updates use 4x4 register
 // tiles and read the panels from global memory (L1/L2 resident).
 // ---------------------------------------------------------------------------
-constexpr int kBK = 16;
+// kBK (panel width of the blocked factorisations) lives in flash_device.h
 
 // In-place inverse of a symmetric positive definite n x n matrix (ld n) by
 // blocked Gauss-Jordan sweeps.  CP: global scratch of n x kBK; P: LDS kBK x kBK;
@@ -715,7 +715,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     S.Wd = p; p += 3 * cap; S.rv = p; p += 3 * cap; S.x0 = p; p += 3 * cap; S.fw = p; p += 3 * cap;
     S.ph = p; p += 3 * cap; S.tmp = p; p += 3 * cap;
     S.sp = p; p += cap; S.kap = p; p += cap; S.yh0 = p; p += cap; S.yh1 = p; p += cap;
-    S.pan = p; p += (size_t)B.rmax * kBK; S.ys = p; p += B.rmax;
+    S.pan = p; p += (size_t)B.rlds * kBK; S.ys = p; p += B.rlds;
     int* ip = reinterpret_cast<int*>(p);
     S.cls = ip; ip += cap; S.pos = ip; ip += cap; S.bas = ip; ip += cap;
   }
@@ -831,66 +831,56 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   };
   load_prev(false);
 
-  // learned warm start: a candidate built from the network's prediction replaces the
-  // previous-iterate start only when the judge prefers it; non-finite candidates never win
+  // learned warm start: contacts without a previous-step multiplier (new contacts, or
+  // every contact after a reset) take the network's prediction instead of the Jacobi
+  // estimate when that lowers the merit 0.5 |Phi|^2 of the start (inner scale);
+  // non-finite predictions never win
   bool learned = false;
-  if (first_lg && B.lam_ml && !(B.ws_state[e] & 2)) {
-    // merit of a start: (0.5 |Phi|^2, max |Phi_j|) with the inner scale
-    auto merit = [&](const auto* L, const CT* Yv, double* mx) {
-      double ps = 0.0, pm = 0.0;
-      for (int j = tid; j < c; j += kBlock) {
-        const CT sp = S.sp[j];
-        const CT l0 = (CT)L[3 * j], l1 = (CT)L[3 * j + 1], l2 = (CT)L[3 * j + 2];
-        const CT cn = B.cd0[cb + j] + Yv[3 * j];
-        const CT ut1 = Yv[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = Yv[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-        const CT phn = fmin(cn, sp * l0);
-        const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
-        const CT rho = mu * fmax(l0, CT(0));
-        const CT ny = sqrt(y1 * y1 + y2 * y2);
-        CT p1 = 0, p2 = 0;
-        if (rho > CT(0)) {
-          if (ny <= rho) { p1 = y1; p2 = y2; }
-          else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
+  if (first_lg && B.lam_ml && (B.ws_state[e] & 0xff00) < (kWsMaxFail << 8)) {
+    int anynew = 0;
+    for (int j = tid; j < c; j += kBlock) anynew |= B.cnew[cb + j];
+    if (block_max((double)anynew, sh_red) > 0) {
+      auto merit = [&](const auto* L, const CT* Yv) {
+        double ps = 0.0;
+        for (int j = tid; j < c; j += kBlock) {
+          const CT sp = S.sp[j];
+          const CT l0 = (CT)L[3 * j], l1 = (CT)L[3 * j + 1], l2 = (CT)L[3 * j + 2];
+          const CT cn = B.cd0[cb + j] + Yv[3 * j];
+          const CT ut1 = Yv[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = Yv[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
+          const CT phn = fmin(cn, sp * l0);
+          const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+          const CT rho = mu * fmax(l0, CT(0));
+          const CT ny = sqrt(y1 * y1 + y2 * y2);
+          CT p1 = 0, p2 = 0;
+          if (rho > CT(0)) {
+            if (ny <= rho) { p1 = y1; p2 = y2; }
+            else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
+          }
+          const CT ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
+          double q = (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
+          if (!(q == q)) q = INFINITY;
+          ps += q;
         }
-        const CT ph1 = sp * (l1 - p1), ph2 = sp * (l2 - p2);
-        double q = (double)phn * phn + (double)ph1 * ph1 + (double)ph2 * ph2;
-        if (!(q == q)) q = INFINITY;
-        ps += q;
-        pm = fmax(pm, q);
-      }
-      *mx = sqrt(block_max(pm, sh_red));
-      return 0.5 * block_sum(ps, sh_red);
-    };
-    double m_prev;
-    double psi_best = merit(S.lam, S.Y, &m_prev);
-    const int mode = B.ws_mode;
-    const int ncand = mode == 3 ? 2 : 1;
-    for (int q = 0; q < ncand; ++q) {
-      const double alpha = (mode == 3 && q == 0) ? 0.5 : 1.0;
+        return 0.5 * block_sum(ps, sh_red);
+      };
+      const double psi_prev = merit(S.lam, S.Y);
       for (int j = tid; j < c; j += kBlock) {
-        const bool take = mode != 1 || B.cnew[cb + j];
-        for (int a = 0; a < 3; ++a) {
-          const double lp = S.lam[3 * j + a], lm = B.lam_ml[3 * (cb + j) + a];
-          S.dl[3 * j + a] = (CT)(take ? lp + alpha * (lm - lp) : lp);
-        }
+        const bool take = B.cnew[cb + j] != 0;
+        for (int a = 0; a < 3; ++a)
+          S.dl[3 * j + a] = (CT)(take ? B.lam_ml[3 * (cb + j) + a] : S.lam[3 * j + a]);
       }
       __syncthreads();
       apply_W(S.dl, S.tmp);
       for (int j = tid; j < c; j += kBlock)
         for (int a = 0; a < 3; ++a) S.tmp[3 * j + a] += yfg[3 * j + a];
       __syncthreads();
-      double m_c;
-      const double psi_c = merit(S.dl, S.tmp, &m_c);
-      const bool win = mode == 2 ? (m_c < 0.5 * m_prev) : (psi_c < psi_best);
-      if (win) {
-        psi_best = psi_c;
-        m_prev = m_c;
+      if (merit(S.dl, S.tmp) < psi_prev) {
         learned = true;
-        for (int j = tid; j < c; j += kBlock)
-          for (int a = 0; a < 3; ++a) {
-            S.lam[3 * j + a] = (double)S.dl[3 * j + a];
-            S.Y[3 * j + a] = S.tmp[3 * j + a];
-          }
+        for (int j = tid; j < c; j += kBlock) {
+          if (B.cnew[cb + j])
+            for (int a = 0; a < 3; ++a) S.lam[3 * j + a] = B.lam_ml[3 * (cb + j) + a];
+          for (int a = 0; a < 3; ++a) S.Y[3 * j + a] = S.tmp[3 * j + a];
+        }
         __syncthreads();
       }
     }
@@ -1038,6 +1028,11 @@ restart:
       }
     }
     const int nR = min(sh_nR, B.rmax);
+    if (sh_nR > B.rmax && tid == 0) B.flags[e] |= 8;   // capacity exceeded: inexact direction
+    // LU panel and solve vector: LDS for systems up to rlds rows, global scratch above
+    CT* gpan = static_cast<CT*>(B.lupan) + (size_t)e * B.rmax * (kBK + 1);
+    CT* gys = gpan + (size_t)B.rmax * kBK;
+    const bool big = nR > B.rlds;
     bool reused = false;
     if (nR > 0) {
       // reuse the stored factorisation when its row set and base are unchanged
@@ -1078,7 +1073,8 @@ restart:
         }
         __syncthreads();
         mark(4);
-        wg_lu_factor(Cm, nR, piv, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
+        if (big) wg_lu_factor(Cm, nR, piv, sh_blk, gpan, sh_red, sh_i, &sh_piv);
+        else wg_lu_factor(Cm, nR, piv, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
         if (tid == 0) { lust[0] = 1; lust[1] = nR; lust[2] = lust[3]; ++nfact; }
       } else if (tid == 0) {
         ++nreuse;
@@ -1114,7 +1110,8 @@ restart:
           for (int b = 0; b < 3; ++b) rr += rv[8 + b] * rin[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
           rv[6] = rr;
         }
-        wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
+        if (big) wg_lu_apply(Cm, nR, piv, Rv, gys, sh_blk);
+        else wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
         for (int p = tid; p < nb; p += kBlock) {
           CT w0 = 0, w1 = 0, w2 = 0;
           for (int s = 0; s < nR; ++s) {
@@ -1243,7 +1240,8 @@ restart:
     if (first_lg && B.ws_state) {
       int w = B.ws_state[e] & ~1;
       if (learned && !learned_failed) w |= 1;
-      if (learned_failed) w |= 2;   // fall back to the previous-step start from now on
+      if (learned_failed && (w & 0xff00) < (kWsMaxFail << 8)) w += 1 << 8;
+      if ((w & 0xff00) >= (kWsMaxFail << 8)) w |= 2;   // previous-iterate start only from now on
       B.ws_state[e] = w;
     }
   }
@@ -1276,10 +1274,10 @@ void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s) {
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
   if (B.csp64) {
-    size_t sm = csp_smem_bytes<double>(B.cap, B.rmax);
+    size_t sm = csp_smem_bytes<double>(B.cap, B.rlds);
     hipLaunchKernelGGL((k_csp<T, double>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
   } else {
-    size_t sm = csp_smem_bytes<T>(B.cap, B.rmax);
+    size_t sm = csp_smem_bytes<T>(B.cap, B.rlds);
     hipLaunchKernelGGL((k_csp<T, T>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
   }
 }

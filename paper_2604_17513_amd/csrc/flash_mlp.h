@@ -33,6 +33,9 @@ struct GemmArgs {
   const float* bias;
   long M; int N, K;
   int relu, accumulate;
+  float* work;      // optional split-K scratch (nullptr: no split); work_cap floats
+  long work_cap;
+  int kslice;       // set by launch_gemm
 };
 
 // Device buffers of an inference pass over the contact slots of a batch.
@@ -49,7 +52,7 @@ struct MlpBuffers {
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 void mlp_forward(const float* W, const float* X, long n, float* H1, float* H2, float* H3, float* Y, hipStream_t s);
 void mlp_backward(const float* W, const float* X, long n, const float* H1, const float* H2, const float* H3,
-                  float* dY, float* dA, float* dB, float* G, hipStream_t s);
+                  float* dY, float* dA, float* dB, float* G, float* work, long work_cap, hipStream_t s);
 void mlp_loss(const float* Y, const float* Lab, long n, float* dY, double* partial, float* loss, hipStream_t s);
 void launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, int t, hipStream_t s);
 void launch_gather_batch(const float* feat, const float* lab, const int* idx, int B, const float* norm, float* X,

@@ -4,6 +4,8 @@
 // bfloat16 (round to nearest even), products accumulate in FP32.  Training
 // keeps FP32 master weights and Adam moments; bias gradients and losses use
 // fixed-order reductions, so a training run is deterministic.
+#include <algorithm>
+
 #include "flash_device.h"
 #include "flash_launch.h"
 #include "flash_mlp.h"
@@ -24,22 +26,35 @@ __device__ __forceinline__ short f2bf(float f) {
 // A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn]; one wave per
 // 32 x 32 tile of C; 32x32x8 lane layout: A row = lane % 32, k = 4 (lane / 32) + t;
 // B column = lane % 32, same k; D row = 8 (r / 4) + 4 (lane / 32) + r % 4, column = lane % 32.
+// blockIdx.z selects a K slice of g.kslice rows when the product is split over K: the
+// slice's partial sums go to g.work[z][M][N] and a second kernel adds the slices in order.
 __global__ void __launch_bounds__(64) k_gemm_bf16(GemmArgs g) {
   const int l = threadIdx.x;
   const long m0 = (long)blockIdx.x * 32, n0 = (long)blockIdx.y * 32;
   const long i = m0 + (l & 31), j = n0 + (l & 31);
   const int kq = 4 * (l >> 5);
+  const int kb = g.work ? (int)blockIdx.z * g.kslice : 0;
+  const int ke = g.work ? min(g.K, kb + g.kslice) : g.K;
   floatx16 c = {};
-  for (int k0 = 0; k0 < g.K; k0 += 8) {
+  for (int k0 = kb; k0 < ke; k0 += 8) {
     bf16x4 a, b;
     for (int t = 0; t < 4; ++t) {
       const int k = k0 + kq + t;
-      const float av = (i < g.M && k < g.K) ? g.A[i * g.sam + (long)k * g.sak] : 0.f;
-      const float bv = (j < g.N && k < g.K) ? g.B[(long)k * g.sbk + j * g.sbn] : 0.f;
+      const float av = (i < g.M && k < ke) ? g.A[i * g.sam + (long)k * g.sak] : 0.f;
+      const float bv = (j < g.N && k < ke) ? g.B[(long)k * g.sbk + j * g.sbn] : 0.f;
       a[t] = f2bf(av);
       b[t] = f2bf(bv);
     }
     c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+  }
+  if (g.work) {
+    float* wk = g.work + (size_t)blockIdx.z * g.M * g.N;
+    for (int r = 0; r < 16; ++r) {
+      const long ii = m0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+      const long jj = n0 + (l & 31);
+      if (ii < g.M && jj < g.N) wk[ii * g.N + jj] = c[r];
+    }
+    return;
   }
   for (int r = 0; r < 16; ++r) {
     const long ii = m0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
@@ -54,10 +69,41 @@ __global__ void __launch_bounds__(64) k_gemm_bf16(GemmArgs g) {
   }
 }
 
-void launch_gemm(const GemmArgs& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return;
+// sum of the K slices in slice order, then the epilogue of the plain kernel
+__global__ void k_splitk_reduce(GemmArgs g, int slices) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.M * g.N) return;
+  const long ii = idx / g.N, jj = idx - ii * g.N;
+  float v = 0.f;
+  for (int z = 0; z < slices; ++z) v += g.work[(size_t)z * g.M * g.N + idx];
+  if (g.bias) v += g.bias[jj];
+  if (g.relu) v = fmaxf(v, 0.f);
+  float* dst = g.C + ii * g.scm + jj * g.scn;
+  *dst = g.accumulate ? *dst + v : v;
+}
+
+void launch_gemm(const GemmArgs& g0, hipStream_t s) {
+  if (g0.M <= 0 || g0.N <= 0) return;
+  GemmArgs g = g0;
   dim3 grid((unsigned)((g.M + 31) / 32), (unsigned)((g.N + 31) / 32));
+  const long tiles = (long)grid.x * grid.y;
+  // few output tiles over a long K (weight gradients): split K so that the chip fills
+  int slices = 1;
+  if (g.work && tiles < 512 && g.K > 256) {
+    slices = (int)std::min<long>((g.K + 127) / 128, std::max<long>(1, 1024 / tiles));
+    slices = std::min<long>(slices, g.work_cap / (g.M * g.N));
+  }
+  if (slices <= 1) {
+    g.work = nullptr;
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, s, g);
+    return;
+  }
+  g.kslice = ((g.K + slices - 1) / slices + 7) / 8 * 8;
+  slices = (g.K + g.kslice - 1) / g.kslice;
+  grid.z = (unsigned)slices;
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, s, g);
+  const long mn = g.M * g.N;
+  hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g, slices);
 }
 
 // dH <- dH * (H > 0)
@@ -152,7 +198,7 @@ void mlp_forward(const float* W, const float* X, long n, float* H1, float* H2, f
 
 // grads of the mean-squared loss; dY holds dLoss/dY on entry (overwritten scratch: dA, dB)
 void mlp_backward(const float* W, const float* X, long n, const float* H1, const float* H2, const float* H3,
-                  float* dY, float* dA, float* dB, float* G, hipStream_t s) {
+                  float* dY, float* dA, float* dB, float* G, float* work, long work_cap, hipStream_t s) {
   const MlpLayout L;
   // dW = dZ^T * Hin  (nout x nin), db = colsum(dZ)
   auto wgrad = [&](const float* dZ, int nout, const float* Hin, int nin, float* dW, float* db) {
@@ -161,6 +207,7 @@ void mlp_backward(const float* W, const float* X, long n, const float* H1, const
     g.A = dZ; g.sam = 1; g.sak = nout;   // A(m, k) = dZ[k][m]
     g.B = Hin; g.sbk = nin; g.sbn = 1;   // B(k, n) = Hin[k][n]
     g.C = dW; g.scm = nin; g.scn = 1;
+    g.work = work; g.work_cap = work_cap;
     launch_gemm(g, s);
     hipLaunchKernelGGL(k_colsum, dim3(nout), dim3(256), 0, s, dZ, n, nout, db);
   };

@@ -59,6 +59,8 @@ struct flash_mlp {
   float *dA = nullptr, *dB = nullptr, *loss = nullptr;
   double* partial = nullptr;
   double* moments = nullptr;
+  float* work = nullptr;                       // split-K partial sums of the weight gradients
+  static constexpr long kWork = 64L * kHidden * kHidden;
   int adam_t = 0;
   std::vector<float> host_norm;
 
@@ -77,7 +79,7 @@ struct flash_mlp {
   void grad(long n, float* loss_dst) {
     mlp_forward(W, X, n, H1, H2, H3, Y, stream);
     mlp_loss(Y, L, n, dY, partial, loss_dst, stream);
-    mlp_backward(W, X, n, H1, H2, H3, dY, dA, dB, G, stream);
+    mlp_backward(W, X, n, H1, H2, H3, dY, dA, dB, G, work, kWork, stream);
   }
 };
 
@@ -123,6 +125,7 @@ flash_status flash_mlp_create(int64_t max_rows, uint64_t seed, void* hip_stream,
     m->loss = dmalloc<float>(1 << 16, m->own);
     m->partial = dmalloc<double>((3 * R + 255) / 256 + 1, m->own);
     m->moments = dmalloc<double>(2 * (kFeat + kOut), m->own);
+    m->work = dmalloc<float>(flash_mlp::kWork, m->own);
     // He-uniform weights (bound sqrt(6 / fan_in)), zero biases
     std::vector<float> w(P, 0.f);
     SplitMix64 rng(seed);

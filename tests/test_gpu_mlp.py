@@ -210,7 +210,10 @@ def test_features_and_labels_match_oracle():
 
 
 def _train_quick(b, sc, torch, F, steps=12, epochs=8):
-    """Records a short rollout of `b` and fits a network to it (GPU kernels only)."""
+    """Records a short rollout of `b` and fits a network to it (GPU kernels only).
+
+    `b` runs with the zero warm start, so every contact of every step is a
+    cold-start example: the case the prediction is used for."""
     cap = b.n_envs * 320 * steps
     fd = torch.zeros((cap, 16), dtype=torch.float32, device="cuda")
     ld = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
@@ -230,7 +233,7 @@ def test_learned_warm_start_step_matches_oracle():
     torch = _torch()
     F = _F()
     sc_train = scenes.squeeze_blocks(4, seed=21, hexes=6)
-    bt = F.from_scene(sc_train)
+    bt = F.from_scene(sc_train, warm_start=F.FLASH_WS_ZERO)
     m, n, losses = _train_quick(bt, sc_train, torch, F)
     _say(f"trained on {n} rows, epoch losses {np.round(losses, 4).tolist()}")
     sc = scenes.squeeze_blocks(2, seed=22, hexes=6)
@@ -243,6 +246,7 @@ def test_learned_warm_start_step_matches_oracle():
             x0, v0 = b.get_state()
             xs, vs = b.split(x0), b.split(v0)
             obs = [b.get_obstacles(e) for e in range(2)]
+            b.set_state(x0, v0)          # forget the multiplier history: every contact starts cold
             b.step(1)
             x1s = b.split(b.get_state()[0])
             for e in range(2):
@@ -257,6 +261,7 @@ def test_learned_warm_start_step_matches_oracle():
         per, mx, its, stc = b.residual()
         assert mx <= 1e-6
     _say(f"prediction chosen in {picked} of 32 env-steps")
+    assert picked >= 1
 
 
 def test_learned_warm_start_rejects_non_finite_predictions():
