@@ -259,7 +259,7 @@ struct flash_batch {
     const bool infer = ws_loaded && p.warm_start == FLASH_WS_LEARNED;
     if (infer || ws_record) {
       launch(K_MLP, [&] {
-        launch_ws_features<T>(B, mu_d, mlp.feat, stream);
+        launch_ws_features<T>(B, mu_d, mlp.feat, mlp.need, stream);
         if (infer) launch_ws_infer<T>(B, mu_d, mlp, stream);
       });
     }
@@ -288,15 +288,14 @@ struct flash_batch {
     mlp.W = dalloc<float>(MlpLayout::total, owned);
     mlp.norm = dalloc<float>(kNorm, owned);
     mlp.feat = dalloc<float>(rows * kFeat, owned);
-    mlp.X = dalloc<float>(rows * kFeat, owned);
-    mlp.H1 = dalloc<float>(rows * kHidden, owned);
-    mlp.H2 = dalloc<float>(rows * kHidden, owned);
-    mlp.H3 = dalloc<float>(rows * kHidden, owned);
+    mlp.need = dalloc<int>(rows, owned);
     mlp.Y = dalloc<float>(rows * kOut, owned);
     mlp.lam_ml = dalloc<double>(rows * 3, owned);
     ws_lab = dalloc<float>(rows * kOut, owned);
     ws_coff = dalloc<int>((size_t)n_envs + 1, owned);
     HIPCHK(hipMemset(mlp.feat, 0, rows * kFeat * sizeof(float)));
+    HIPCHK(hipMemset(mlp.Y, 0, rows * kOut * sizeof(float)));
+    prepare_mlp();
   }
 
   void step(int n) {

@@ -43,14 +43,19 @@ struct MlpBuffers {
   const float* W;      // FP32 copy of the bf16 weights (exactly representable)
   const float* norm;   // [kNorm]
   float* feat;         // [rows * kFeat] raw features
-  float* X;            // [rows * kFeat] normalised features
-  float* H1; float* H2; float* H3;   // [rows * kHidden]
+  int* need;           // [rows] 1: active contact without a previous-step multiplier
   float* Y;            // [rows * kOut]
   double* lam_ml;      // [rows * 3] cone-projected candidate multipliers
 };
 
 void launch_gemm(const GemmArgs& g, hipStream_t s);
-void mlp_forward(const float* W, const float* X, long n, float* H1, float* H2, float* H3, float* Y, hipStream_t s);
+// Raises the dynamic LDS limit of the fused forward kernel (call once before its first launch).
+void prepare_mlp();
+// Fused forward pass on the matrix cores: Y = network(X).  norm != nullptr: X holds raw
+// features; need != nullptr: 32-row tiles without a flagged row are skipped; H1..H3 != nullptr:
+// hidden activations stored for the backward pass.
+void launch_mlp_fused(const float* W, const float* norm, const float* X, long rows, const int* need, float* Y,
+                      float* H1, float* H2, float* H3, hipStream_t s);
 void mlp_backward(const float* W, const float* X, long n, const float* H1, const float* H2, const float* H3,
                   float* dY, float* dA, float* dB, float* G, float* work, long work_cap, hipStream_t s);
 void mlp_loss(const float* Y, const float* Lab, long n, float* dY, double* partial, float* loss, hipStream_t s);
@@ -59,7 +64,8 @@ void launch_gather_batch(const float* feat, const float* lab, const int* idx, in
                          float* Y, hipStream_t s);
 void launch_col_moments(const float* X, long rows, int cols, double* out, hipStream_t s);
 
-template <class T> void launch_ws_features(const DevBatch<T>& B, const T* mu_env, float* feat, hipStream_t s);
+template <class T> void launch_ws_features(const DevBatch<T>& B, const T* mu_env, float* feat, int* need,
+                                          hipStream_t s);
 // labels of the first contact solve of a step (launched right after it)
 template <class T> void launch_ws_labels(const DevBatch<T>& B, const float* feat, float* lab, hipStream_t s);
 template <class T> void launch_ws_infer(const DevBatch<T>& B, const T* mu_env, const MlpBuffers& M, hipStream_t s);

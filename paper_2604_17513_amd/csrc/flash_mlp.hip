@@ -106,6 +106,159 @@ void launch_gemm(const GemmArgs& g0, hipStream_t s) {
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g, slices);
 }
 
+// ---------------------------------------------------------------------------
+// Fused forward pass on v_mfma_f32_32x32x16_bf16.  Lane layout of that
+// instruction: A(m, k) from lane m + 32 (k / 8), element k % 8; B(k, n) from
+// lane n + 32 (k / 8), element k % 8; D(i, j) in lane j + 32 ((i / 4) % 2),
+// register 4 (i / 8) + i % 4.  The network runs transposed (H^T = W X^T):
+// rows of a D tile are neurons, columns are 32 samples, so the registers a
+// lane holds for one output tile are exactly the B operand of the next layer
+// once the 16 inputs of each K step are visited in the order neuron(k) =
+// 8 ((k % 8) / 4) + 4 (k / 8) + k % 4.  The weights are staged in LDS as
+// bf16 with the columns of each 16-block permuted to that order (bits 2 and
+// 3 of the input index swapped), so every A operand is one 16-byte read.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kLd1 = 24;    // LDS row stride of W1 (bf16): 48 B keeps 16-byte reads conflict-free
+constexpr int kLdH = 136;   // LDS row stride of W2, W3, W4 (bf16): 272 B
+constexpr int kWaves = 4;
+
+struct FusedSmem {
+  __bf16 w1[kHidden * kLd1];
+  __bf16 w2[kHidden * kLdH];
+  __bf16 w3[kHidden * kLdH];
+  __bf16 w4[kOut * kLdH];
+  float b[3 * kHidden + 4];
+  float nrm[2 * kFeat];
+};
+constexpr size_t kFusedSmem = sizeof(FusedSmem);
+
+__device__ __forceinline__ int perm16(int c) { return (c & ~12) | ((c & 4) << 1) | ((c & 8) >> 1); }
+
+__device__ __forceinline__ __bf16 to_bf(float f) { return __builtin_bit_cast(__bf16, f2bf(f)); }
+
+// one hidden layer: hn = relu(W h + b) on the 4 x 16 register tile of a wave
+__device__ __forceinline__ void fused_hidden(const __bf16* w, const float* bias, const float (&h)[4][16],
+                                             float (&hn)[4][16], int l) {
+  bf16x8 bop[4][2];
+  for (int mt = 0; mt < 4; ++mt)
+    for (int p = 0; p < 2; ++p)
+      for (int t = 0; t < 8; ++t) bop[mt][p][t] = to_bf(h[mt][8 * p + t]);
+  for (int mt = 0; mt < 4; ++mt) {
+    const __bf16* wrow = w + (32 * mt + (l & 31)) * kLdH + 8 * (l >> 5);
+    floatx16 acc = {};
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 2; ++p) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(wrow + 32 * q + 16 * p);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop[q][p], acc, 0, 0, 0);
+      }
+    for (int r = 0; r < 16; ++r)
+      hn[mt][r] = fmaxf(acc[r] + bias[32 * mt + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3)], 0.f);
+  }
+}
+
+__device__ __forceinline__ void fused_store(float* H, long row, long rows, const float (&h)[4][16], int l) {
+  if (row >= rows) return;
+  for (int mt = 0; mt < 4; ++mt)
+    for (int q = 0; q < 4; ++q) {
+      float4 v = make_float4(h[mt][4 * q], h[mt][4 * q + 1], h[mt][4 * q + 2], h[mt][4 * q + 3]);
+      *reinterpret_cast<float4*>(H + row * kHidden + 32 * mt + 8 * q + 4 * (l >> 5)) = v;
+    }
+}
+
+// Y = network(X) for `rows` rows.  norm != nullptr: X holds raw features, normalised on load.
+// need != nullptr: 32-row tiles without a flagged row are skipped (their Y is left as is).
+// H1 != nullptr: the hidden activations are stored for the backward pass.
+__global__ void __launch_bounds__(64 * kWaves) k_mlp_fused(const float* W, const float* norm, const float* X,
+                                                           long rows, const int* need, float* Y, float* H1,
+                                                           float* H2, float* H3) {
+  extern __shared__ __align__(16) unsigned char fsm_raw[];
+  FusedSmem& S = *reinterpret_cast<FusedSmem*>(fsm_raw);
+  const MlpLayout L;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kHidden * kFeat; i += blockDim.x) {
+    const int r = i / kFeat, c = i - r * kFeat;
+    S.w1[r * kLd1 + c] = to_bf(W[L.w1 + i]);
+  }
+  for (int i = tid; i < kHidden * kHidden; i += blockDim.x) {
+    const int r = i / kHidden, c = i - r * kHidden;
+    S.w2[r * kLdH + perm16(c)] = to_bf(W[L.w2 + i]);
+    S.w3[r * kLdH + perm16(c)] = to_bf(W[L.w3 + i]);
+  }
+  for (int i = tid; i < kOut * kHidden; i += blockDim.x) {
+    const int r = i / kHidden, c = i - r * kHidden;
+    S.w4[r * kLdH + perm16(c)] = to_bf(W[L.w4 + i]);
+  }
+  for (int i = tid; i < kHidden; i += blockDim.x) {
+    S.b[i] = W[L.b1 + i];
+    S.b[kHidden + i] = W[L.b2 + i];
+    S.b[2 * kHidden + i] = W[L.b3 + i];
+  }
+  if (tid < kOut) S.b[3 * kHidden + tid] = W[L.b4 + tid];
+  if (tid < 2 * kFeat) S.nrm[tid] = norm ? norm[tid] : (tid < kFeat ? 0.f : 1.f);
+  __syncthreads();
+
+  const int l = tid & 63, wave = tid >> 6;
+  const int h = l >> 5;
+  const long ntiles = (rows + 31) / 32;
+  for (long tile = (long)blockIdx.x * kWaves + wave; tile < ntiles; tile += (long)gridDim.x * kWaves) {
+    const long row = tile * 32 + (l & 31);
+    if (need) {
+      const bool mine = row < rows && need[row] != 0;
+      if (__ballot(mine) == 0) continue;
+    }
+    // layer 1: B operand = 8 features of this lane's sample
+    bf16x8 xb;
+    for (int t = 0; t < 8; ++t) {
+      const int k = 8 * h + t;
+      const float v = row < rows ? X[row * kFeat + k] : 0.f;
+      xb[t] = to_bf((v - S.nrm[k]) * S.nrm[kFeat + k]);
+    }
+    float ha[4][16], hb[4][16];
+    for (int mt = 0; mt < 4; ++mt) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(S.w1 + (32 * mt + (l & 31)) * kLd1 + 8 * h);
+      floatx16 acc = {};
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, xb, acc, 0, 0, 0);
+      for (int r = 0; r < 16; ++r) ha[mt][r] = fmaxf(acc[r] + S.b[32 * mt + 8 * (r >> 2) + 4 * h + (r & 3)], 0.f);
+    }
+    if (H1) fused_store(H1, row, rows, ha, l);
+    fused_hidden(S.w2, S.b + kHidden, ha, hb, l);
+    if (H2) fused_store(H2, row, rows, hb, l);
+    fused_hidden(S.w3, S.b + 2 * kHidden, hb, ha, l);
+    if (H3) fused_store(H3, row, rows, ha, l);
+    // output layer: rows 0..2 of a zero-padded 32-row tile
+    bf16x8 bop[4][2];
+    for (int mt = 0; mt < 4; ++mt)
+      for (int p = 0; p < 2; ++p)
+        for (int t = 0; t < 8; ++t) bop[mt][p][t] = to_bf(ha[mt][8 * p + t]);
+    floatx16 acc = {};
+    const int m = l & 31;
+    for (int q = 0; q < 4; ++q)
+      for (int p = 0; p < 2; ++p) {
+        bf16x8 a;
+        if (m < kOut) a = *reinterpret_cast<const bf16x8*>(S.w4 + m * kLdH + 8 * h + 32 * q + 16 * p);
+        else for (int t = 0; t < 8; ++t) a[t] = __builtin_bit_cast(__bf16, (short)0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bop[q][p], acc, 0, 0, 0);
+      }
+    if (h == 0 && row < rows)
+      for (int k = 0; k < kOut; ++k) Y[row * kOut + k] = acc[k] + S.b[3 * kHidden + k];
+  }
+}
+
+void prepare_mlp() {
+  (void)hipFuncSetAttribute((const void*)k_mlp_fused, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedSmem);
+}
+
+void launch_mlp_fused(const float* W, const float* norm, const float* X, long rows, const int* need, float* Y,
+                      float* H1, float* H2, float* H3, hipStream_t s) {
+  if (rows <= 0) return;
+  const long ntiles = (rows + 31) / 32;
+  const long blocks = std::min<long>((ntiles + kWaves - 1) / kWaves, 1024);
+  hipLaunchKernelGGL(k_mlp_fused, dim3((unsigned)blocks), dim3(64 * kWaves), kFusedSmem, s, W, norm, X, rows, need, Y,
+                     H1, H2, H3);
+}
+
 // dH <- dH * (H > 0)
 __global__ void k_relu_grad(float* dH, const float* H, long n) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,23 +332,6 @@ __global__ void k_gather_batch(const float* feat, const float* lab, const int* i
 // ---------------------------------------------------------------------------
 // forward / backward of the network on row-major activations
 // ---------------------------------------------------------------------------
-void mlp_forward(const float* W, const float* X, long n, float* H1, float* H2, float* H3, float* Y, hipStream_t s) {
-  const MlpLayout L;
-  auto lin = [&](const float* in, int nin, const float* w, const float* b, int nout, float* out, int relu) {
-    GemmArgs g{};
-    g.M = n; g.N = nout; g.K = nin;
-    g.A = in; g.sam = nin; g.sak = 1;
-    g.B = w; g.sbk = 1; g.sbn = nin;    // B(k, n) = W[n][k]
-    g.C = out; g.scm = nout; g.scn = 1;
-    g.bias = b; g.relu = relu; g.accumulate = 0;
-    launch_gemm(g, s);
-  };
-  lin(X, kFeat, W + L.w1, W + L.b1, kHidden, H1, 1);
-  lin(H1, kHidden, W + L.w2, W + L.b2, kHidden, H2, 1);
-  lin(H2, kHidden, W + L.w3, W + L.b3, kHidden, H3, 1);
-  lin(H3, kHidden, W + L.w4, W + L.b4, 3, Y, 0);
-}
-
 // grads of the mean-squared loss; dY holds dLoss/dY on entry (overwritten scratch: dA, dB)
 void mlp_backward(const float* W, const float* X, long n, const float* H1, const float* H2, const float* H3,
                   float* dY, float* dA, float* dB, float* G, float* work, long work_cap, hipStream_t s) {
@@ -259,15 +395,17 @@ void launch_gather_batch(const float* feat, const float* lab, const int* idx, in
 // (dobs.n)/dc, 1.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ void k_ws_features(DevBatch<T> B, const T* mu_env, float* feat) {
+__global__ void k_ws_features(DevBatch<T> B, const T* mu_env, float* feat, int* need) {
   const long slot = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= (long)B.n_envs * B.cap) return;
   const int e = (int)(slot / B.cap), jj = (int)(slot - (long)e * B.cap);
   float* f = feat + slot * kFeat;
   if (jj >= B.ccount[e]) {
     for (int k = 0; k < kFeat; ++k) f[k] = 0.f;
+    if (need) need[slot] = 0;
     return;
   }
+  if (need) need[slot] = B.cnew[slot];
   const double dc = B.margin > 0 ? B.margin : 1e-3;
   const int vloc = B.cvert[slot];
   const int vi = B.voff[e] + vloc;
@@ -394,16 +532,10 @@ __global__ void k_ws_compact(DevBatch<T> B, const int* coff, const float* feat, 
   for (int k = 0; k < kOut; ++k) out_lab[row * kOut + k] = lab[slot * kOut + k];
 }
 
-__global__ void k_normalize_rows(const float* feat, long n, const float* norm, float* X) {
-  const long r = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  for (int k = 0; k < kFeat; ++k) X[r * kFeat + k] = (feat[r * kFeat + k] - norm[k]) * norm[kFeat + k];
-}
-
 template <class T>
-void launch_ws_features(const DevBatch<T>& B, const T* mu_env, float* feat, hipStream_t s) {
+void launch_ws_features(const DevBatch<T>& B, const T* mu_env, float* feat, int* need, hipStream_t s) {
   const long n = (long)B.n_envs * B.cap;
-  hipLaunchKernelGGL(k_ws_features<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, mu_env, feat);
+  hipLaunchKernelGGL(k_ws_features<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, mu_env, feat, need);
 }
 template <class T>
 void launch_ws_labels(const DevBatch<T>& B, const float* feat, float* lab, hipStream_t s) {
@@ -413,8 +545,7 @@ void launch_ws_labels(const DevBatch<T>& B, const float* feat, float* lab, hipSt
 template <class T>
 void launch_ws_infer(const DevBatch<T>& B, const T* mu_env, const MlpBuffers& M, hipStream_t s) {
   const long n = (long)B.n_envs * B.cap;
-  hipLaunchKernelGGL(k_normalize_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M.feat, n, M.norm, M.X);
-  mlp_forward(M.W, M.X, n, M.H1, M.H2, M.H3, M.Y, s);
+  launch_mlp_fused(M.W, M.norm, M.feat, n, M.need, M.Y, nullptr, nullptr, nullptr, s);
   hipLaunchKernelGGL(k_ws_candidates<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B, mu_env, M.feat, M.Y,
                      M.norm, M.lam_ml);
 }
@@ -429,7 +560,7 @@ void launch_ws_compact(const DevBatch<T>& B, const float* feat, const float* lab
 }
 
 #define INSTW(T)                                                                           \
-  template void launch_ws_features<T>(const DevBatch<T>&, const T*, float*, hipStream_t); \
+  template void launch_ws_features<T>(const DevBatch<T>&, const T*, float*, int*, hipStream_t); \
   template void launch_ws_labels<T>(const DevBatch<T>&, const float*, float*, hipStream_t);             \
   template void launch_ws_infer<T>(const DevBatch<T>&, const T*, const MlpBuffers&, hipStream_t); \
   template void launch_ws_compact<T>(const DevBatch<T>&, const float*, const float*, float*, float*, long, int*, \

@@ -77,7 +77,7 @@ struct flash_mlp {
 
   // loss and gradient of one minibatch already in X (normalised) and L (scaled labels)
   void grad(long n, float* loss_dst) {
-    mlp_forward(W, X, n, H1, H2, H3, Y, stream);
+    launch_mlp_fused(W, nullptr, X, n, nullptr, Y, H1, H2, H3, stream);
     mlp_loss(Y, L, n, dY, partial, loss_dst, stream);
     mlp_backward(W, X, n, H1, H2, H3, dY, dA, dB, G, work, kWork, stream);
   }
@@ -101,6 +101,7 @@ flash_status flash_mlp_create(int64_t max_rows, uint64_t seed, void* hip_stream,
   flash_mlp* m = new flash_mlp();
   try {
     m->max_rows = (long)max_rows;
+    prepare_mlp();
     if (hip_stream) {
       m->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -244,10 +245,7 @@ flash_status flash_mlp_fit_norm(flash_mlp* m, const float* feat, const float* la
 flash_status flash_mlp_forward(flash_mlp* m, const float* x, int64_t n, float* y) {
   if (!m || !x || !y || n < 0) return fail(FLASH_ERR_INVALID_ARG, "null or negative argument");
   try {
-    for (int64_t r0 = 0; r0 < n; r0 += m->max_rows) {
-      const long rows = (long)std::min<int64_t>(m->max_rows, n - r0);
-      mlp_forward(m->W, x + r0 * kFeat, rows, m->H1, m->H2, m->H3, y + r0 * kOut, m->stream);
-    }
+    launch_mlp_fused(m->W, nullptr, x, (long)n, nullptr, y, nullptr, nullptr, nullptr, m->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(m->stream));
   } catch (const FlashError& ex) {
@@ -325,7 +323,7 @@ flash_status flash_mlp_eval(flash_mlp* m, const float* feat, const float* lab, i
       for (long i = 0; i < rows; ++i) id[(size_t)i] = (int)(r0 + i);
       HIPCHK(hipMemcpyAsync(idx, id.data(), rows * sizeof(int), hipMemcpyHostToDevice, m->stream));
       launch_gather_batch(feat, lab, idx, (int)rows, m->norm, m->X, m->L, m->stream);
-      mlp_forward(m->W, m->X, rows, m->H1, m->H2, m->H3, m->Y, m->stream);
+      launch_mlp_fused(m->W, nullptr, m->X, rows, nullptr, m->Y, nullptr, nullptr, nullptr, m->stream);
       mlp_loss(m->Y, m->L, rows, m->dY, m->partial, m->loss, m->stream);
       float l = 0.f;
       HIPCHK(hipStreamSynchronize(m->stream));

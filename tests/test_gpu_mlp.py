@@ -3,14 +3,17 @@ FP64 network oracle, the per-contact features and labels against the oracle's,
 training behaviour, and the learned-warm-start step against the FP64 step oracle.
 
 Tolerances of the network comparisons.  Both sides round every GEMM operand to
-bfloat16; the GPU sums the exact products in FP32, the oracle in FP64 (about
-K 2^-24 relative apart, K <= 4096).  A hidden activation whose FP32 value lies
-within that distance of a bfloat16 rounding tie rounds the other way on one
-side (probability ~ 1e-7 / 2^-8 per value): such a value moves by one bf16
-unit (2^-8 relative), which shifts an output by at most ~2^-8 / sqrt(128) of
-its scale.  Outputs are therefore compared to 2e-3 of their largest magnitude
-and gradients norm-wise to 1e-2, which a dropped term, a transposed operand or
-a missing ReLU mask exceed by orders of magnitude.
+bfloat16; the GPU sums the exact products in FP32, the oracle in FP64, so a
+pre-activation differs by about sqrt(K) 2^-24 relative (K = 128).  A hidden
+value that close to a bfloat16 rounding boundary rounds the other way on one
+side (probability ~ 1e-6 / 2^-8 ~ 4e-4 per value, so a few flips per hundred
+rows); a flip moves that value by one bf16 unit (2^-8 relative) and the
+outputs downstream of it by up to ~2^-8 of their scale.  Outputs are therefore
+checked in two parts: the bulk (99th percentile of the per-row error) against
+1e-4 of the largest output, which only the FP32-versus-FP64 summation order can
+reach, and the worst row against 1e-2; gradients norm-wise to 1e-2.  A dropped
+term, a transposed operand or a missing ReLU mask exceeds these by orders of
+magnitude in every row.
 """
 import sys
 
@@ -49,23 +52,27 @@ def _net(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
-@pytest.mark.parametrize("n", [1, 37, 300])
+@pytest.mark.parametrize("n", [1, 37, 300, 140001])
 def test_mlp_forward_matches_oracle(n):
+    """n = 140001 needs more 32-row tiles than the persistent grid has waves (ragged last tile)."""
     torch = _torch()
     F = _F()
     _say(f"mlp forward n={n}")
     th = _net(n)
     X = np.random.default_rng(10 + n).standard_normal((n, 16)).astype(np.float32)
-    m = F.Mlp(max_rows=512, seed=0)
+    m = F.Mlp(max_rows=4096, seed=0)
     m.set_params(th)
     xd = torch.from_numpy(X).cuda()
     yd = torch.empty((n, 3), dtype=torch.float32, device="cuda")
     m.forward(xd, n, yd)
     Y = yd.cpu().numpy().astype(np.float64)
     R, _ = M.forward(th.astype(np.float64), X.astype(np.float64), rounded=True)
-    err = np.abs(Y - R).max() / max(np.abs(R).max(), 1e-30)
-    _say(f"  max rel err {err:.2e}")
-    assert err <= 2e-3
+    scale = max(np.abs(R).max(), 1e-30)
+    row_err = np.abs(Y - R).max(axis=1) / scale
+    p99 = np.percentile(row_err, 99)
+    _say(f"  row error / max|Y|: p50 {np.median(row_err):.2e} p99 {p99:.2e} max {row_err.max():.2e}")
+    assert p99 <= 1e-4
+    assert row_err.max() <= 1e-2
 
 
 @pytest.mark.parametrize("n", [5, 64, 333])
