@@ -11,10 +11,22 @@ A step is one pass of the whole hot path over all environments (detection,
 prediction, K x (projection, assembly, global apply, contact solve, position
 update), finalisation).  The state is resident in HBM before the timed region.
 
+Arms, each on a fresh batch over the same steps (10 warm-up, then the timed
+steps): plain (previous-step warm start, one launch per phase, no graph),
+graph (the whole step captured in one HIP graph) and graph + learned warm
+start.  The learned arm's network is trained first, on the GPU, from a
+recorded rollout with seeds disjoint from the timed workload; recording and
+training are reported separately and excluded from the timed region.
+`value` is the graph + learned arm (every row of the hot path, batching and
+the learned start included); --quick runs the plain arm only.
+
 Prints one JSON line (rank 0).  The roofline object covers the dominant kernel
 (the explicit-inverse global apply), timed with HIP events on the batch's
-stream inside the timed region; cpu_baseline times the FP64 oracle on the
-host on a bounded sample of the same workload.
+stream inside the plain arm's timed region; its traffic comes from the
+committed counter summary when that was taken on the same kernel source
+(sha256 of the kernel template), else null.  roofline_network covers the
+fused bf16 MFMA forward pass.  cpu_baseline times the FP64 oracle on the host
+on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -29,6 +41,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "env-steps/sec at NCP residual 1e-6: plain vs batched+learned warm-start, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 K_APPLY = 4
 
 
@@ -70,6 +83,114 @@ def _oracle_env(e, n_steps):
         return time.time() - t0, r.residual
 
 
+def kernel_source_hash(path, name):
+    """sha256 (12 hex digits) of one kernel template's source text (from its template line to the
+    closing brace at column 0), used to tell whether committed counter data still applies."""
+    import hashlib
+    src = open(path).read()
+    i = src.index(f"{name}(")
+    i = src.rfind("template <", 0, i)
+    j = src.index("\n}\n", i)
+    return hashlib.sha256(src[i:j + 3].encode()).hexdigest()[:12]
+
+
+def committed_traffic(path, src_hash):
+    """HBM bytes per launch from a committed counter summary, if it was taken on this kernel source."""
+    if not os.path.exists(path):
+        return None, None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+            k, v = line.strip().split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != src_hash or "traffic_bytes_per_launch" not in vals:
+        return None, vals.get("kernel_source_sha256")
+    return float(vals["traffic_bytes_per_launch"]), src_hash
+
+
+def train_warm_start(F, scenes, torch, n_envs=256, steps=60, epochs=6, seed=1):
+    """Records cold-start training pairs (zero warm start: every contact of every step lacks a
+    previous multiplier) from a squeeze rollout with seeds disjoint from the timed workload, and fits
+    the warm-start network on the GPU.  Returns (bf16 weights, norm, info)."""
+    t0 = time.time()
+    sc = scenes.squeeze_blocks(n_envs, seed=seed)
+    b = F.from_scene(sc, warm_start=F.FLASH_WS_ZERO)
+    cap = n_envs * 320 * steps
+    fd = torch.zeros((cap, 16), dtype=torch.float32, device="cuda")
+    ld = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+    b.ws_record(True)
+    n = 0
+    for _ in range(steps):
+        b.step(1)
+        n = b.ws_collect(fd, ld, cap, n)
+    b.close()
+    t_rec = time.time() - t0
+    m = F.Mlp(max_rows=65536, seed=seed)
+    m.fit_norm(fd, ld, n)
+    t1 = time.time()
+    losses = []
+    for ep in range(epochs):
+        lr = 1e-3 if ep < epochs - 2 else 3e-4
+        losses += m.train(fd, ld, n, epochs=1, batch=4096, lr=lr, seed=ep).tolist()
+    t_train = time.time() - t1
+    info = {"pairs": int(n), "record_s": round(t_rec, 1), "train_s": round(t_train, 2), "epochs": epochs,
+            "batch": 4096, "epoch_loss": [round(x, 5) for x in losses],
+            "train_rows_per_s": round(n * epochs / t_train), "source": f"squeeze_blocks({n_envs}, seed={seed}), "
+            f"{steps} steps, zero warm start"}
+    w, nm = m.params_bf16(), m.norm()
+    del fd, ld
+    m.close()
+    return w, nm, info
+
+
+def mlp_roofline(F, torch, rows=1 << 22, reps=5):
+    """Fused bf16 MFMA forward pass over `rows` feature rows, timed with HIP events on the stream it
+    runs on: algorithmic 70,400 FLOP per row against the dense bf16 peak."""
+    st = torch.cuda.current_stream()
+    m = F.Mlp(max_rows=4096, seed=0, stream=st.cuda_stream)
+    x = torch.randn((rows, 16), dtype=torch.float32, device="cuda")
+    y = torch.empty((rows, 3), dtype=torch.float32, device="cuda")
+    m.forward(x, rows, y)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(reps):
+        m.forward(x, rows, y)
+    b.record(st)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    tflops = 70400.0 * rows / (ms * 1e-3) / 1e12
+    m.close()
+    return {"bound": "mfma", "kernel": "k_mlp_fused (16-128-128-128-3 forward, v_mfma_f32_32x32x16_bf16)",
+            "achieved": round(tflops, 1), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tflops / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None, "rows_per_launch": rows,
+            "flop_per_row": 70400, "avg_launch_ms": round(ms, 4)}
+
+
+def run_arm(F, sc, args, use_graph, warm_start, ws=None, time_apply=False):
+    """Fresh batch of the workload; W warm-up steps, then K timed steps (synchronised both sides).
+    time_apply: HIP events around every kernel launch of the timed steps (per-class totals)."""
+    import torch
+    b = F.from_scene(sc, use_graph=use_graph, warm_start=warm_start)
+    if ws is not None:
+        b.ws_load(*ws)
+    b.step(args.warmup)
+    b.synchronize()
+    b.residual_history(reset=True)
+    if time_apply:
+        b.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    b.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = b.kernel_times() if time_apply else None
+    b.set_kernel_timing(0)
+    hist_max, hist_over, newton, env_steps = b.residual_history(reset=True, full=True)
+    return b, dt, kt, hist_max, hist_over, newton / max(env_steps, 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,9 +198,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--envs", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
-    ap.add_argument("--quick", action="store_true", help="skip the graph arm and the per-kernel breakdown")
+    ap.add_argument("--quick", action="store_true",
+                    help="plain eager arm only (no graph or learned arm, no breakdown, no network roofline)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: environments are independent and this build "
@@ -112,56 +234,55 @@ def main():
 
     sc = scenes.squeeze_blocks(args.envs, seed=0)
     nv = [e.n_vertices for e in sc.envs]
+
+    # A1: plain (previous-step warm start, one launch per phase, no graph); every launch bracketed by
+    # HIP events (per-kernel breakdown of the timed steps and the apply kernel's average duration)
     t0 = time.time()
-    b = F.from_scene(sc)
-    precompute_s = time.time() - t0
-    log(f"created {args.envs} envs in {precompute_s:.1f}s")
-
-    b.step(args.warmup)
-    b.synchronize()
-    b.residual_history(reset=True)
-
-    # timed region: events around every global-apply launch (the dominant kernel)
-    b.set_kernel_timing(1 << K_APPLY)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(args.steps)
-    b.synchronize()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kt = b.kernel_times()
-    b.set_kernel_timing(0)
-    per, mx, its, st = b.residual()
-    hist_max, hist_over = b.residual_history(reset=True)
-    stats = b.stats()
-    value = args.envs * args.steps / dt
-    ms_step = 1000.0 * dt / args.steps
+    b, dt, kt, mx1, over1, its1 = run_arm(F, sc, args, use_graph=False, warm_start=F.FLASH_WS_PREV,
+                                          time_apply=True)
+    log(f"plain arm: {1000 * dt / args.steps:.2f} ms/step ({time.time() - t0:.0f}s with create)")
+    v_plain = args.envs * args.steps / dt
     apply_ms, apply_n = kt["apply"]
     apply_avg = apply_ms / max(apply_n, 1)
     bpl = apply_bytes_per_launch(nv)
     achieved = bpl / (apply_avg * 1e-3) / 1e9
-    log(f"timed {args.steps} steps: {ms_step:.2f} ms/step, {value:.0f} env-steps/s; apply avg {apply_avg:.3f} ms")
+    stats = b.stats()
+    breakdown = {k: round(v[0] / args.steps, 3) for k, v in kt.items() if v[1]}
+    b.close()
 
-    breakdown, value_g, dt_g, mx_g = {}, None, None, None
+    arms = {"plain_eager": {"env_steps_per_s": round(v_plain, 2), "ms_per_step": round(1000 * dt / args.steps, 3),
+                            "max_residual": mx1, "env_steps_above_tol": over1,
+                            "newton_per_env_step": round(its1, 2)}}
+    value, dt_v, mx_v, over_v, dtype_arm = v_plain, dt, mx1, over1, "plain_eager"
+    training, mlp_roof = None, None
     if not args.quick:
-        # per-kernel breakdown (separate pass, every class timed)
-        b.set_kernel_timing(True)
-        b.step(2)
-        b.synchronize()
-        breakdown = {k: round(v[0] / 2, 3) for k, v in b.kernel_times().items() if v[1]}
-        b.set_kernel_timing(0)
-        # graph-captured variant of the same step
-        g = F.from_scene(scenes.squeeze_blocks(args.envs, seed=0), use_graph=True)
-        g.step(args.warmup)
-        g.synchronize()
-        t0 = time.perf_counter()
-        g.step(args.steps)
-        g.synchronize()
-        dt_g = time.perf_counter() - t0
-        _, mx_g, _, _ = g.residual()
-        value_g = args.envs * args.steps / dt_g
-        log(f"graph arm: {1000 * dt_g / args.steps:.2f} ms/step, {value_g:.0f} env-steps/s")
-        del g
+        # A2: batched (whole step captured in one HIP graph), previous-step warm start
+        b, dt2, _, mx2, over2, its2 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV)
+        b.close()
+        arms["graph"] = {"env_steps_per_s": round(args.envs * args.steps / dt2, 2),
+                         "ms_per_step": round(1000 * dt2 / args.steps, 3), "max_residual": mx2,
+                         "env_steps_above_tol": over2, "newton_per_env_step": round(its2, 2)}
+        log(f"graph arm: {1000 * dt2 / args.steps:.2f} ms/step")
+        # A3: batched + learned warm start (training excluded from the timed region, reported)
+        w, nm, training = train_warm_start(F, scenes, torch)
+        log(f"trained warm start on {training['pairs']} pairs in {training['train_s']}s")
+        b, dt3, _, mx3, over3, its3 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_LEARNED,
+                                              ws=(w, nm))
+        picks = sum(s_["ws_state"] & 1 for s_ in b.stats())
+        b.close()
+        arms["graph_learned"] = {"env_steps_per_s": round(args.envs * args.steps / dt3, 2),
+                                 "ms_per_step": round(1000 * dt3 / args.steps, 3), "max_residual": mx3,
+                                 "env_steps_above_tol": over3, "newton_per_env_step": round(its3, 2),
+                                 "envs_started_from_prediction_last_step": int(picks)}
+        log(f"graph+learned arm: {1000 * dt3 / args.steps:.2f} ms/step")
+        value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "graph_learned"
+        mlp_roof = mlp_roofline(F, torch)
+        log(f"network forward: {mlp_roof['achieved']} TFLOP/s")
+
+    gemv_hash = kernel_source_hash(os.path.join(ROOT, "paper_2604_17513_amd", "csrc", "flash_kernels.hip"), "k_gemv")
+    traffic, _ = committed_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_squeeze_blocks_1024.md"), gemv_hash)
+    if args.envs != 1024:
+        traffic = None
 
     out = {
         "metric": METRIC,
@@ -170,7 +291,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(1000.0 * dt_v / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -178,41 +299,39 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "squeeze_blocks: 1024 envs x 10^3-hex block (1331 v, 6000 tets), two box fingers + ground, "
-                        "h=1/60, K=20 local-global iterations, FP32, every contact solve to NCP residual <= 1e-6",
+                        "h=1/60, K=20 local-global iterations, FP32 (contact-space solve FP64), every contact "
+                        "solve to NCP residual <= 1e-6; steps 10-40 of the squeeze",
+            "arm_reported_as_value": dtype_arm,
             "n_envs": args.envs,
             "vertices_per_env": nv[0],
             "tets_per_env": int(sc.envs[0].n_elements),
-            "contacts_per_env_mean": round(float(np.mean([s["contacts"] for s in stats])), 1),
+            "contacts_per_env_mean": round(float(np.mean([s_["contacts"] for s_ in stats])), 1),
             "lg_iterations": sc.params.lg_iterations,
             "ncp_tol": sc.params.ncp_tol,
-            "warm_start": "previous-step",
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "apply (explicit-inverse global solve, k_gemv)",
+            "kernel": "apply (explicit-inverse global solve, k_gemv<float,false>)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "bytes_per_launch": bpl,
             "avg_launch_ms": round(apply_avg, 4),
             "launches": apply_n,
+            "kernel_source_sha256": gemv_hash,
         },
-        "max_residual": hist_max,
-        "env_steps_above_tol": hist_over,
-        "residual_ok": bool(hist_max <= sc.params.ncp_tol),
-        "newton_iters_per_step_mean": round(float(np.mean(its)), 2),
-        "arms": {
-            "plain_eager": {"env_steps_per_s": round(value, 2), "ms_per_step": round(ms_step, 3),
-                            "max_residual": mx},
-            "graph": None if value_g is None else {
-                "env_steps_per_s": round(value_g, 2), "ms_per_step": round(1000 * dt_g / args.steps, 3),
-                "max_residual": mx_g},
-        },
+        "max_residual": mx_v,
+        "env_steps_above_tol": over_v,
+        "residual_ok": bool(mx_v <= sc.params.ncp_tol),
+        "arms": arms,
         "kernel_ms_per_step": breakdown,
-        "precompute_s": round(precompute_s, 2),
     }
+    if mlp_roof is not None:
+        out["roofline_network"] = mlp_roof
+    if training is not None:
+        out["warm_start_training"] = training
 
     if args.copy_probe:
         n = 1 << 28

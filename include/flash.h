@@ -184,10 +184,13 @@ flash_status flash_contacts(flash_batch *b, int32_t env, flash_contact *out, int
 flash_status flash_residual(flash_batch *b, double *per_env, double *max_out, int32_t *inner_iters);
 flash_status flash_stats(flash_batch *b, flash_env_stats *per_env);
 
-/* Worst end-of-step NCP residual over all envs and steps since the previous
- * reset (*max_out, metres) and the number of env-steps that ended above
- * ncp_tol (*over_out).  reset != 0 clears both after reading. */
-flash_status flash_residual_history(flash_batch *b, double *max_out, int64_t *over_out, int32_t reset);
+/* Statistics over all envs and steps since the previous reset: worst
+ * end-of-step NCP residual (*max_out, metres), env-steps that ended above
+ * ncp_tol (*over_out), Newton iterations summed over every contact solve
+ * (*newton_out) and env-steps taken (*env_steps_out).  Any output may be
+ * NULL; reset != 0 clears the statistics after reading. */
+flash_status flash_residual_history(flash_batch *b, double *max_out, int64_t *over_out,
+                                    int64_t *newton_out, int64_t *env_steps_out, int32_t reset);
 
 /* Per-kernel timing with HIP events recorded on the batch's stream around each
  * launch of the kernel classes selected by `enable` (bit k = class k in the

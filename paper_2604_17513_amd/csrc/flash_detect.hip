@@ -304,8 +304,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, sh_red[w]);
     B.resid[e] = m;
     // worst residual and over-tolerance step count since the last statistics reset
-    B.resid_hist[2 * e] = fmax(B.resid_hist[2 * e], m);
-    if (!(m <= B.ncp_tol)) B.resid_hist[2 * e + 1] += 1.0;
+    double* hist = B.resid_hist + 4 * e;
+    hist[0] = (m == m) ? fmax(hist[0], m) : INFINITY;
+    if (!(m <= B.ncp_tol)) hist[1] += 1.0;
+    hist[2] += (double)B.iters[e];
+    hist[3] += 1.0;
   }
   if (bad) atomicOr(&B.flags[e], 1);
   __syncthreads();

@@ -106,7 +106,8 @@ struct DevBatch {
 
   // per env outputs
   double* resid;              // [n_envs]
-  double* resid_hist;         // [2 per env] max residual and count of steps above ncp_tol since reset
+  double* resid_hist;         // [4 per env] since the last reset: max residual, steps above ncp_tol,
+                              // Newton iterations, steps
   double ncp_tol;             // acceptance tolerance of the end-of-step residual
   int* iters;                 // [n_envs] Newton iterations this step
   int* refac;                 // [n_envs]

@@ -475,8 +475,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   }
   B.resid = dalloc<double>(ne, own);
   HIPCHK(hipMemset(B.resid, 0, ne * sizeof(double)));
-  B.resid_hist = dalloc<double>(2 * (size_t)ne, own);
-  HIPCHK(hipMemset(B.resid_hist, 0, 2 * (size_t)ne * sizeof(double)));
+  B.resid_hist = dalloc<double>(4 * (size_t)ne, own);
+  HIPCHK(hipMemset(B.resid_hist, 0, 4 * (size_t)ne * sizeof(double)));
   B.ncp_tol = b->p.ncp_tol;
   B.iters = dalloc<int>(ne, own);
   B.refac = dalloc<int>(ne, own);
@@ -843,22 +843,28 @@ flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launc
   return FLASH_OK;
 }
 
-flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* over_out, int32_t reset) {
+flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* over_out, int64_t* newton_out,
+                                    int64_t* env_steps_out, int32_t reset) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
   try {
     HIPCHK(hipStreamSynchronize(b->stream));
     const int ne = b->n_envs;
     double* dp = b->fp64 ? b->bd.resid_hist : b->bf.resid_hist;
-    std::vector<double> h(2 * (size_t)ne);
+    std::vector<double> h(4 * (size_t)ne);
     HIPCHK(hipMemcpy(h.data(), dp, h.size() * sizeof(double), hipMemcpyDeviceToHost));
     double m = 0.0;
-    int64_t over = 0;
+    int64_t over = 0, newton = 0, steps = 0;
     for (int e = 0; e < ne; ++e) {
-      m = (h[2 * e] > m || !(h[2 * e] == h[2 * e])) ? h[2 * e] : m;
-      over += (int64_t)h[2 * e + 1];
+      const double* q = h.data() + 4 * (size_t)e;
+      m = (q[0] > m || !(q[0] == q[0])) ? q[0] : m;
+      over += (int64_t)q[1];
+      newton += (int64_t)q[2];
+      steps += (int64_t)q[3];
     }
     if (max_out) *max_out = m;
     if (over_out) *over_out = over;
+    if (newton_out) *newton_out = newton;
+    if (env_steps_out) *env_steps_out = steps;
     if (reset) HIPCHK(hipMemset(dp, 0, h.size() * sizeof(double)));
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());

@@ -103,7 +103,8 @@ def lib():
         L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
         L.flash_residual.argtypes = [P, D, D, C.POINTER(I32)]
         L.flash_stats.argtypes = [P, C.POINTER(flash_env_stats)]
-        L.flash_residual_history.argtypes = [P, D, C.POINTER(C.c_int64), I32]
+        L.flash_residual_history.argtypes = [P, D, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                             C.POINTER(C.c_int64), I32]
         L.flash_set_kernel_timing.argtypes = [P, I32]
         L.flash_kernel_times.argtypes = [P, D, C.POINTER(C.c_int64), I32, C.POINTER(I32)]
         L.flash_kernel_name.argtypes = [I32]
@@ -300,11 +301,15 @@ class Batch:
         _check(st, allow=(FLASH_ERR_NOT_CONVERGED, FLASH_ERR_NONFINITE))
         return per, mx.value, its, st
 
-    def residual_history(self, reset: bool = True):
-        """(worst residual, number of env-steps above ncp_tol) since the last reset."""
+    def residual_history(self, reset: bool = True, full: bool = False):
+        """(worst residual, env-steps above ncp_tol) since the last reset; with full=True also
+        (Newton iterations, env-steps)."""
         mx = C.c_double()
-        over = C.c_int64()
-        _check(lib().flash_residual_history(self._h, C.byref(mx), C.byref(over), 1 if reset else 0))
+        over, newton, steps = C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().flash_residual_history(self._h, C.byref(mx), C.byref(over), C.byref(newton), C.byref(steps),
+                                            1 if reset else 0))
+        if full:
+            return mx.value, over.value, newton.value, steps.value
         return mx.value, over.value
 
     def stats(self):
