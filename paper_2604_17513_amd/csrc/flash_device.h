@@ -57,8 +57,13 @@ struct DevBatch {
   const T* tet_B;             // [9*NT] D_m^-1 row-major (B[r][c] at (3r+c)*NT)
   const T* tet_w;             // [NT]
   T* fel;                     // [3 per incidence] vertex forces w (p - F_x) gradN_a, vertex-ordered
-  const int* inc_off;         // [NV+1] incidence ranges per vertex
-  const int* slot;            // [4*NT] incidence slot of (tet t, local vertex a) at t*4+a
+  const int* inc_off;         // [NV+1] incidence ranges per vertex (element slots, then hinge slots)
+  const int* slot;            // [4*NT] incidence slot of (element t, local vertex a) at t*4+a (-1: none)
+  int NH;                     // bending hinges over all envs
+  const int* hinge_idx;       // [4*NH] global vertex ids (edge x0 x1, opposite x2 x3)
+  const T* hinge_alpha;       // [4*NH] stencil alpha
+  const T* hinge_w;           // [NH] weight w_h
+  const int* hinge_slot;      // [4*NH] incidence slots
 
   const T* G;                 // dense inverses
   const int64_t* goff;        // [n_envs] element offset of env block

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -44,10 +45,13 @@ flash_status fail(flash_status s, const std::string& m) { return record_error(s,
 // ----------------------------------------------------------------------------
 struct HostEnv {
   int n = 0, m = 0, k = 4;
-  std::vector<int> elem;      // oriented, k per element
-  std::vector<double> Bm;     // 9 per tet
+  std::vector<int> elem;      // 4 per element: oriented tet, or triangle + (-1)
+  std::vector<double> Bm;     // 9 per element: D_m^-1 (tets, 3x3) or the 2x2 D_m^-1 in entries 0..3 (triangles)
   std::vector<double> w;      // per element
   std::vector<double> mass;   // per vertex
+  std::vector<int> hidx;      // 4 per bending hinge (edge x0 x1, opposite x2 x3)
+  std::vector<double> halpha; // 4 per hinge
+  std::vector<double> hw;     // per hinge
   std::vector<double> Ginv;   // n*n symmetric
 };
 
@@ -89,16 +93,107 @@ void tet_data(const flash_env_desc& d, HostEnv& H) {
   }
 }
 
+// Membrane triangles (Sec. III-B projective constraints with the closest matrix of
+// orthonormal columns): rest frame e1 = unit(X1 - X0), n = unit((X1 - X0) x (X2 - X0)),
+// e2 = n x e1; D_m = rest edge coordinates in (e1, e2), B = D_m^-1; F = [x1 - x0 | x2 - x0] B;
+// w = 2 mu_L A t; lumped mass rho t A / 3 per vertex.  Bending hinges on interior edges,
+// flat rest state, target p = 0: G_h q = sum alpha_a x_a with alpha_2 = 1/d_2,
+// alpha_3 = 1/d_3 (rest distances of the opposite vertices to the edge line) and
+// alpha_0, alpha_1 from sum alpha = 0, sum alpha X = 0; w_h = 3 k_b |e|^2 / (A_1 + A_2).
+void tri_data(const flash_env_desc& d, HostEnv& H) {
+  const int n = d.n_vertices, m = d.n_elements;
+  H.n = n; H.m = m; H.k = 3;
+  H.elem.assign(4 * (size_t)m, -1);
+  H.Bm.assign(9 * (size_t)m, 0.0);
+  H.w.resize(m);
+  H.mass.assign(n, 0.0);
+  const double muL = d.young / (2.0 * (1.0 + d.poisson));
+  auto X = [&](int v, int c) { return d.rest_x[3 * (size_t)v + c]; };
+  std::vector<double> area(m);
+  for (int t = 0; t < m; ++t) {
+    int id[3];
+    for (int a = 0; a < 3; ++a) {
+      id[a] = d.elements[3 * (size_t)t + a];
+      if (id[a] < 0 || id[a] >= n) throw FlashError(FLASH_ERR_INVALID_ARG, "element index out of range");
+      H.elem[4 * (size_t)t + a] = id[a];
+    }
+    double E1[3], E2[3], nn[3], e1[3], e2[3];
+    for (int c = 0; c < 3; ++c) { E1[c] = X(id[1], c) - X(id[0], c); E2[c] = X(id[2], c) - X(id[0], c); }
+    nn[0] = E1[1] * E2[2] - E1[2] * E2[1];
+    nn[1] = E1[2] * E2[0] - E1[0] * E2[2];
+    nn[2] = E1[0] * E2[1] - E1[1] * E2[0];
+    const double l1 = std::sqrt(E1[0] * E1[0] + E1[1] * E1[1] + E1[2] * E1[2]);
+    const double ln = std::sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    if (!(l1 > 0) || !(ln > 0)) throw FlashError(FLASH_ERR_INVALID_ARG, "degenerate rest triangle");
+    for (int c = 0; c < 3; ++c) { e1[c] = E1[c] / l1; nn[c] /= ln; }
+    e2[0] = nn[1] * e1[2] - nn[2] * e1[1];
+    e2[1] = nn[2] * e1[0] - nn[0] * e1[2];
+    e2[2] = nn[0] * e1[1] - nn[1] * e1[0];
+    const double D00 = E1[0] * e1[0] + E1[1] * e1[1] + E1[2] * e1[2];
+    const double D01 = E2[0] * e1[0] + E2[1] * e1[1] + E2[2] * e1[2];
+    const double D10 = E1[0] * e2[0] + E1[1] * e2[1] + E1[2] * e2[2];
+    const double D11 = E2[0] * e2[0] + E2[1] * e2[1] + E2[2] * e2[2];
+    const double det = D00 * D11 - D01 * D10;
+    if (!(std::fabs(det) > 0)) throw FlashError(FLASH_ERR_INVALID_ARG, "degenerate rest triangle");
+    double* Bt = &H.Bm[9 * (size_t)t];
+    Bt[0] = D11 / det; Bt[1] = -D01 / det; Bt[2] = -D10 / det; Bt[3] = D00 / det;
+    area[t] = std::fabs(det) / 2.0;
+    H.w[t] = 2.0 * muL * area[t] * d.thickness;
+    for (int a = 0; a < 3; ++a) H.mass[id[a]] += d.density * d.thickness * area[t] / 3.0;
+  }
+  if (!(d.bending > 0)) return;
+  // interior edges: (min vertex, max vertex) -> (triangle, opposite vertex) x 2
+  std::map<std::pair<int, int>, std::vector<std::pair<int, int>>> edges;
+  for (int t = 0; t < m; ++t) {
+    const int* id = &H.elem[4 * (size_t)t];
+    for (int a = 0; a < 3; ++a) {
+      const int u = id[a], v = id[(a + 1) % 3], o = id[(a + 2) % 3];
+      edges[{std::min(u, v), std::max(u, v)}].push_back({t, o});
+    }
+  }
+  for (const auto& kv : edges) {
+    if (kv.second.size() != 2) continue;
+    const int i0 = kv.first.first, i1 = kv.first.second;
+    const int w2 = kv.second[0].second, w3 = kv.second[1].second;
+    double e[3], L2 = 0.0;
+    for (int c = 0; c < 3; ++c) { e[c] = X(i1, c) - X(i0, c); L2 += e[c] * e[c]; }
+    const double L = std::sqrt(L2);
+    double proj[2], dist[2];
+    const int opp[2] = {w2, w3};
+    for (int q = 0; q < 2; ++q) {
+      double r[3], a = 0.0;
+      for (int c = 0; c < 3; ++c) { r[c] = X(opp[q], c) - X(i0, c); a += r[c] * e[c] / L; }
+      double d2 = 0.0;
+      for (int c = 0; c < 3; ++c) { const double z = r[c] - a * e[c] / L; d2 += z * z; }
+      proj[q] = a;
+      dist[q] = std::sqrt(d2);
+    }
+    if (!(dist[0] > 0) || !(dist[1] > 0)) throw FlashError(FLASH_ERR_INVALID_ARG, "degenerate hinge");
+    const double al2 = 1.0 / dist[0], al3 = 1.0 / dist[1];
+    const double al1 = -(al2 * proj[0] + al3 * proj[1]) / L;
+    const double al0 = -(al1 + al2 + al3);
+    const double A1 = area[kv.second[0].first], A2 = area[kv.second[1].first];
+    H.hidx.insert(H.hidx.end(), {i0, i1, w2, w3});
+    H.halpha.insert(H.halpha.end(), {al0, al1, al2, al3});
+    H.hw.push_back(3.0 * d.bending * L2 / (A1 + A2));
+  }
+}
+
 // Skyline (profile) Cholesky of Abar followed by the explicit inverse.
 void system_inverse(const flash_env_desc& d, HostEnv& H, double h, int nthreads) {
+  (void)d;
   const int n = H.n, m = H.m;
   std::vector<int> first(n);
   for (int i = 0; i < n; ++i) first[i] = i;
-  for (int t = 0; t < m; ++t) {
-    const int* id = &H.elem[4 * (size_t)t];
-    int lo = std::min(std::min(id[0], id[1]), std::min(id[2], id[3]));
-    for (int a = 0; a < 4; ++a) first[id[a]] = std::min(first[id[a]], lo);
-  }
+  const int k = H.k;
+  auto profile = [&](const int* id, int cnt) {
+    int lo = id[0];
+    for (int a = 1; a < cnt; ++a) lo = std::min(lo, id[a]);
+    for (int a = 0; a < cnt; ++a) first[id[a]] = std::min(first[id[a]], lo);
+  };
+  for (int t = 0; t < m; ++t) profile(&H.elem[4 * (size_t)t], k);
+  const int nh = (int)H.hw.size();
+  for (int q = 0; q < nh; ++q) profile(&H.hidx[4 * (size_t)q], 4);
   std::vector<size_t> rp(n + 1, 0);
   for (int i = 0; i < n; ++i) rp[i + 1] = rp[i] + (size_t)(i - first[i] + 1);
   std::vector<double> L(rp[n], 0.0);
@@ -108,17 +203,34 @@ void system_inverse(const flash_env_desc& d, HostEnv& H, double h, int nthreads)
   for (int t = 0; t < m; ++t) {
     const int* id = &H.elem[4 * (size_t)t];
     const double* Bt = &H.Bm[9 * (size_t)t];
-    double gN[4][3];
-    for (int c = 0; c < 3; ++c) {
-      gN[1][c] = Bt[c]; gN[2][c] = Bt[3 + c]; gN[3][c] = Bt[6 + c];
-      gN[0][c] = -(Bt[c] + Bt[3 + c] + Bt[6 + c]);
+    double gN[4][3] = {};
+    if (k == 4) {
+      for (int c = 0; c < 3; ++c) {
+        gN[1][c] = Bt[c]; gN[2][c] = Bt[3 + c]; gN[3][c] = Bt[6 + c];
+        gN[0][c] = -(Bt[c] + Bt[3 + c] + Bt[6 + c]);
+      }
+    } else {
+      for (int c = 0; c < 2; ++c) {
+        gN[1][c] = Bt[c]; gN[2][c] = Bt[2 + c];
+        gN[0][c] = -(Bt[c] + Bt[2 + c]);
+      }
     }
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) {
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) {
         int i = id[a], j = id[b];
         if (j > i) continue;
         double v = hh * H.w[t] * (gN[a][0] * gN[b][0] + gN[a][1] * gN[b][1] + gN[a][2] * gN[b][2]);
         at(i, j) += v;
+      }
+  }
+  for (int q = 0; q < nh; ++q) {
+    const int* id = &H.hidx[4 * (size_t)q];
+    const double* al = &H.halpha[4 * (size_t)q];
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) {
+        const int i = id[a], j = id[b];
+        if (j > i) continue;
+        at(i, j) += hh * H.hw[q] * al[a] * al[b];
       }
   }
   // Crout factorisation in place
@@ -255,7 +367,10 @@ struct flash_batch {
   template <class T>
   void enqueue_step(const DevBatch<T>& B) {
     const T* mu_d = static_cast<const T*>(mu_dev);
-    launch(K_DETECT, [&] { launch_detect<T>(B, mu_d, stream); });
+    launch(K_DETECT, [&] {
+      launch_detect<T>(B, mu_d, stream);
+      launch_hinge<T>(B, stream);
+    });
     const bool infer = ws_loaded && p.warm_start == FLASH_WS_LEARNED;
     if (infer || ws_record) {
       launch(K_MLP, [&] {
@@ -363,17 +478,47 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
       for (int k = 0; k < 3; ++k) x[(size_t)k * NV + vo + i] = (T)envs[e].rest_x[3 * i + k];
     }
     for (int t = 0; t < h.m; ++t) {
-      for (int a = 0; a < 4; ++a) tidx[(size_t)a * NT + to + t] = vo + h.elem[4 * (size_t)t + a];
+      for (int a = 0; a < 4; ++a) {
+        const int v = h.elem[4 * (size_t)t + a];
+        tidx[(size_t)a * NT + to + t] = v < 0 ? -1 : vo + v;   // -1: triangle
+        if (v >= 0) inc_off[vo + v + 1] += 1;
+      }
       for (int q = 0; q < 9; ++q) tB[(size_t)q * NT + to + t] = (T)h.Bm[9 * (size_t)t + q];
       tw[to + t] = (T)h.w[t];
-      for (int a = 0; a < 4; ++a) inc_off[vo + h.elem[4 * (size_t)t + a] + 1] += 1;
+    }
+  }
+  // bending hinges (4 incidences each), after the elements
+  int NH = 0;
+  for (int e = 0; e < ne; ++e) NH += (int)H[e].hw.size();
+  std::vector<int> hidx(4 * (size_t)NH), hslot(4 * (size_t)NH);
+  std::vector<T> halpha(4 * (size_t)NH), hw(NH);
+  {
+    int q0 = 0;
+    for (int e = 0; e < ne; ++e) {
+      const HostEnv& h = H[e];
+      const int vo = b->voff[e], nh = (int)h.hw.size();
+      for (int q = 0; q < nh; ++q) {
+        for (int a = 0; a < 4; ++a) {
+          const int v = vo + h.hidx[4 * (size_t)q + a];
+          hidx[(size_t)a * NH + q0 + q] = v;
+          halpha[(size_t)a * NH + q0 + q] = (T)h.halpha[4 * (size_t)q + a];
+          inc_off[v + 1] += 1;
+        }
+        hw[q0 + q] = (T)h.hw[q];
+      }
+      q0 += nh;
     }
   }
   for (int i = 0; i < NV; ++i) inc_off[i + 1] += inc_off[i];
   {
     std::vector<int> fillp(inc_off.begin(), inc_off.end() - 1);
     for (int t = 0; t < NT; ++t)
-      for (int a = 0; a < 4; ++a) slot[(size_t)t * 4 + a] = fillp[tidx[(size_t)a * NT + t]]++;
+      for (int a = 0; a < 4; ++a) {
+        const int v = tidx[(size_t)a * NT + t];
+        slot[(size_t)t * 4 + a] = v < 0 ? -1 : fillp[v]++;
+      }
+    for (int q = 0; q < NH; ++q)
+      for (int a = 0; a < 4; ++a) hslot[(size_t)a * NH + q] = fillp[hidx[(size_t)a * NH + q]]++;
   }
   // dense inverses
   std::vector<int64_t> goff(ne);
@@ -420,9 +565,15 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   int* d_tidx = dalloc<int>(4 * (size_t)NT, own); up(d_tidx, tidx); B.tet_idx = d_tidx;
   T* d_tB = dalloc<T>(9 * (size_t)NT, own); up(d_tB, tB); B.tet_B = d_tB;
   T* d_tw = dalloc<T>(NT, own); up(d_tw, tw); B.tet_w = d_tw;
-  B.fel = dalloc<T>(12 * (size_t)NT, own);
+  B.fel = dalloc<T>(3 * (size_t)inc_off[NV], own);
+  HIPCHK(hipMemset(B.fel, 0, 3 * (size_t)inc_off[NV] * sizeof(T)));
   int* d_io = dalloc<int>(NV + 1, own); up(d_io, inc_off); B.inc_off = d_io;
   int* d_slot = dalloc<int>(4 * (size_t)NT, own); up(d_slot, slot); B.slot = d_slot;
+  B.NH = NH;
+  int* d_hidx = dalloc<int>(4 * (size_t)NH, own); if (NH) up(d_hidx, hidx); B.hinge_idx = d_hidx;
+  T* d_hal = dalloc<T>(4 * (size_t)NH, own); if (NH) up(d_hal, halpha); B.hinge_alpha = d_hal;
+  T* d_hw = dalloc<T>(NH, own); if (NH) up(d_hw, hw); B.hinge_w = d_hw;
+  int* d_hsl = dalloc<int>(4 * (size_t)NH, own); if (NH) up(d_hsl, hslot); B.hinge_slot = d_hsl;
   B.G = G;
   int64_t* d_goff = dalloc<int64_t>(ne, own); up(d_goff, goff); B.goff = d_goff;
   int* d_gld = dalloc<int>(ne, own); up(d_gld, gld); B.gld = d_gld;
@@ -684,7 +835,9 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     return fail(FLASH_ERR_INVALID_ARG, "precision must be FLASH_FP32 or FLASH_FP64");
   for (int e = 0; e < n_envs; ++e) {
     const flash_env_desc& d = envs[e];
-    if (d.elem != FLASH_TET) return fail(FLASH_ERR_UNSUPPORTED, "only FLASH_TET environments are built");
+    if (d.elem != FLASH_TET && d.elem != FLASH_TRI) return fail(FLASH_ERR_INVALID_ARG, "unknown element kind");
+    if (d.elem == FLASH_TRI && (!(d.thickness > 0) || !(d.bending >= 0)))
+      return fail(FLASH_ERR_INVALID_ARG, "triangle environments need thickness > 0 and bending >= 0");
     if (d.n_vertices <= 0 || d.n_elements <= 0 || !d.rest_x || !d.elements)
       return fail(FLASH_ERR_INVALID_ARG, "empty environment");
     if (!(d.density > 0) || !(d.young > 0) || !(d.poisson > -1 && d.poisson < 0.5) || !(d.mu >= 0))
@@ -713,7 +866,7 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     std::vector<HostEnv> H(n_envs);
     const int nth = std::max(1u, std::thread::hardware_concurrency());
     for (int e = 0; e < n_envs; ++e) {
-      tet_data(envs[e], H[e]);
+      if (envs[e].elem == FLASH_TET) tet_data(envs[e], H[e]); else tri_data(envs[e], H[e]);
       system_inverse(envs[e], H[e], p->h, nth);
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);

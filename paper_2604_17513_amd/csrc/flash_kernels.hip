@@ -185,6 +185,115 @@ __device__ void polar_svd64(const double* F, double* R) {
 // ---------------------------------------------------------------------------
 // local projection (Eq. 3) and per-tet vertex forces w (p - F(x_t)) gradN_a
 // ---------------------------------------------------------------------------
+// Closest matrix with orthonormal columns to a 3x2 F in FP64: eigenvectors v1, v2 of
+// S = F^T F (2x2, closed form), u_i = F v_i / sigma_i, and for a rank-deficient F a unit u2
+// orthogonal to u1; R = u1 v1^T + u2 v2^T.
+__device__ void ortho_cols64(const double* F, double* R) {
+  const double s00 = F[0] * F[0] + F[2] * F[2] + F[4] * F[4];
+  const double s01 = F[0] * F[1] + F[2] * F[3] + F[4] * F[5];
+  const double s11 = F[1] * F[1] + F[3] * F[3] + F[5] * F[5];
+  const double hd = 0.5 * (s00 - s11), rt = sqrt(hd * hd + s01 * s01);
+  const double l1 = 0.5 * (s00 + s11) + rt;
+  double v1[2];
+  if (rt > 0) {
+    // eigenvector of the larger eigenvalue, from the better-conditioned row
+    if (hd >= 0) { v1[0] = hd + rt; v1[1] = s01; } else { v1[0] = s01; v1[1] = rt - hd; }
+    const double nv = sqrt(v1[0] * v1[0] + v1[1] * v1[1]);
+    v1[0] /= nv; v1[1] /= nv;
+  } else { v1[0] = 1.0; v1[1] = 0.0; }
+  const double v2[2] = {-v1[1], v1[0]};
+  double u1[3], u2[3];
+  for (int r = 0; r < 3; ++r) {
+    u1[r] = F[2 * r] * v1[0] + F[2 * r + 1] * v1[1];
+    u2[r] = F[2 * r] * v2[0] + F[2 * r + 1] * v2[1];
+  }
+  double n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  if (!(n1 > 0)) { u1[0] = 1.0; u1[1] = 0.0; u1[2] = 0.0; n1 = 1.0; }
+  for (int r = 0; r < 3; ++r) u1[r] /= n1;
+  // Gram-Schmidt against u1; a vanishing remainder takes any direction orthogonal to u1
+  double d = u1[0] * u2[0] + u1[1] * u2[1] + u1[2] * u2[2];
+  for (int r = 0; r < 3; ++r) u2[r] -= d * u1[r];
+  double n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  if (!(n2 > 1e-12 * sqrt(fmax(l1, 0.0)))) {
+    const int k = (fabs(u1[0]) <= fabs(u1[1]) && fabs(u1[0]) <= fabs(u1[2])) ? 0 : (fabs(u1[1]) <= fabs(u1[2]) ? 1 : 2);
+    double ek[3] = {0.0, 0.0, 0.0};
+    ek[k] = 1.0;
+    u2[0] = u1[1] * ek[2] - u1[2] * ek[1];
+    u2[1] = u1[2] * ek[0] - u1[0] * ek[2];
+    u2[2] = u1[0] * ek[1] - u1[1] * ek[0];
+    n2 = sqrt(u2[0] * u2[0] + u2[1] * u2[1] + u2[2] * u2[2]);
+  }
+  for (int r = 0; r < 3; ++r) u2[r] /= n2;
+  for (int r = 0; r < 3; ++r) {
+    R[2 * r] = u1[r] * v1[0] + u2[r] * v2[0];
+    R[2 * r + 1] = u1[r] * v1[1] + u2[r] * v2[1];
+  }
+}
+
+// Membrane triangle: F = [x1 - x0 | x2 - x0] B (3x2, B = D_m^-1 2x2 in tet_B entries 0..3),
+// p = the closest matrix with orthonormal columns, F S^-1/2 with S = F^T F in closed form
+// (sqrt S = (S + sqrt(det S) I) / sqrt(tr S + 2 sqrt(det S))); nearly rank-deficient F
+// (det S < 1e-4 (tr S / 2)^2) goes to the FP64 eigen path.  Forces w (p - F_x) gradN_a.
+template <class T>
+__device__ void project_tri(const DevBatch<T>& B, int t, const int* id) {
+  const int NT = B.NT, NV = B.NV;
+  T dx[2][3], du[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int k = 0; k < 3; ++k) {
+      dx[a][k] = B.x[k * NV + id[a + 1]] - B.x[k * NV + id[0]];
+      du[a][k] = B.u[k * NV + id[a + 1]] - B.u[k * NV + id[0]];
+    }
+  T Bm[4];
+  for (int k = 0; k < 4; ++k) Bm[k] = B.tet_B[k * NT + t];
+  T F[6], Fx[6];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 2; ++c) {
+      T f = 0, fx = 0;
+      for (int a = 0; a < 2; ++a) {
+        fx += dx[a][r] * Bm[2 * a + c];
+        f += (dx[a][r] + du[a][r]) * Bm[2 * a + c];
+      }
+      F[2 * r + c] = f;
+      Fx[2 * r + c] = fx;
+    }
+  const T s00 = F[0] * F[0] + F[2] * F[2] + F[4] * F[4];
+  const T s01 = F[0] * F[1] + F[2] * F[3] + F[4] * F[5];
+  const T s11 = F[1] * F[1] + F[3] * F[3] + F[5] * F[5];
+  const T det = s00 * s11 - s01 * s01, tr = s00 + s11;
+  T R[6];
+  if (det > T(1e-4) * T(0.25) * tr * tr) {
+    const T r = sqrt(det), dsq = sqrt(tr + T(2) * r);
+    // inverse of (S + r I) / dsq
+    const T a00 = s00 + r, a11 = s11 + r;
+    const T idet = dsq / (a00 * a11 - s01 * s01);
+    const T i00 = a11 * idet, i01 = -s01 * idet, i11 = a00 * idet;
+    for (int q = 0; q < 3; ++q) {
+      R[2 * q] = F[2 * q] * i00 + F[2 * q + 1] * i01;
+      R[2 * q + 1] = F[2 * q] * i01 + F[2 * q + 1] * i11;
+    }
+  } else {
+    double Fd[6], Rd[6];
+    for (int k = 0; k < 6; ++k) Fd[k] = (double)F[k];
+    ortho_cols64(Fd, Rd);
+    for (int k = 0; k < 6; ++k) R[k] = (T)Rd[k];
+    atomicAdd(&B.fp64_polar[B.tet_env[t]], 1);
+  }
+  const T w = B.tet_w[t];
+  T P[6];
+  for (int k = 0; k < 6; ++k) P[k] = w * (R[k] - Fx[k]);
+  T f0[3] = {0, 0, 0};
+  for (int a = 0; a < 2; ++a) {
+    T* dst = B.fel + 3 * (size_t)B.slot[4 * (size_t)t + a + 1];
+    for (int r = 0; r < 3; ++r) {
+      const T fa = P[2 * r] * Bm[2 * a] + P[2 * r + 1] * Bm[2 * a + 1];
+      dst[r] = fa;
+      f0[r] -= fa;
+    }
+  }
+  T* dst0 = B.fel + 3 * (size_t)B.slot[4 * (size_t)t];
+  for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
   const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -192,6 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
   const int NT = B.NT, NV = B.NV;
   int id[4];
   for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * NT + t];
+  if (id[3] < 0) { project_tri(B, t, id); return; }
   T X0[3], U0[3], dx[3][3], du[3][3];
   for (int k = 0; k < 3; ++k) { X0[k] = B.x[k * NV + id[0]]; U0[k] = B.u[k * NV + id[0]]; }
   for (int a = 0; a < 3; ++a)
@@ -247,21 +357,68 @@ __global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
   for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
 }
 
+// Bending hinges have the target p = 0, so in displacement form each contributes the
+// constant (per step) force w_h G_h^T (0 - G_h x) = -w_h alpha_a (sum_b alpha_b x_b) to its
+// four vertices; written once per step into the hinge slots that the assembly gathers.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_hinge(DevBatch<T> B) {
+  const int q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= B.NH) return;
+  const int NV = B.NV, NH = B.NH;
+  int id[4];
+  T al[4];
+  for (int a = 0; a < 4; ++a) { id[a] = B.hinge_idx[a * NH + q]; al[a] = B.hinge_alpha[a * NH + q]; }
+  T gx[3];
+  for (int k = 0; k < 3; ++k) {
+    T sum = 0;
+    for (int a = 0; a < 4; ++a) sum += al[a] * B.x[k * NV + id[a]];
+    gx[k] = sum;
+  }
+  const T w = B.hinge_w[q];
+  for (int a = 0; a < 4; ++a) {
+    T* dst = B.fel + 3 * (size_t)B.hinge_slot[a * NH + q];
+    for (int k = 0; k < 3; ++k) dst[k] = -w * al[a] * gx[k];
+  }
+}
+
+template <class T>
+void launch_hinge(const DevBatch<T>& B, hipStream_t s) {
+  if (B.NH == 0) return;
+  hipLaunchKernelGGL(k_hinge<T>, dim3((B.NH + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B);
+}
+
 // b = M u~ + h^2 sum over incident tets (fixed incidence order; the forces of
 // vertex i occupy the contiguous slots inc_off[i] .. inc_off[i+1]-1).
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= B.NV) return;
-  const int NV = B.NV;
+  // The workgroup's 256 vertices own one contiguous range of incidence slots: it is
+  // staged through LDS in coalesced chunks, then each thread sums its own slots in
+  // slot order (the same order, hence the same bits, as a direct per-vertex loop).
+  constexpr int CH = 1024;
+  __shared__ T s_f[3 * CH];
+  const int vbeg = blockIdx.x * kBlock;
+  if (vbeg >= B.NV) return;
+  const int vend = min(vbeg + kBlock, B.NV);
+  const int i = vbeg + threadIdx.x;
+  const int pb = B.inc_off[vbeg], pe = B.inc_off[vend];
+  int my0 = 0, my1 = 0;
+  if (i < vend) { my0 = B.inc_off[i]; my1 = B.inc_off[i + 1]; }
   T s0 = 0, s1 = 0, s2 = 0;
-  const int p1 = B.inc_off[i + 1];
-  for (int p = B.inc_off[i]; p < p1; ++p) {
-    const T* f = B.fel + 3 * (size_t)p;
-    s0 += f[0];
-    s1 += f[1];
-    s2 += f[2];
+  for (int c0 = pb; c0 < pe; c0 += CH) {
+    const int c1 = min(c0 + CH, pe);
+    __syncthreads();
+    for (int q = threadIdx.x; q < 3 * (c1 - c0); q += kBlock) s_f[q] = B.fel[3 * (size_t)c0 + q];
+    __syncthreads();
+    const int a = max(my0, c0), b = min(my1, c1);
+    for (int p = a; p < b; ++p) {
+      const T* f = s_f + 3 * (p - c0);
+      s0 += f[0];
+      s1 += f[1];
+      s2 += f[2];
+    }
   }
+  if (i >= vend) return;
+  const int NV = B.NV;
   const T hh = (T)(B.h * B.h);
   const T m = B.mass[i];
   B.b[i] = m * B.ut[i] + hh * s0;
@@ -1294,6 +1451,7 @@ void prepare_csp(int cap, int rmax) {
 #define INST(T)                                                          \
   template void prepare_csp<T>(int, int);                                \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
+  template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_project<T>(const DevBatch<T>&, hipStream_t);      \
   template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \
   template void launch_apply<T>(const DevBatch<T>&, int, hipStream_t);   \

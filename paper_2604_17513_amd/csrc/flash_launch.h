@@ -7,6 +7,7 @@ namespace flash {
 template <class T> void launch_detect(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
 template <class T> void launch_finalize(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
 template <class T> void launch_gather(const DevBatch<T>& B, hipStream_t s);
+template <class T> void launch_hinge(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_project(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_assemble(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_apply(const DevBatch<T>& B, int max_ld, hipStream_t s);

@@ -90,6 +90,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library missing: {LIB_PATH}; build it with paper_2604_17513_amd/build.py")
+        # torch brings its own HIP runtime; loading it first makes this library bind to the same
+        # one (a second runtime in the process would leave torch without a device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, D = C.c_void_p, C.c_int32, C.POINTER(C.c_double)
         L.flash_create_batch.argtypes = [C.POINTER(flash_env_desc), I32, C.POINTER(flash_params), P, C.POINTER(P)]

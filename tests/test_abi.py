@@ -47,10 +47,13 @@ def test_invalid_arguments_are_rejected_without_device():
     p.ncp_tol = 1e-6
     assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
     p.lg_iterations = 5
-    d[0].elem = 1      # triangles are not built in this library
+    d[0].elem = 7      # neither FLASH_TET nor FLASH_TRI
     d[0].n_vertices = 3
     d[0].n_elements = 1
-    assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_UNSUPPORTED
+    assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
+    d[0].elem = 1      # triangles need a thickness
+    d[0].thickness = 0.0
+    assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
     assert L.flash_step(None, 1) == F.FLASH_ERR_INVALID_ARG
     assert L.flash_destroy_batch(None) == F.FLASH_ERR_INVALID_ARG
     assert L.flash_residual(None, None, None, None) == F.FLASH_ERR_INVALID_ARG

@@ -1,0 +1,111 @@
+"""GPU parity for membrane triangles with hinge bending, and for uneven batches that mix
+cloth and tet environments in one launch per phase.
+
+Same protocol as the tet parity tests: from the GPU's own start state (promoted exactly to
+FP64) and obstacle poses, one GPU step and one oracle step; positions within
+1e-5 * max(|q|_inf, L_env) in FP32 and 1e-9 * ... in FP64, identical contact lists, and the
+oracle's NCP residual of the GPU's positions and multipliers <= 1e-6 m.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import flash_oracle as O
+from paper_2604_17513_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _F():
+    from paper_2604_17513_amd import flash as F
+    return F
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _check_step(b, sc, oes, envs, rel, label):
+    x0, v0 = b.get_state()
+    xs, vs = b.split(x0), b.split(v0)
+    obs = {e: b.get_obstacles(e) for e in envs}
+    b.step(1)
+    x1s = b.split(b.get_state()[0])
+    for e in envs:
+        ref = O.step(oes[e], xs[e], vs[e], obs[e], sc.params, tol=1e-12)
+        L = np.linalg.norm(sc.envs[e].rest_x.max(0) - sc.envs[e].rest_x.min(0))
+        tol = rel * max(np.abs(ref.x).max(), L)
+        err = np.abs(x1s[e] - ref.x).max()
+        gc = b.contacts(e)
+        same = (gc["vertex"].tolist() == ref.contacts.vertex.tolist()
+                and gc["obstacle"].tolist() == ref.contacts.obstacle.tolist())
+        r = O.contact_residual(oes[e], xs[e], x1s[e], ref.contacts, gc["lambda"], sc.params.h) if same else np.inf
+        _say(f"{label} env {e}: {len(gc['vertex'])} contacts, max|dq| {err:.3e} (tol {tol:.3e}), residual {r:.2e}")
+        assert same
+        assert err <= tol
+        assert r <= 1e-6
+
+
+@pytest.mark.parametrize("precision,rel", [("fp64", 1e-9), ("fp32", 1e-5)])
+def test_cloth_drop_matches_oracle(precision, rel):
+    F = _F()
+    sc = scenes.cloth_drop(n=12, seed=0)
+    oes = {0: O.precompute(sc.envs[0], sc.params.h)}
+    b = F.from_scene(sc, precision=F.FLASH_FP64 if precision == "fp64" else F.FLASH_FP32)
+    checked = 0
+    for s in range(24):
+        if s in (0, 5, 6, 7, 9, 12, 17, 23):
+            _check_step(b, sc, oes, [0], rel, f"{precision} step {s}")
+            checked += 1
+        else:
+            b.step(1)
+    per, mx, its, st = b.residual()
+    assert mx <= 1e-6
+    assert checked == 8
+
+
+def test_cloth_free_flight_closed_form():
+    """Rigid translation: ARAP and flat hinges exert no force, so implicit Euler gives
+    x_n = x_0 + n h v_0 + h^2 g n (n + 1) / 2 exactly (up to rounding)."""
+    F = _F()
+    sc = scenes.cloth_drop(n=10, seed=0)
+    sc.x0[0] = sc.envs[0].rest_x + np.array([0.0, 20.0, 0.0])   # far above the ground and the box
+    v0 = np.tile([0.2, 0.5, -0.1], (sc.envs[0].n_vertices, 1))
+    sc.v0[0] = v0
+    b = F.from_scene(sc, precision=F.FLASH_FP64)
+    n = 12
+    b.step(n)
+    x, v = b.get_state()
+    h = sc.params.h
+    g = np.asarray(sc.params.gravity)
+    xe = sc.x0[0] + n * h * v0 + h * h * g * n * (n + 1) / 2
+    ve = v0 + n * h * g
+    assert np.abs(x - xe).max() <= 1e-11 * max(np.abs(xe).max(), 1.0)
+    assert np.abs(v - ve).max() <= 1e-9
+
+
+def test_uneven_cloth_and_tet_batch():
+    """Cloth sheets and tet blocks of different sizes in one batch (one launch per phase),
+    each env against the oracle, and each env bitwise equal to a batch of its own."""
+    F = _F()
+    parts = [scenes.cloth_drop(n=12, seed=1), scenes.drop_cube(seed=2, hexes=3, drop_height=0.002),
+             scenes.cloth_drop(n=9, seed=3, bending=0.0), scenes.drop_cube(seed=4, hexes=5, drop_height=0.002)]
+    envs, xs, vs, obs = [], [], [], []
+    for p in parts:
+        envs += p.envs; xs += p.x0; vs += p.v0; obs += p.obstacles
+    sc = scenes.Scene(envs, xs, vs, obs, scenes.Params(lg_iterations=10))
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in range(len(envs))}
+    b = F.from_scene(sc)
+    for s in range(10):
+        if s in (2, 6, 9):
+            _check_step(b, sc, oes, list(range(len(envs))), 1e-5, f"uneven step {s}")
+        else:
+            b.step(1)
+    xb = b.split(b.get_state()[0])
+    for e in (0, 3):
+        one = scenes.Scene([envs[e]], [xs[e]], [vs[e]], [obs[e]], sc.params)
+        b1 = F.from_scene(one)
+        b1.step(10)
+        assert np.array_equal(b1.get_state()[0], xb[e])
