@@ -248,6 +248,7 @@ def main():
     achieved = bpl / (apply_avg * 1e-3) / 1e9
     stats = b.stats()
     breakdown = {k: round(v[0] / args.steps, 3) for k, v in kt.items() if v[1]}
+    schedule = b.schedule_info()
     b.close()
 
     arms = {"plain_eager": {"env_steps_per_s": round(v_plain, 2), "ms_per_step": round(1000 * dt / args.steps, 3),
@@ -308,6 +309,9 @@ def main():
             "contacts_per_env_mean": round(float(np.mean([s_["contacts"] for s_ in stats])), 1),
             "lg_iterations": sc.params.lg_iterations,
             "ncp_tol": sc.params.ncp_tol,
+            "apply_schedule": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in schedule.items()
+                               if k != "candidate_ms"},
+            "apply_schedule_candidate_ms": [round(x, 4) for x in schedule["candidate_ms"]],
         },
         "roofline": {
             "bound": "hbm",

@@ -112,7 +112,10 @@ typedef struct {
   int32_t contact_fp32;           /* FP32 batches: 0 (default) runs the per-env contact-space
                                      solve in FP64, 1 in FP32 (stalls on stiff, high-friction
                                      contact sets); FP64 batches ignore it */
-  int32_t reserved_params;
+  int32_t fixed_schedule;         /* 0 (default): the first flash_step times the work schedules of the
+                                     explicit-inverse products on this batch and keeps the fastest
+                                     (see flash_schedule_info); 1: default schedule.  Every schedule
+                                     gives bitwise identical results. */
 } flash_params;
 
 /* One contact of the last step.  impulse = h F lambda in the world frame (N s);
@@ -202,6 +205,15 @@ flash_status flash_set_kernel_timing(flash_batch *b, int32_t enable);
 flash_status flash_kernel_times(flash_batch *b, double *total_ms, int64_t *launches, int32_t cap,
                                 int32_t *n_out);
 const char *flash_kernel_name(int32_t i);
+
+/* Work schedule of the explicit-inverse products (global apply and position
+ * update; batching over uneven envs, Eq. 11-12).  One workgroup per (env,
+ * column tile) work item, items of the largest envs first.  info[0] = columns
+ * per tile, info[1] = rows in flight per wave, info[2] = work items, info[3] =
+ * 1 if the autotuner chose it.  cand_ms (6 doubles, may be NULL): the
+ * autotuner's milliseconds per apply launch for tiles of 8, 16 and 32 bytes
+ * per lane, each with 4 and 8 rows in flight (0 when not tuned). */
+flash_status flash_schedule_info(flash_batch *b, int32_t *info, double *cand_ms);
 
 /* Diagnostic: ms_out[0..7] = wall-clock milliseconds per env spent in the 8
  * phases of the contact solve (setup, residual/classification, base inverse,

@@ -318,6 +318,13 @@ struct flash_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int device = 0;
+  // explicit-inverse product schedule: work lists for the three tile widths, the chosen
+  // variant, and the autotuner's measurements (ms per apply launch of each candidate)
+  int2* gemv_items[3] = {nullptr, nullptr, nullptr};
+  int gemv_n_items[3] = {0, 0, 0};
+  GemvSchedule sched{};
+  bool tuned = false;
+  double cand_ms[6] = {0, 0, 0, 0, 0, 0};
   // learned warm start: network weights, per-slot inference buffers, training-pair recording
   bool ws_loaded = false, ws_record = false;
   MlpBuffers mlp{};
@@ -382,10 +389,10 @@ struct flash_batch {
     for (int k = 0; k < p.lg_iterations; ++k) {
       launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
       launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });
-      launch(K_APPLY, [&] { launch_apply<T>(B, max_ld, stream); });
+      launch(K_APPLY, [&] { launch_apply<T>(B, sched, stream); });
       launch(K_CSP, [&] { launch_csp<T>(B, mu_d, k == 0 ? 1 : 0, stream); });
       if (k == 0 && ws_record) launch(K_MLP, [&] { launch_ws_labels<T>(B, mlp.feat, ws_lab, stream); });
-      launch(K_CORRECT, [&] { launch_correct<T>(B, max_ld, stream); });
+      launch(K_CORRECT, [&] { launch_correct<T>(B, sched, stream); });
     }
     launch(K_FINALIZE, [&] { launch_finalize<T>(B, mu_d, stream); });
     HIPCHK(hipGetLastError());
@@ -413,7 +420,49 @@ struct flash_batch {
     prepare_mlp();
   }
 
+  GemvSchedule schedule(int vw, int unroll) const {
+    GemvSchedule g;
+    g.items = gemv_items[vw];
+    g.n_items = gemv_n_items[vw];
+    g.vw = vw;
+    g.unroll = unroll;
+    return g;
+  }
+
+  // Autotuner: times every (tile width, unroll) candidate of the global apply on this
+  // batch (one warm-up launch, then 3 timed launches each) and keeps the fastest for the
+  // apply and the position update.  The candidates give identical bits, so the choice
+  // never changes results.  The apply only writes z, which every step recomputes.
+  template <class T>
+  void autotune(const DevBatch<T>& B) {
+    hipEvent_t a, c;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&c));
+    double best = 1e30;
+    int bk = 3;
+    for (int k = 0; k < 6; ++k) {
+      const GemvSchedule g = schedule(k / 2, (k & 1) ? 8 : 4);
+      launch_apply<T>(B, g, stream);
+      HIPCHK(hipEventRecord(a, stream));
+      for (int r = 0; r < 3; ++r) launch_apply<T>(B, g, stream);
+      HIPCHK(hipEventRecord(c, stream));
+      HIPCHK(hipEventSynchronize(c));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, a, c));
+      cand_ms[k] = ms / 3.0;
+      if (cand_ms[k] < best) { best = cand_ms[k]; bk = k; }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(c);
+    HIPCHK(hipGetLastError());
+    sched = schedule(bk / 2, (bk & 1) ? 8 : 4);
+  }
+
   void step(int n) {
+    if (!tuned) {
+      if (!p.fixed_schedule) { if (fp64) autotune(bd); else autotune(bf); }
+      tuned = true;
+    }
     if (p.use_graph && !timing) {
       if (!gexec) {
         HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -534,6 +583,23 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
     max_ld = std::max(max_ld, ld);
   }
   b->max_ld = max_ld;
+  // work lists of the explicit-inverse products: every existing column tile, largest envs first
+  {
+    std::vector<int> order(ne);
+    for (int e = 0; e < ne; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return H[a].n > H[c].n; });
+    for (int vw = 0; vw < 3; ++vw) {
+      const int tile = gemv_tile<T>(vw);
+      std::vector<int2> items;
+      for (int e : order)
+        for (int t0 = 0; t0 < H[e].n; t0 += tile) items.push_back(make_int2(e, t0));
+      int2* d = dalloc<int2>(items.size(), own);
+      HIPCHK(hipMemcpy(d, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice));
+      b->gemv_items[vw] = d;
+      b->gemv_n_items[vw] = (int)items.size();
+    }
+    b->sched = b->schedule(1, 4);   // 16 bytes per lane, 4 rows in flight: the untuned default
+  }
   T* G = dalloc<T>((size_t)gtot, own);
   {
     std::vector<T> blk;
@@ -1022,6 +1088,18 @@ flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* ov
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());
   }
+  return FLASH_OK;
+}
+
+flash_status flash_schedule_info(flash_batch* b, int32_t* info, double* cand_ms) {
+  if (!b || !info) return fail(FLASH_ERR_INVALID_ARG, "null argument");
+  const int es = b->fp64 ? 8 : 4;
+  info[0] = 64 * ((8 << b->sched.vw) / es);
+  info[1] = b->sched.unroll;
+  info[2] = b->sched.n_items;
+  info[3] = (b->tuned && !b->p.fixed_schedule) ? 1 : 0;
+  if (cand_ms)
+    for (int k = 0; k < 6; ++k) cand_ms[k] = b->cand_ms[k];
   return FLASH_OK;
 }
 

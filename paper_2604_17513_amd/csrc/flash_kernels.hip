@@ -436,18 +436,26 @@ __global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
 // ---------------------------------------------------------------------------
 constexpr int kChunk = 1024;
 
-template <class T, bool ROWS>
-__global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B) {
-  constexpr int VW = 16 / sizeof(T);
+// VW columns per lane (TILE = 64 VW per workgroup), UNROLL rows in flight per wave.
+// A workgroup takes one (env, first column) work item; the item list holds only the
+// column tiles that exist, largest envs first.  Neither parameter changes the
+// arithmetic: every column is summed over the same rows in the same order by the same
+// wave, so all schedules give the same bits.
+template <class T, int VW>
+struct alignas(VW * sizeof(T) >= 16 ? 16 : VW * sizeof(T)) GVec {
+  T v[VW];
+};
+
+template <class T, bool ROWS, int VW, int UNROLL>
+__global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* items) {
   constexpr int TILE = 64 * VW;
   __shared__ T s_vec[3][kChunk];
   __shared__ int s_row[kChunk];
   __shared__ T s_red[kBlock / 64 - 1][3][TILE];
-  const int e = blockIdx.y;
+  const int2 item = items[blockIdx.x];
+  const int e = item.x, tile0 = item.y;
   const int v0 = B.voff[e];
   const int n = B.voff[e + 1] - v0;
-  const int tile0 = blockIdx.x * TILE;
-  if (tile0 >= n) return;
   const int ld = B.gld[e];
   const T* G = B.G + B.goff[e];
   const int nrows = ROWS ? B.ccount[e] : n;
@@ -475,22 +483,14 @@ __global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B) {
     }
     __syncthreads();
     if (active) {
-#pragma unroll 4
+#pragma unroll UNROLL
       for (int r = wid; r < nr; r += kBlock / 64) {
-        const T* gp = G + (size_t)s_row[r] * ld + col0;
-        T g[VW];
-        if constexpr (VW == 4) {
-          float4 q = *reinterpret_cast<const float4*>(gp);
-          g[0] = q.x; g[1] = q.y; g[2] = q.z; g[3] = q.w;
-        } else {
-          double2 q = *reinterpret_cast<const double2*>(gp);
-          g[0] = q.x; g[1] = q.y;
-        }
+        const GVec<T, VW> g = *reinterpret_cast<const GVec<T, VW>*>(G + (size_t)s_row[r] * ld + col0);
         const T b0 = s_vec[0][r], b1 = s_vec[1][r], b2 = s_vec[2][r];
         for (int q = 0; q < VW; ++q) {
-          acc[q][0] += g[q] * b0;
-          acc[q][1] += g[q] * b1;
-          acc[q][2] += g[q] * b2;
+          acc[q][0] += g.v[q] * b0;
+          acc[q][1] += g.v[q] * b1;
+          acc[q][2] += g.v[q] * b2;
         }
       }
     }
@@ -1418,15 +1418,32 @@ template <class T>
 void launch_assemble(const DevBatch<T>& B, hipStream_t s) {
   hipLaunchKernelGGL(k_assemble<T>, dim3((B.NV + kBlock - 1) / kBlock), dim3(kBlock), 0, s, B);
 }
+// columns per lane of schedule variant vw (0, 1, 2): 8, 16, 32 bytes per lane
 template <class T>
-void launch_apply(const DevBatch<T>& B, int max_ld, hipStream_t s) {
-  constexpr int TILE = 64 * (16 / sizeof(T));
-  hipLaunchKernelGGL((k_gemv<T, false>), dim3((max_ld + TILE - 1) / TILE, B.n_envs), dim3(kBlock), 0, s, B);
+constexpr int gemv_vw(int vw) { return (int)((8 << vw) / sizeof(T)); }
+
+template <class T, bool ROWS>
+static void launch_gemv(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s) {
+  const dim3 grid((unsigned)S.n_items), blk(kBlock);
+  const int2* it = S.items;
+  const int key = S.vw * 2 + (S.unroll == 8 ? 1 : 0);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(0), 4>), grid, blk, 0, s, B, it); break;
+    case 1: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(0), 8>), grid, blk, 0, s, B, it); break;
+    case 2: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(1), 4>), grid, blk, 0, s, B, it); break;
+    case 3: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(1), 8>), grid, blk, 0, s, B, it); break;
+    case 4: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(2), 4>), grid, blk, 0, s, B, it); break;
+    default: hipLaunchKernelGGL((k_gemv<T, ROWS, gemv_vw<T>(2), 8>), grid, blk, 0, s, B, it); break;
+  }
+}
+
+template <class T>
+void launch_apply(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s) {
+  launch_gemv<T, false>(B, S, s);
 }
 template <class T>
-void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s) {
-  constexpr int TILE = 64 * (16 / sizeof(T));
-  hipLaunchKernelGGL((k_gemv<T, true>), dim3((max_ld + TILE - 1) / TILE, B.n_envs), dim3(kBlock), 0, s, B);
+void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s) {
+  launch_gemv<T, true>(B, S, s);
 }
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
@@ -1454,8 +1471,8 @@ void prepare_csp(int cap, int rmax) {
   template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_project<T>(const DevBatch<T>&, hipStream_t);      \
   template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \
-  template void launch_apply<T>(const DevBatch<T>&, int, hipStream_t);   \
-  template void launch_correct<T>(const DevBatch<T>&, int, hipStream_t); \
+  template void launch_apply<T>(const DevBatch<T>&, const GemvSchedule&, hipStream_t);   \
+  template void launch_correct<T>(const DevBatch<T>&, const GemvSchedule&, hipStream_t); \
   template void launch_csp<T>(const DevBatch<T>&, const T*, int, hipStream_t);
 INST(float)
 INST(double)

@@ -10,9 +10,18 @@ template <class T> void launch_gather(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_hinge(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_project(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_assemble(const DevBatch<T>& B, hipStream_t s);
-template <class T> void launch_apply(const DevBatch<T>& B, int max_ld, hipStream_t s);
+// Work list and tile parameters of the explicit-inverse products (apply and position update).
+struct GemvSchedule {
+  const int2* items;   // (env, first column) per workgroup, largest envs first
+  int n_items;
+  int vw;              // 0, 1, 2: 8, 16 or 32 bytes of columns per lane
+  int unroll;          // 4 or 8 rows in flight per wave
+};
+template <class T> constexpr int gemv_tile(int vw) { return 64 * (int)((8 << vw) / sizeof(T)); }
+
+template <class T> void launch_apply(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
 template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s);
-template <class T> void launch_correct(const DevBatch<T>& B, int max_ld, hipStream_t s);
+template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
 // Raises the dynamic LDS limit of the contact-solve kernel for `cap` contacts per env.
 template <class T> void prepare_csp(int cap, int rmax);
 

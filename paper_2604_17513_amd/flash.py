@@ -34,7 +34,8 @@ EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
-    "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_ws_load", "flash_ws_record",
+    "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
+    "flash_ws_record",
     "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
     "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
     "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_train", "flash_mlp_eval", "flash_last_error",
@@ -60,7 +61,7 @@ class flash_params(C.Structure):
                 ("max_inner_iterations", C.c_int32), ("ncp_tol", C.c_double), ("contact_margin", C.c_double),
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
-                ("contact_fp32", C.c_int32), ("reserved_params", C.c_int32)]
+                ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -116,6 +117,7 @@ def lib():
         L.flash_kernel_name.argtypes = [I32]
         L.flash_kernel_name.restype = C.c_char_p
         L.flash_phase_times.argtypes = [P, D]
+        L.flash_schedule_info.argtypes = [P, C.POINTER(I32), D]
         F32, I64 = C.POINTER(C.c_float), C.c_int64
         L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, F32]
         L.flash_ws_record.argtypes = [P, I32]
@@ -153,7 +155,8 @@ def _dptr(a: np.ndarray):
 
 
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
-                  use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0) -> flash_params:
+                  use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
+                  fixed_schedule: bool = False) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -168,6 +171,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.use_graph = 1 if use_graph else 0
     s.max_contacts_per_env = max_contacts
     s.inner_tol = inner_tol
+    s.fixed_schedule = 1 if fixed_schedule else 0
     return s
 
 
@@ -190,7 +194,7 @@ class Batch:
 
     def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
-                 stream: Optional[int] = None, inner_tol: float = 0.0):
+                 stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -209,7 +213,7 @@ class Batch:
             d.elements = el.ctypes.data_as(C.POINTER(C.c_int32))
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
-        self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol)
+        self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -334,6 +338,14 @@ class Batch:
             mask = 0
         _check(lib().flash_set_kernel_timing(self._h, int(mask)))
 
+    def schedule_info(self):
+        """(columns per tile, rows in flight per wave, work items, tuned, candidate ms per apply launch)."""
+        info = np.zeros(4, dtype=np.int32)
+        ms = np.zeros(6)
+        _check(lib().flash_schedule_info(self._h, info.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(ms)))
+        return dict(tile_cols=int(info[0]), unroll=int(info[1]), work_items=int(info[2]), tuned=bool(info[3]),
+                    candidate_ms=ms.tolist())
+
     def phase_times(self):
         out = np.zeros(12)
         _check(lib().flash_phase_times(self._h, _dptr(out)))
@@ -446,9 +458,11 @@ class Mlp:
 
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
-               use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0) -> Batch:
+               use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
+               fixed_schedule: bool = False) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
-    b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol)
+    b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
+              fixed_schedule=fixed_schedule)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:

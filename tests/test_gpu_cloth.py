@@ -109,3 +109,28 @@ def test_uneven_cloth_and_tet_batch():
         b1 = F.from_scene(one)
         b1.step(10)
         assert np.array_equal(b1.get_state()[0], xb[e])
+
+
+def test_autotuned_schedule_is_bitwise_identical():
+    """The autotuner picks the work schedule of the explicit-inverse products by timing;
+    every candidate sums each output over the same rows in the same order, so a tuned
+    batch and a batch on the default schedule end in the same bits."""
+    F = _F()
+    parts = [scenes.cloth_drop(n=14, seed=5), scenes.drop_cube(seed=6, hexes=4, drop_height=0.002),
+             scenes.cloth_drop(n=8, seed=7), scenes.drop_cube(seed=8, hexes=6, drop_height=0.002)]
+    envs, xs, vs, obs = [], [], [], []
+    for p in parts:
+        envs += p.envs; xs += p.x0; vs += p.v0; obs += p.obstacles
+    sc = scenes.Scene(envs, xs, vs, obs, scenes.Params(lg_iterations=6))
+    tuned = F.from_scene(sc)
+    fixed = F.from_scene(sc, fixed_schedule=True)
+    tuned.step(8)
+    fixed.step(8)
+    it, ifx = tuned.schedule_info(), fixed.schedule_info()
+    _say(f"tuned schedule {it}; fixed {ifx}")
+    assert it["tuned"] and not ifx["tuned"]
+    assert all(m > 0 for m in it["candidate_ms"])
+    n_tiles = sum(-(-e.n_vertices // it["tile_cols"]) for e in envs)
+    assert it["work_items"] == n_tiles
+    assert np.array_equal(tuned.get_state()[0], fixed.get_state()[0])
+    assert np.array_equal(tuned.get_state()[1], fixed.get_state()[1])
