@@ -114,8 +114,11 @@ typedef struct {
                                      contact sets); FP64 batches ignore it */
   int32_t fixed_schedule;         /* 0 (default): the first flash_step times the work schedules of the
                                      explicit-inverse products on this batch and keeps the fastest
-                                     (see flash_schedule_info); 1: default schedule.  Every schedule
-                                     gives bitwise identical results. */
+                                     (see flash_schedule_info), and every step runs the per-env
+                                     contact solves longest-first by the previous step's solve
+                                     times (batches of up to 4096 envs); 1: default schedule, envs
+                                     in index order.  Every schedule gives bitwise identical
+                                     results. */
 } flash_params;
 
 /* One contact of the last step.  impulse = h F lambda in the world frame (N s);
@@ -220,8 +223,10 @@ flash_status flash_schedule_info(flash_batch *b, int32_t *info, double *cand_ms)
  * right-hand sides, capacitance build, capacitance LU, direction, line
  * search); ms_out[8..11] = per-env counts of capacitance factorisations,
  * factorisation reuses, line-search failures and solves ended above the
- * inner tolerance.  Averaged over envs, accumulated since the previous call
- * (then reset).  ms_out holds 12 doubles. */
+ * inner tolerance; ms_out[12] = mean rows of a factored capacitance system,
+ * ms_out[13] = the largest, ms_out[14] = Newton iterations per env,
+ * ms_out[15] = contact solves per env.  Accumulated since the previous call
+ * (then reset).  ms_out holds 16 doubles. */
 flash_status flash_phase_times(flash_batch *b, double *ms_out);
 
 /* ---------------------------------------------------------------------------

@@ -100,7 +100,8 @@ struct DevBatch {
   void* Cm;                   // [rmax*rmax per env] capacitance matrix + row data
   int* base;                  // [cap per env] base-set contact ids (ordered)
   void* scr;                  // [cap*16 per env] panel scratch of the blocked inverse
-  void* lupan;                // [rmax*(kBK+1) per env] LU panel and solve vector of systems above rlds rows
+  void* lupan;                // [rmax*(kBK+2) per env] LU panel (row stride kBK+1) and solve vector of
+                              // systems above rlds rows
   int* nbase;                 // [n_envs]
   int* lust;                  // [4 per env] stored capacitance factorisation: valid, rows, base version x2
 
@@ -119,6 +120,10 @@ struct DevBatch {
   int* flags;                 // [n_envs]
   int* fp64_polar;            // [n_envs]
   unsigned long long* phase;  // [n_envs * 12] contact-solve phase ticks and event counts (nullptr: off)
+
+  // scheduling of the per-env contact solves (nullptr: identity order)
+  int* order;                 // [n_envs] env of each contact-solve workgroup
+  unsigned long long* cost;   // [n_envs] wall-clock ticks of the env's solves since the last ordering
 
   // learned warm start (optional)
   const double* lam_ml;       // [3 per contact] predicted multipliers (nullptr: off)

@@ -377,6 +377,7 @@ struct flash_batch {
     launch(K_DETECT, [&] {
       launch_detect<T>(B, mu_d, stream);
       launch_hinge<T>(B, stream);
+      launch_order<T>(B, stream);
     });
     const bool infer = ws_loaded && p.warm_start == FLASH_WS_LEARNED;
     if (infer || ws_record) {
@@ -672,8 +673,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.Ginv = dalloc<unsigned char>(ne * cap * cap * cts, own);
   {
     const size_t rm = (size_t)B.rmax;
-    B.Cm = dalloc<unsigned char>(ne * (rm * rm + 16 * rm) * cts + 3 * ne * rm * sizeof(int), own);
-    B.lupan = dalloc<unsigned char>(ne * rm * (kBK + 1) * cts, own);
+    B.Cm = dalloc<unsigned char>(ne * (rm * rm + 16 * rm) * cts + 4 * ne * rm * sizeof(int), own);
+    B.lupan = dalloc<unsigned char>(ne * rm * (kBK + 2) * cts, own);
   }
   B.base = dalloc<int>(ne * cap, own);
   B.scr = dalloc<unsigned char>(ne * cap * 16 * cts, own);
@@ -703,8 +704,17 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   HIPCHK(hipMemset(B.refac, 0, ne * sizeof(int)));
   HIPCHK(hipMemset(B.flags, 0, ne * sizeof(int)));
   HIPCHK(hipMemset(B.fp64_polar, 0, ne * sizeof(int)));
-  B.phase = dalloc<unsigned long long>((size_t)ne * 12, own);
-  HIPCHK(hipMemset(B.phase, 0, (size_t)ne * 12 * sizeof(unsigned long long)));
+  B.phase = dalloc<unsigned long long>((size_t)ne * 16, own);
+  HIPCHK(hipMemset(B.phase, 0, (size_t)ne * 16 * sizeof(unsigned long long)));
+  B.order = nullptr;
+  B.cost = nullptr;
+  if (ne <= 4096 && !b->p.fixed_schedule) {
+    std::vector<int> ident(ne);
+    for (int e = 0; e < ne; ++e) ident[e] = e;
+    int* d_order = dalloc<int>(ne, own); up(d_order, ident); B.order = d_order;
+    B.cost = dalloc<unsigned long long>(ne, own);
+    HIPCHK(hipMemset(B.cost, 0, ne * sizeof(unsigned long long)));
+  }
   B.lam_ml = nullptr;
   B.ws_state = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.ws_state, 0, ne * sizeof(int)));
@@ -1109,7 +1119,7 @@ flash_status flash_phase_times(flash_batch* b, double* ms_out) {
     HIPCHK(hipStreamSynchronize(b->stream));
     const int ne = b->n_envs;
     unsigned long long* dp = b->fp64 ? b->bd.phase : b->bf.phase;
-    std::vector<unsigned long long> h((size_t)ne * 12);
+    std::vector<unsigned long long> h((size_t)ne * 16);
     HIPCHK(hipMemcpy(h.data(), dp, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     int khz = 0;
     HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device));
@@ -1118,11 +1128,18 @@ flash_status flash_phase_times(flash_batch* b, double* ms_out) {
       for (int e = 0; e < ne; ++e) t += (double)h[(size_t)e * 8 + k];
       ms_out[k] = khz > 0 ? t / (double)khz / ne : 0.0;
     }
-    for (int k = 0; k < 4; ++k) {
-      double t = 0;
-      for (int e = 0; e < ne; ++e) t += (double)h[(size_t)ne * 8 + 4 * e + k];
-      ms_out[8 + k] = t / ne;
+    const unsigned long long* cnt = h.data() + (size_t)ne * 8;
+    double sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long mx = 0;
+    for (int e = 0; e < ne; ++e) {
+      for (int k = 0; k < 8; ++k) sum[k] += (double)cnt[8 * (size_t)e + k];
+      mx = std::max(mx, cnt[8 * (size_t)e + 5]);
     }
+    for (int k = 0; k < 4; ++k) ms_out[8 + k] = sum[k] / ne;
+    ms_out[12] = sum[0] > 0 ? sum[4] / sum[0] : 0.0;   // mean capacitance rows per factorisation
+    ms_out[13] = (double)mx;                           // largest capacitance system
+    ms_out[14] = sum[6] / ne;                          // Newton iterations per env
+    ms_out[15] = sum[7] / ne;                          // contact solves with contacts per env
     HIPCHK(hipMemset(dp, 0, h.size() * sizeof(unsigned long long)));
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());

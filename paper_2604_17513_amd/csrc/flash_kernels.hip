@@ -638,15 +638,16 @@ __device__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
 // matrix (ties to the lowest row) and the pivot row of step k is stored in
 // piv[k].  Each kBK-column panel is factored in LDS (pan: n * kBK values).
 template <class T>
-__device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
+__device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
   const int tid = threadIdx.x;
+  constexpr int PS = kBK + 1;   // odd panel row stride: column accesses spread over the LDS banks
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
     const int pr_rows = n - k0;
     __syncthreads();
     for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
       const int i = idx / kb, t = idx - i * kb;
-      pan[i * kBK + t] = A[(size_t)(k0 + i) * n + k0 + t];
+      pan[i * PS + t] = A[(size_t)(k0 + i) * n + k0 + t];
     }
     __syncthreads();
     if (tid < 64) {
@@ -655,7 +656,7 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
         double best = -1.0;
         int bi = pr_rows;
         for (int i = t + tid; i < pr_rows; i += 64) {
-          const double a = fabs((double)pan[i * kBK + t]);
+          const double a = fabs((double)pan[i * PS + t]);
           if (a > best) { best = a; bi = i; }
         }
         for (int d = 32; d > 0; d >>= 1) {
@@ -666,19 +667,19 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
         const int pr = bi < pr_rows ? bi : t;
         if (tid == 0) piv[k0 + t] = k0 + pr;
         if (pr != t && tid < kb) {
-          const T t0 = pan[t * kBK + tid];
-          pan[t * kBK + tid] = pan[pr * kBK + tid];
-          pan[pr * kBK + tid] = t0;
+          const T t0 = pan[t * PS + tid];
+          pan[t * PS + tid] = pan[pr * PS + tid];
+          pan[pr * PS + tid] = t0;
         }
         __builtin_amdgcn_wave_barrier();
-        const T pv = pan[t * kBK + t];
+        const T pv = pan[t * PS + t];
         const int w = kb - t - 1;
         T urow[kBK];
-        for (int q = 0; q < w; ++q) urow[q] = pan[t * kBK + t + 1 + q];
+        for (int q = 0; q < w; ++q) urow[q] = pan[t * PS + t + 1 + q];
         for (int i = t + 1 + tid; i < pr_rows; i += 64) {
-          const T l = pv != T(0) ? pan[i * kBK + t] / pv : T(0);
-          pan[i * kBK + t] = l;
-          for (int q = 0; q < w; ++q) pan[i * kBK + t + 1 + q] -= l * urow[q];
+          const T l = pv != T(0) ? pan[i * PS + t] / pv : T(0);
+          pan[i * PS + t] = l;
+          for (int q = 0; q < w; ++q) pan[i * PS + t + 1 + q] -= l * urow[q];
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -687,7 +688,7 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
     // write the factored panel back; apply the block's row swaps to the other columns
     for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
       const int i = idx / kb, t = idx - i * kb;
-      A[(size_t)(k0 + i) * n + k0 + t] = pan[i * kBK + t];
+      A[(size_t)(k0 + i) * n + k0 + t] = pan[i * PS + t];
     }
     for (int j = tid; j < n; j += kBlock) {
       if (j >= k0 && j < k0 + kb) continue;
@@ -702,7 +703,7 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
     }
     for (int idx = tid; idx < kb * kb; idx += kBlock) {
       const int i = idx / kb, j = idx - i * kb;
-      L11[i * kBK + j] = pan[i * kBK + j];
+      L11[i * kBK + j] = pan[i * PS + j];
     }
     __syncthreads();
     // U12 = L11^-1 A12 (unit lower)
@@ -729,7 +730,7 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
         for (int t = 0; t < kb; ++t) {
           T a[4], b[4];
           for (int q = 0; q < 4; ++q) {
-            a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * kBK + t] : T(0);
+            a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * PS + t] : T(0);
             b[q] = (j0 + q < n) ? A[(size_t)(k0 + t) * n + j0 + q] : T(0);
           }
           for (int p = 0; p < 4; ++p)
@@ -744,22 +745,29 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, T* L11, T* pan, double* sh_r
     }
   }
   __syncthreads();
-}
-
-// Solves A y = r with the factors of wg_lu_factor.  r[16 q + 6] holds the
-// right-hand side; the solution goes to r[16 q + 7].  ys: LDS of n values;
-// D: LDS kBK * kBK.
-template <class T>
-__device__ void wg_lu_apply(const T* A, int n, const int* piv, T* r, T* ys, T* D) {
-  const int tid = threadIdx.x;
-  __syncthreads();
-  for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * q + 6];
+  // the row swaps as one gather: applying them to the identity gives perm, so that
+  // (P y)[q] = y[perm[q]]; built in the panel scratch, then copied out in parallel
+  int* pw = reinterpret_cast<int*>(pan);
+  for (int q = tid; q < n; q += kBlock) pw[q] = q;
   __syncthreads();
   if (tid == 0)
     for (int k = 0; k < n; ++k) {
       const int pr = piv[k];
-      if (pr != k) { const T t0 = ys[k]; ys[k] = ys[pr]; ys[pr] = t0; }
+      if (pr != k) { const int t0 = pw[k]; pw[k] = pw[pr]; pw[pr] = t0; }
     }
+  __syncthreads();
+  for (int q = tid; q < n; q += kBlock) perm[q] = pw[q];
+  __syncthreads();
+}
+
+// Solves A y = r with the factors of wg_lu_factor.  r[16 q + 6] holds the
+// right-hand side; the solution goes to r[16 q + 7].  perm: the row gather of the
+// pivoting; ys: scratch of n values; D: LDS kBK * kBK.
+template <class T>
+__device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys, T* D) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * perm[q] + 6];
   __syncthreads();
   // forward substitution with the unit lower factor
   for (int k0 = 0; k0 < n; k0 += kBK) {
@@ -826,13 +834,13 @@ struct CspSmem {
   double* lam;                                 // [3*cap] multipliers, FP64
   T *Y, *dl, *Wd, *rv, *x0, *fw, *ph, *tmp;    // [3*cap]
   T *sp, *kap, *yh0, *yh1;                    // [cap]
-  T *pan, *ys;                                // [rmax*kBK], [rmax]
+  T *pan, *ys;                                // [rlds*(kBK+1)], [rlds]
   int *cls, *pos, *bas;                       // [cap]
 };
 
 template <class T>
 __host__ __device__ size_t csp_smem_bytes(int cap, int rmax) {
-  return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 1) * sizeof(T) +
+  return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 2) * sizeof(T) +
          (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
 }
 
@@ -857,7 +865,9 @@ __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y
 template <class T, class CT>
 __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int e = blockIdx.x;
+  // workgroups take envs in the order of the last step's solve times, longest first
+  const int e = B.order ? B.order[blockIdx.x] : blockIdx.x;
+  const unsigned long long t_start = (B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
   const int c = B.ccount[e];
   if (c == 0) {
     if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~1;
@@ -872,7 +882,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
     S.Wd = p; p += 3 * cap; S.rv = p; p += 3 * cap; S.x0 = p; p += 3 * cap; S.fw = p; p += 3 * cap;
     S.ph = p; p += 3 * cap; S.tmp = p; p += 3 * cap;
     S.sp = p; p += cap; S.kap = p; p += cap; S.yh0 = p; p += cap; S.yh1 = p; p += cap;
-    S.pan = p; p += (size_t)B.rlds * kBK; S.ys = p; p += B.rlds;
+    S.pan = p; p += (size_t)B.rlds * (kBK + 1); S.ys = p; p += B.rlds;
     int* ip = reinterpret_cast<int*>(p);
     S.cls = ip; ip += cap; S.pos = ip; ip += cap; S.bas = ip; ip += cap;
   }
@@ -907,9 +917,10 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   // vR(3) uR(3) rhs y Krow(3) Erow(3) -- 16 values per row
   CT* Rv = static_cast<CT*>(B.Cm) + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)e * B.rmax * 16;
   int* Rj = reinterpret_cast<int*>(static_cast<CT*>(B.Cm) + (size_t)B.n_envs * B.rmax * B.rmax + (size_t)B.n_envs * B.rmax * 16) +
-            (size_t)e * B.rmax * 3;
+            (size_t)e * B.rmax * 4;
   int* RjF = Rj + B.rmax;      // row list of the stored factorisation
   int* piv = Rj + 2 * B.rmax;  // its pivots
+  int* perm = Rj + 3 * B.rmax; // and the equivalent row gather
   int* lust = B.lust + 4 * e;  // valid, nR, base version at factorisation, current base version
 
   // ---- load state ----
@@ -1044,7 +1055,8 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   }
   bool learned_failed = false;
 
-  int it = 0, nref = 0, nfact = 0, nreuse = 0, nlsfail = 0;
+  int it = 0, nref = 0, nfact = 0, nreuse = 0, nlsfail = 0, max_nr = 0;
+  long sum_nr = 0;
   const int maxit = B.max_newton;
   double r = 0.0;
   mark(0);
@@ -1187,8 +1199,8 @@ restart:
     const int nR = min(sh_nR, B.rmax);
     if (sh_nR > B.rmax && tid == 0) B.flags[e] |= 8;   // capacity exceeded: inexact direction
     // LU panel and solve vector: LDS for systems up to rlds rows, global scratch above
-    CT* gpan = static_cast<CT*>(B.lupan) + (size_t)e * B.rmax * (kBK + 1);
-    CT* gys = gpan + (size_t)B.rmax * kBK;
+    CT* gpan = static_cast<CT*>(B.lupan) + (size_t)e * B.rmax * (kBK + 2);
+    CT* gys = gpan + (size_t)B.rmax * (kBK + 1);
     const bool big = nR > B.rlds;
     bool reused = false;
     if (nR > 0) {
@@ -1230,9 +1242,9 @@ restart:
         }
         __syncthreads();
         mark(4);
-        if (big) wg_lu_factor(Cm, nR, piv, sh_blk, gpan, sh_red, sh_i, &sh_piv);
-        else wg_lu_factor(Cm, nR, piv, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
-        if (tid == 0) { lust[0] = 1; lust[1] = nR; lust[2] = lust[3]; ++nfact; }
+        if (big) wg_lu_factor(Cm, nR, piv, perm, sh_blk, gpan, sh_red, sh_i, &sh_piv);
+        else wg_lu_factor(Cm, nR, piv, perm, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
+        if (tid == 0) { lust[0] = 1; lust[1] = nR; lust[2] = lust[3]; ++nfact; sum_nr += nR; max_nr = max(max_nr, nR); }
       } else if (tid == 0) {
         ++nreuse;
       }
@@ -1267,8 +1279,8 @@ restart:
           for (int b = 0; b < 3; ++b) rr += rv[8 + b] * rin[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
           rv[6] = rr;
         }
-        if (big) wg_lu_apply(Cm, nR, piv, Rv, gys, sh_blk);
-        else wg_lu_apply(Cm, nR, piv, Rv, S.ys, sh_blk);
+        if (big) wg_lu_apply(Cm, nR, perm, Rv, gys, sh_blk);
+        else wg_lu_apply(Cm, nR, perm, Rv, S.ys, sh_blk);
         for (int p = tid; p < nb; p += kBlock) {
           CT w0 = 0, w1 = 0, w2 = 0;
           for (int s = 0; s < nR; ++s) {
@@ -1388,12 +1400,18 @@ restart:
     B.iters[e] += it;
     B.refac[e] += nref;
     if (B.phase) {
-      B.phase[(size_t)B.n_envs * 8 + 4 * e + 0] += nfact;
-      B.phase[(size_t)B.n_envs * 8 + 4 * e + 1] += nreuse;
-      B.phase[(size_t)B.n_envs * 8 + 4 * e + 2] += nlsfail;
-      B.phase[(size_t)B.n_envs * 8 + 4 * e + 3] += (r > B.tol) ? 1 : 0;
+      unsigned long long* cnt = B.phase + (size_t)B.n_envs * 8 + 8 * e;
+      cnt[0] += nfact;
+      cnt[1] += nreuse;
+      cnt[2] += nlsfail;
+      cnt[3] += (r > B.tol) ? 1 : 0;
+      cnt[4] += sum_nr;
+      cnt[5] = max((unsigned long long)max_nr, cnt[5]);
+      cnt[6] += it;
+      cnt[7] += 1;
     }
     if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
+    if (B.cost) B.cost[e] += wall_clock64() - t_start;
     if (first_lg && B.ws_state) {
       int w = B.ws_state[e] & ~1;
       if (learned && !learned_failed) w |= 1;
@@ -1445,6 +1463,50 @@ template <class T>
 void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s) {
   launch_gemv<T, true>(B, S, s);
 }
+// Longest-processing-time order of the contact-solve workgroups: envs sorted by the
+// solve time they took in the previous step (descending; ties by env index), by a
+// bitonic sort in one workgroup; the accumulated times are then cleared.  Scheduling
+// only: the order never changes what a workgroup computes.
+constexpr int kOrderMax = 4096;
+__global__ void __launch_bounds__(1024) k_order(int n_envs, unsigned long long* cost, int* order) {
+  __shared__ unsigned long long key[kOrderMax];
+  __shared__ int val[kOrderMax];
+  int N = 1;
+  while (N < n_envs) N <<= 1;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    // larger cost first; the env index breaks ties (smaller first) through the low bits
+    key[i] = i < n_envs ? ((min(cost[i], 0xFFFFFFFFull) << 32) | (unsigned)(0x7FFFFFFF - i)) : 0ull;
+    val[i] = i;
+  }
+  __syncthreads();
+  for (int k = 2; k <= N; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int l = i ^ j;
+        if (l > i) {
+          const bool desc = (i & k) == 0;
+          const unsigned long long a = key[i], b = key[l];
+          if (desc ? (a < b) : (a > b)) {
+            key[i] = b; key[l] = a;
+            const int t = val[i]; val[i] = val[l]; val[l] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n_envs; i += blockDim.x) {
+    order[i] = val[i];
+    cost[i] = 0ull;
+  }
+}
+
+template <class T>
+void launch_order(const DevBatch<T>& B, hipStream_t s) {
+  if (!B.order || !B.cost || B.n_envs > kOrderMax) return;
+  hipLaunchKernelGGL(k_order, dim3(1), dim3(1024), 0, s, B.n_envs, B.cost, B.order);
+}
+
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
   if (B.csp64) {
@@ -1469,6 +1531,7 @@ void prepare_csp(int cap, int rmax) {
   template void prepare_csp<T>(int, int);                                \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
   template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
+  template void launch_order<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_project<T>(const DevBatch<T>&, hipStream_t);      \
   template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \
   template void launch_apply<T>(const DevBatch<T>&, const GemvSchedule&, hipStream_t);   \

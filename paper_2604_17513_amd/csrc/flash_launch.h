@@ -8,6 +8,8 @@ template <class T> void launch_detect(const DevBatch<T>& B, const T* mu_env, hip
 template <class T> void launch_finalize(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
 template <class T> void launch_gather(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_hinge(const DevBatch<T>& B, hipStream_t s);
+// Orders the contact-solve workgroups longest-first from the previous step's solve times.
+template <class T> void launch_order(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_project(const DevBatch<T>& B, hipStream_t s);
 template <class T> void launch_assemble(const DevBatch<T>& B, hipStream_t s);
 // Work list and tile parameters of the explicit-inverse products (apply and position update).

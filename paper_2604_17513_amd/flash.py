@@ -156,7 +156,7 @@ def _dptr(a: np.ndarray):
 
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
-                  fixed_schedule: bool = False) -> flash_params:
+                  fixed_schedule: bool = False, contact_fp32: bool = False) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -172,6 +172,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.max_contacts_per_env = max_contacts
     s.inner_tol = inner_tol
     s.fixed_schedule = 1 if fixed_schedule else 0
+    s.contact_fp32 = 1 if contact_fp32 else 0
     return s
 
 
@@ -194,7 +195,8 @@ class Batch:
 
     def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
-                 stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False):
+                 stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
+                 contact_fp32: bool = False):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -213,7 +215,8 @@ class Batch:
             d.elements = el.ctypes.data_as(C.POINTER(C.c_int32))
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
-        self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule)
+        self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
+                                contact_fp32)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -347,10 +350,11 @@ class Batch:
                     candidate_ms=ms.tolist())
 
     def phase_times(self):
-        out = np.zeros(12)
+        out = np.zeros(16)
         _check(lib().flash_phase_times(self._h, _dptr(out)))
         names = ["setup", "residual", "base_inverse", "rhs", "cap_build", "cap_lu", "direction", "line_search",
-                 "n_factor", "n_reuse", "n_ls_fail", "n_unconverged"]
+                 "n_factor", "n_reuse", "n_ls_fail", "n_unconverged", "cap_rows_mean", "cap_rows_max",
+                 "newton", "solves"]
         return dict(zip(names, out.tolist()))
 
     def kernel_times(self):
@@ -459,10 +463,10 @@ class Mlp:
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
-               fixed_schedule: bool = False) -> Batch:
+               fixed_schedule: bool = False, contact_fp32: bool = False) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
-              fixed_schedule=fixed_schedule)
+              fixed_schedule=fixed_schedule, contact_fp32=contact_fp32)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:
