@@ -1,0 +1,115 @@
+"""Health flags, error paths and checkpoint behaviour on the GPU (conditions forced from the
+host; every kernel still runs to completion).
+
+* a non-finite state in one env is flagged for that env only, and leaves every other env
+  bitwise unchanged (envs never couple);
+* an inner-iteration cap of 1 with one local-global iteration per step ends the squeeze's
+  steps above the tolerance and is reported as not converged;
+* a get/set state round trip is bitwise, and resuming after it (which drops the multiplier
+  history) agrees with the uninterrupted run within the solve tolerance;
+* invalid env indices and too small output capacities are rejected with their status.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2604_17513_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _F():
+    from paper_2604_17513_amd import flash as F
+    return F
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_nonfinite_env_is_isolated():
+    F = _F()
+    sc = scenes.squeeze_blocks(3, seed=31, hexes=4)
+    a = F.from_scene(sc)
+    b = F.from_scene(sc)
+    a.step(3)
+    b.step(3)
+    x, v = b.get_state(env=1)
+    x[5, 1] = np.nan
+    b.set_state(x, v, env=1)
+    a.step(3)
+    b.step(3)
+    per, mx, its, st = b.residual()
+    stats = b.stats()
+    _say("residuals", per, "flags", [s["flags"] for s in stats], "status", st)
+    assert st == F.FLASH_ERR_NONFINITE
+    assert stats[1]["flags"] & 1
+    assert not (stats[0]["flags"] & 1) and not (stats[2]["flags"] & 1)
+    xa, xb = a.split(a.get_state()[0]), b.split(b.get_state()[0])
+    assert np.array_equal(xa[0], xb[0]) and np.array_equal(xa[2], xb[2])
+    assert not np.all(np.isfinite(xb[1]))
+
+
+def test_iteration_cap_reports_not_converged():
+    F = _F()
+    # one local-global iteration with one Newton iteration: the squeeze's contact solve
+    # cannot reach the tolerance in a step (with K = 20 the iterations add up and it does)
+    sc = scenes.squeeze_blocks(2, seed=32, hexes=5)
+    sc.params.max_inner_iterations = 1
+    sc.params.lg_iterations = 1
+    b = F.from_scene(sc)
+    st = F.FLASH_OK
+    for _ in range(20):
+        b.step(1)
+        per, mx, its, st = b.residual()
+        if st != F.FLASH_OK:
+            break
+    stats = b.stats()
+    _say("capped residuals", per, "status", st, "flags", [s["flags"] for s in stats])
+    assert st == F.FLASH_ERR_NOT_CONVERGED
+    assert mx > sc.params.ncp_tol
+    assert any(s["flags"] & 2 for s in stats)
+
+
+def test_state_round_trip_and_resume():
+    F = _F()
+    sc = scenes.squeeze_blocks(2, seed=33, hexes=5)
+    a = F.from_scene(sc)
+    b = F.from_scene(sc)
+    a.step(12)
+    b.step(12)
+    x, v = b.get_state()
+    b.set_state(x, v)
+    x2, v2 = b.get_state()
+    assert np.array_equal(x, x2) and np.array_equal(v, v2)
+    a.step(6)
+    b.step(6)
+    xa, xb = a.get_state()[0], b.get_state()[0]
+    # the resumed run lost only its warm start: each step's solve still reaches the tolerance
+    L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+    err = np.abs(xa - xb).max()
+    _say(f"resume difference {err:.2e} m")
+    assert err <= 1e-5 * max(np.abs(xa).max(), L)
+    per, mx, its, st = b.residual()
+    assert mx <= sc.params.ncp_tol
+
+
+def test_invalid_env_and_capacity_are_rejected():
+    F = _F()
+    L = F.lib()
+    sc = scenes.squeeze_blocks(2, seed=34, hexes=4)
+    b = F.from_scene(sc)
+    b.step(2)
+    x = np.zeros((sc.envs[0].n_vertices, 3))
+    st = L.flash_set_state(b._h, 7, x.ctypes.data_as(C.POINTER(C.c_double)), None)
+    assert st == F.FLASH_ERR_INVALID_ARG
+    st = L.flash_get_state(b._h, -2, x.ctypes.data_as(C.POINTER(C.c_double)), None)
+    assert st == F.FLASH_ERR_INVALID_ARG
+    out = (F.flash_contact * 1)()
+    n = C.c_int32()
+    st = L.flash_contacts(b._h, 0, out, 1, C.byref(n))
+    assert st == F.FLASH_ERR_CAPACITY
+    assert n.value == len(b.contacts(0)["vertex"]) > 1
