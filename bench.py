@@ -12,12 +12,12 @@ prediction, K x (projection, assembly, global apply, contact solve, position
 update), finalisation).  The state is resident in HBM before the timed region.
 
 Arms, each on a fresh batch over the same steps (10 warm-up, then the timed
-steps): plain (previous-step warm start, one launch per phase, no graph),
-graph (the whole step captured in one HIP graph) and graph + learned warm
-start.  The learned arm's network is trained first, on the GPU, from a
+steps): plain (previous-step warm start, one launch per phase, no graph, one
+stream), batched (the envs in 2 groups, each stepped on its own stream as one
+captured HIP graph per step) and batched + learned warm start.  The learned arm's network is trained first, on the GPU, from a
 recorded rollout with seeds disjoint from the timed workload; recording and
 training are reported separately and excluded from the timed region.
-`value` is the graph + learned arm (every row of the hot path, batching and
+`value` is the batched + learned arm (every row of the hot path, batching and
 the learned start included); --quick runs the plain arm only.
 
 Prints one JSON line (rank 0).  The roofline object covers the dominant kernel
@@ -167,11 +167,12 @@ def mlp_roofline(F, torch, rows=1 << 22, reps=5):
             "flop_per_row": 70400, "avg_launch_ms": round(ms, 4)}
 
 
-def run_arm(F, sc, args, use_graph, warm_start, ws=None, time_apply=False):
+def run_arm(F, sc, args, use_graph, warm_start, ws=None, time_apply=False, groups=0):
     """Fresh batch of the workload; W warm-up steps, then K timed steps (synchronised both sides).
-    time_apply: HIP events around every kernel launch of the timed steps (per-class totals)."""
+    time_apply: HIP events around every kernel launch of the timed steps (per-class totals);
+    groups: env groups stepped on their own streams."""
     import torch
-    b = F.from_scene(sc, use_graph=use_graph, warm_start=warm_start)
+    b = F.from_scene(sc, use_graph=use_graph, warm_start=warm_start, stream_groups=groups)
     if ws is not None:
         b.ws_load(*ws)
     b.step(args.warmup)
@@ -200,6 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
+    ap.add_argument("--groups", type=int, default=2, help="env groups on separate streams in the batched arms")
     ap.add_argument("--quick", action="store_true",
                     help="plain eager arm only (no graph or learned arm, no breakdown, no network roofline)")
     args = ap.parse_args()
@@ -257,10 +259,13 @@ def main():
     value, dt_v, mx_v, over_v, dtype_arm = v_plain, dt, mx1, over1, "plain_eager"
     training, mlp_roof = None, None
     if not args.quick:
-        # A2: batched (whole step captured in one HIP graph), previous-step warm start
-        b, dt2, _, mx2, over2, its2 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV)
+        # A2: batched (each of 2 env groups on its own stream, its step captured in a HIP graph),
+        # previous-step warm start
+        b, dt2, _, mx2, over2, its2 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV,
+                                              groups=args.groups)
         b.close()
-        arms["graph"] = {"env_steps_per_s": round(args.envs * args.steps / dt2, 2),
+        arms["graph_groups"] = {"stream_groups": args.groups,
+                                 "env_steps_per_s": round(args.envs * args.steps / dt2, 2),
                          "ms_per_step": round(1000 * dt2 / args.steps, 3), "max_residual": mx2,
                          "env_steps_above_tol": over2, "newton_per_env_step": round(its2, 2)}
         log(f"graph arm: {1000 * dt2 / args.steps:.2f} ms/step")
@@ -268,15 +273,16 @@ def main():
         w, nm, training = train_warm_start(F, scenes, torch)
         log(f"trained warm start on {training['pairs']} pairs in {training['train_s']}s")
         b, dt3, _, mx3, over3, its3 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_LEARNED,
-                                              ws=(w, nm))
+                                              ws=(w, nm), groups=args.groups)
         picks = sum(s_["ws_state"] & 1 for s_ in b.stats())
         b.close()
-        arms["graph_learned"] = {"env_steps_per_s": round(args.envs * args.steps / dt3, 2),
+        arms["graph_groups_learned"] = {"stream_groups": args.groups,
+                                        "env_steps_per_s": round(args.envs * args.steps / dt3, 2),
                                  "ms_per_step": round(1000 * dt3 / args.steps, 3), "max_residual": mx3,
                                  "env_steps_above_tol": over3, "newton_per_env_step": round(its3, 2),
                                  "envs_started_from_prediction_last_step": int(picks)}
         log(f"graph+learned arm: {1000 * dt3 / args.steps:.2f} ms/step")
-        value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "graph_learned"
+        value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "graph_groups_learned"
         mlp_roof = mlp_roofline(F, torch)
         log(f"network forward: {mlp_roof['achieved']} TFLOP/s")
 

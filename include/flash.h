@@ -119,6 +119,12 @@ typedef struct {
                                      times (batches of up to 4096 envs); 1: default schedule, envs
                                      in index order.  Every schedule gives bitwise identical
                                      results. */
+  int32_t stream_groups;          /* 0 or 1: one stream.  G >= 2: the envs are split into G
+                                     contiguous groups, each stepped on a stream of its own so that
+                                     one group's contact-solve tail overlaps the others' work
+                                     (hip_stream must then be NULL).  Results are bitwise those of
+                                     one group: envs never couple. */
+  int32_t reserved_params;
 } flash_params;
 
 /* One contact of the last step.  impulse = h F lambda in the world frame (N s);
@@ -213,7 +219,9 @@ const char *flash_kernel_name(int32_t i);
  * update; batching over uneven envs, Eq. 11-12).  One workgroup per (env,
  * column tile) work item, items of the largest envs first.  info[0] = columns
  * per tile, info[1] = rows in flight per wave, info[2] = work items, info[3] =
- * 1 if the autotuner chose it.  cand_ms (6 doubles, may be NULL): the
+ * 1 if the autotuner chose it, info[4] = stream groups (info holds 5 values).
+ * For a grouped batch the choice of group 0 is reported and the work items
+ * are summed over the groups.  cand_ms (6 doubles, may be NULL): the
  * autotuner's milliseconds per apply launch for tiles of 8, 16 and 32 bytes
  * per lane, each with 4 and 8 rows in flight (0 when not tuned). */
 flash_status flash_schedule_info(flash_batch *b, int32_t *info, double *cand_ms);

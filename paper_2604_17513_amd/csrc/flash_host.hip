@@ -318,6 +318,11 @@ struct flash_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   int device = 0;
+  // env groups: a batch created with stream_groups >= 2 holds one sub-batch per contiguous
+  // group of envs, each on a stream of its own, so that one group's contact-solve tail
+  // overlaps the other groups' work; the C ABI dispatches env indices to the groups
+  std::vector<flash_batch*> groups;
+  std::vector<int> gofs;      // first env of each group, then n_envs
   // explicit-inverse product schedule: work lists for the three tile widths, the chosen
   // variant, and the autotuner's measurements (ms per apply launch of each candidate)
   int2* gemv_items[3] = {nullptr, nullptr, nullptr};
@@ -332,6 +337,7 @@ struct flash_batch {
   int* ws_coff = nullptr;
 
   ~flash_batch() {
+    for (flash_batch* g : groups) delete g;
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (auto& pe : pending) { (void)hipEventDestroy(pe.second.first); (void)hipEventDestroy(pe.second.second); }
@@ -919,6 +925,31 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     if (!(d.density > 0) || !(d.young > 0) || !(d.poisson > -1 && d.poisson < 0.5) || !(d.mu >= 0))
       return fail(FLASH_ERR_INVALID_ARG, "invalid material");
   }
+  if (p->stream_groups < 0) return fail(FLASH_ERR_INVALID_ARG, "stream_groups < 0");
+  if (p->stream_groups > 1 && n_envs > 1) {
+    if (hip_stream) return fail(FLASH_ERR_INVALID_ARG, "stream_groups >= 2 runs on streams owned by the batch");
+    const int G = std::min<int>(p->stream_groups, n_envs);
+    flash_batch* b = new flash_batch();
+    b->p = *p;
+    b->n_envs = n_envs;
+    b->fp64 = p->precision == FLASH_FP64;
+    b->voff.assign(n_envs + 1, 0);
+    for (int e = 0; e < n_envs; ++e) b->voff[e + 1] = b->voff[e] + envs[e].n_vertices;
+    b->NV = b->voff[n_envs];
+    b->gofs.assign(G + 1, 0);
+    for (int g = 0; g <= G; ++g) b->gofs[g] = (int)((int64_t)n_envs * g / G);
+    flash_params q = *p;
+    q.stream_groups = 0;
+    for (int g = 0; g < G; ++g) {
+      flash_batch* c = nullptr;
+      const flash_status st = flash_create_batch(envs + b->gofs[g], b->gofs[g + 1] - b->gofs[g], &q, nullptr, &c);
+      if (st != FLASH_OK) { delete b; return st; }
+      b->groups.push_back(c);
+    }
+    b->tuned = true;
+    *out = b;
+    return FLASH_OK;
+  }
   flash_batch* b = nullptr;
   try {
     b = new flash_batch();
@@ -961,10 +992,37 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
 
 flash_status flash_destroy_batch(flash_batch* b) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
-  (void)hipStreamSynchronize(b->stream);
+  for (flash_batch* g : b->groups) (void)hipStreamSynchronize(g->stream);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
   delete b;
   return FLASH_OK;
 }
+
+}  // extern "C"
+
+// ---- env groups: dispatch to the sub-batches --------------------------------------
+#define HIPCHK_STATUS(x)                                                               \
+  do {                                                                                 \
+    hipError_t _e = (x);                                                               \
+    if (_e != hipSuccess) return fail(FLASH_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+namespace {
+int group_of(const flash_batch* b, int env) {
+  int g = 0;
+  while (env >= b->gofs[g + 1]) ++g;
+  return g;
+}
+template <class F>
+flash_status each_group(flash_batch* b, F&& f) {
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    const flash_status st = f((int)g, b->groups[g]);
+    if (st != FLASH_OK) return st;
+  }
+  return FLASH_OK;
+}
+}  // namespace
+
+extern "C" {
 
 #define GUARD(body)                                            \
   try {                                                        \
@@ -977,12 +1035,26 @@ flash_status flash_destroy_batch(flash_batch* b) {
 
 flash_status flash_set_state(flash_batch* b, int32_t env, const double* x, const double* v) {
   if (!b || !x || bad_env(b, env)) return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env or null x");
+  if (!b->groups.empty()) {
+    if (env >= 0) { const int g = group_of(b, env); return flash_set_state(b->groups[g], env - b->gofs[g], x, v); }
+    return each_group(b, [&](int g, flash_batch* c) {
+      const size_t o = 3 * (size_t)b->voff[b->gofs[g]];
+      return flash_set_state(c, -1, x + o, v ? v + o : nullptr);
+    });
+  }
   GUARD(if (b->fp64) set_state_t<double>(b, env, x, v); else set_state_t<float>(b, env, x, v));
   return FLASH_OK;
 }
 
 flash_status flash_get_state(flash_batch* b, int32_t env, double* x, double* v) {
   if (!b || bad_env(b, env)) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or env");
+  if (!b->groups.empty()) {
+    if (env >= 0) { const int g = group_of(b, env); return flash_get_state(b->groups[g], env - b->gofs[g], x, v); }
+    return each_group(b, [&](int g, flash_batch* c) {
+      const size_t o = 3 * (size_t)b->voff[b->gofs[g]];
+      return flash_get_state(c, -1, x ? x + o : nullptr, v ? v + o : nullptr);
+    });
+  }
   GUARD(if (b->fp64) get_state_t<double>(b, env, x, v); else get_state_t<float>(b, env, x, v));
   return FLASH_OK;
 }
@@ -993,12 +1065,22 @@ flash_status flash_set_obstacles(flash_batch* b, int32_t env, const flash_obstac
   const int ne = env < 0 ? b->n_envs : 1;
   for (int q = 0; q < ne * n; ++q)
     if (o[q].kind < FLASH_PLANE || o[q].kind > FLASH_CAPSULE) return fail(FLASH_ERR_INVALID_ARG, "bad obstacle kind");
+  if (!b->groups.empty()) {
+    if (env >= 0) { const int g = group_of(b, env); return flash_set_obstacles(b->groups[g], env - b->gofs[g], o, n); }
+    return each_group(b, [&](int g, flash_batch* c) {
+      return flash_set_obstacles(c, -1, o ? o + (size_t)b->gofs[g] * n : nullptr, n);
+    });
+  }
   GUARD(if (b->fp64) set_obstacles_t<double>(b, env, o, n); else set_obstacles_t<float>(b, env, o, n));
   return FLASH_OK;
 }
 
 flash_status flash_get_obstacles(flash_batch* b, int32_t env, flash_obstacle* o, int32_t capacity, int32_t* n_out) {
   if (!b || env < 0 || env >= b->n_envs || !n_out) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or env");
+  if (!b->groups.empty()) {
+    const int g = group_of(b, env);
+    return flash_get_obstacles(b->groups[g], env - b->gofs[g], o, capacity, n_out);
+  }
   const int n = b->nobs[env];
   *n_out = n;
   if (capacity < n || !o) return fail(FLASH_ERR_CAPACITY, "obstacle capacity too small");
@@ -1008,11 +1090,20 @@ flash_status flash_get_obstacles(flash_batch* b, int32_t env, flash_obstacle* o,
 
 flash_status flash_step(flash_batch* b, int32_t n_steps) {
   if (!b || n_steps < 0) return fail(FLASH_ERR_INVALID_ARG, "invalid batch or step count");
+  if (!b->groups.empty()) {
+    // step by step across the groups, so that every group's queue is fed in turn
+    for (int i = 0; i < n_steps; ++i) {
+      const flash_status st = each_group(b, [&](int, flash_batch* c) { return flash_step(c, 1); });
+      if (st != FLASH_OK) return st;
+    }
+    return FLASH_OK;
+  }
   GUARD(b->step(n_steps));
   return FLASH_OK;
 }
 
 flash_status flash_synchronize(flash_batch* b) {
+  if (b && !b->groups.empty()) return each_group(b, [&](int, flash_batch* c) { return flash_synchronize(c); });
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
   GUARD(HIPCHK(hipStreamSynchronize(b->stream)));
   return FLASH_OK;
@@ -1020,6 +1111,30 @@ flash_status flash_synchronize(flash_batch* b) {
 
 flash_status flash_contacts(flash_batch* b, int32_t env, flash_contact* out, int32_t capacity, int32_t* n_out) {
   if (!b || bad_env(b, env) || !n_out || capacity < 0) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  if (!b->groups.empty()) {
+    if (env >= 0) {
+      const int g = group_of(b, env);
+      const flash_status st = flash_contacts(b->groups[g], env - b->gofs[g], out, capacity, n_out);
+      if (st == FLASH_OK)
+        for (int k = 0; k < *n_out; ++k) out[k].env += b->gofs[g];
+      return st;
+    }
+    int total = 0;
+    bool short_cap = false;
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      int32_t ng = 0;
+      const int room = std::max(capacity - total, 0);
+      const flash_status st = flash_contacts(b->groups[g], -1, (out && room > 0) ? out + total : nullptr, room, &ng);
+      if (st == FLASH_ERR_CAPACITY || (st == FLASH_ERR_INVALID_ARG && room == 0)) short_cap = true;
+      else if (st != FLASH_OK) return st;
+      if (!short_cap)
+        for (int k = 0; k < ng; ++k) out[total + k].env += b->gofs[g];
+      total += ng;
+    }
+    *n_out = total;
+    if (short_cap || total > capacity) return fail(FLASH_ERR_CAPACITY, "contact capacity too small");
+    return FLASH_OK;
+  }
   int over = 0;
   GUARD(over = b->fp64 ? contacts_t<double>(b, env, out, capacity, n_out) : contacts_t<float>(b, env, out, capacity, n_out));
   if (over) return fail(FLASH_ERR_CAPACITY, "contact capacity too small");
@@ -1028,6 +1143,8 @@ flash_status flash_contacts(flash_batch* b, int32_t env, flash_contact* out, int
 
 flash_status flash_stats(flash_batch* b, flash_env_stats* per_env) {
   if (!b || !per_env) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  if (!b->groups.empty())
+    return each_group(b, [&](int g, flash_batch* c) { return flash_stats(c, per_env + b->gofs[g]); });
   GUARD(if (b->fp64) stats_t<double>(b, per_env); else stats_t<float>(b, per_env));
   return FLASH_OK;
 }
@@ -1054,6 +1171,7 @@ flash_status flash_residual(flash_batch* b, double* per_env, double* max_out, in
 
 flash_status flash_set_kernel_timing(flash_batch* b, int32_t enable) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  if (!b->groups.empty()) return each_group(b, [&](int, flash_batch* c) { return flash_set_kernel_timing(c, enable); });
   GUARD(b->collect_timing());
   b->timing = enable != 0;
   b->timing_mask = (uint32_t)enable;
@@ -1063,6 +1181,24 @@ flash_status flash_set_kernel_timing(flash_batch* b, int32_t enable) {
 
 flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launches, int32_t cap, int32_t* n_out) {
   if (!b || !n_out) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  if (!b->groups.empty()) {
+    // totals summed over the groups (their launches overlap in time)
+    std::vector<double> t(K_COUNT, 0.0), tg(K_COUNT);
+    std::vector<int64_t> n(K_COUNT, 0), ng(K_COUNT);
+    const flash_status st = each_group(b, [&](int, flash_batch* c) {
+      int32_t k = 0;
+      const flash_status s2 = flash_kernel_times(c, tg.data(), ng.data(), K_COUNT, &k);
+      for (int q = 0; q < K_COUNT; ++q) { t[q] += tg[q]; n[q] += ng[q]; }
+      return s2;
+    });
+    if (st != FLASH_OK) return st;
+    *n_out = K_COUNT;
+    for (int k = 0; k < K_COUNT && k < cap; ++k) {
+      if (total_ms) total_ms[k] = t[k];
+      if (launches) launches[k] = n[k];
+    }
+    return FLASH_OK;
+  }
   GUARD(b->collect_timing());
   *n_out = K_COUNT;
   for (int k = 0; k < K_COUNT && k < cap; ++k) {
@@ -1075,6 +1211,23 @@ flash_status flash_kernel_times(flash_batch* b, double* total_ms, int64_t* launc
 flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* over_out, int64_t* newton_out,
                                     int64_t* env_steps_out, int32_t reset) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  if (!b->groups.empty()) {
+    double m = 0.0;
+    int64_t over = 0, newton = 0, steps = 0;
+    const flash_status st = each_group(b, [&](int, flash_batch* c) {
+      double mg = 0.0;
+      int64_t og = 0, ng = 0, sg = 0;
+      const flash_status s2 = flash_residual_history(c, &mg, &og, &ng, &sg, reset);
+      m = (mg > m || !(mg == mg)) ? mg : m;
+      over += og; newton += ng; steps += sg;
+      return s2;
+    });
+    if (max_out) *max_out = m;
+    if (over_out) *over_out = over;
+    if (newton_out) *newton_out = newton;
+    if (env_steps_out) *env_steps_out = steps;
+    return st;
+  }
   try {
     HIPCHK(hipStreamSynchronize(b->stream));
     const int ne = b->n_envs;
@@ -1103,11 +1256,25 @@ flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* ov
 
 flash_status flash_schedule_info(flash_batch* b, int32_t* info, double* cand_ms) {
   if (!b || !info) return fail(FLASH_ERR_INVALID_ARG, "null argument");
+  if (!b->groups.empty()) {
+    // group 0's choice; work items summed over the groups; info[4] = groups
+    int32_t items = 0, gi[5];
+    for (size_t g = 0; g < b->groups.size(); ++g) {
+      const flash_status st = flash_schedule_info(b->groups[g], gi, g == 0 ? cand_ms : nullptr);
+      if (st != FLASH_OK) return st;
+      if (g == 0) { info[0] = gi[0]; info[1] = gi[1]; info[3] = gi[3]; }
+      items += gi[2];
+    }
+    info[2] = items;
+    info[4] = (int32_t)b->groups.size();
+    return FLASH_OK;
+  }
   const int es = b->fp64 ? 8 : 4;
   info[0] = 64 * ((8 << b->sched.vw) / es);
   info[1] = b->sched.unroll;
   info[2] = b->sched.n_items;
   info[3] = (b->tuned && !b->p.fixed_schedule) ? 1 : 0;
+  info[4] = 1;
   if (cand_ms)
     for (int k = 0; k < 6; ++k) cand_ms[k] = b->cand_ms[k];
   return FLASH_OK;
@@ -1115,6 +1282,24 @@ flash_status flash_schedule_info(flash_batch* b, int32_t* info, double* cand_ms)
 
 flash_status flash_phase_times(flash_batch* b, double* ms_out) {
   if (!b || !ms_out) return fail(FLASH_ERR_INVALID_ARG, "invalid arguments");
+  if (!b->groups.empty()) {
+    // per-env means weighted by the groups' env counts; the largest system is a maximum
+    double acc[16] = {0}, g16[16];
+    double rows = 0.0, facts = 0.0;
+    const flash_status st = each_group(b, [&](int g, flash_batch* c) {
+      const flash_status s2 = flash_phase_times(c, g16);
+      const double w = (double)(b->gofs[g + 1] - b->gofs[g]) / b->n_envs;
+      for (int k = 0; k < 16; ++k)
+        if (k != 12 && k != 13) acc[k] += w * g16[k];
+      rows += g16[12] * g16[8] * w;
+      facts += g16[8] * w;
+      acc[13] = std::max(acc[13], g16[13]);
+      return s2;
+    });
+    for (int k = 0; k < 16; ++k) ms_out[k] = acc[k];
+    ms_out[12] = facts > 0 ? rows / facts : 0.0;
+    return st;
+  }
   try {
     HIPCHK(hipStreamSynchronize(b->stream));
     const int ne = b->n_envs;
@@ -1149,6 +1334,7 @@ flash_status flash_phase_times(flash_batch* b, double* ms_out) {
 
 flash_status flash_ws_load(flash_batch* b, const uint16_t* w, size_t n_params, const float* norm) {
   if (!b || !w || !norm) return fail(FLASH_ERR_INVALID_ARG, "null argument");
+  if (!b->groups.empty()) return each_group(b, [&](int, flash_batch* c) { return flash_ws_load(c, w, n_params, norm); });
   if (n_params != (size_t)MlpLayout::total) return fail(FLASH_ERR_INVALID_ARG, "n_params must be 35587");
   for (int k = 0; k < kNorm; ++k)
     if (!std::isfinite(norm[k])) return fail(FLASH_ERR_INVALID_ARG, "non-finite normalisation");
@@ -1177,6 +1363,11 @@ flash_status flash_ws_load(flash_batch* b, const uint16_t* w, size_t n_params, c
 
 flash_status flash_ws_record(flash_batch* b, int32_t on) {
   if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  if (!b->groups.empty()) {
+    const flash_status st = each_group(b, [&](int, flash_batch* c) { return flash_ws_record(c, on); });
+    b->ws_record = on != 0;
+    return st;
+  }
   try {
     if (on) b->ensure_ws_buffers();
     b->ws_record = on != 0;
@@ -1191,6 +1382,21 @@ flash_status flash_ws_collect(flash_batch* b, float* feat_dev, float* lab_dev, i
   if (!b || !feat_dev || !lab_dev || !n_inout || *n_inout < 0 || capacity < 0)
     return fail(FLASH_ERR_INVALID_ARG, "null or negative argument");
   if (!b->ws_record) return fail(FLASH_ERR_INVALID_ARG, "recording is off (flash_ws_record)");
+  if (!b->groups.empty()) {
+    // rows of the groups in env order; nothing is written unless all of them fit
+    int64_t rows = 0;
+    for (flash_batch* c : b->groups) {
+      HIPCHK_STATUS(hipStreamSynchronize(c->stream));
+      std::vector<int> cc(c->n_envs);
+      const int cap = c->fp64 ? c->bd.cap : c->bf.cap;
+      HIPCHK_STATUS(hipMemcpy(cc.data(), c->fp64 ? c->bd.ccount : c->bf.ccount, c->n_envs * sizeof(int),
+                              hipMemcpyDeviceToHost));
+      for (int q : cc) rows += std::min(q, cap);
+    }
+    if (*n_inout + rows > capacity)
+      return fail(FLASH_ERR_CAPACITY, "collect needs " + std::to_string(*n_inout + rows) + " rows");
+    return each_group(b, [&](int, flash_batch* c) { return flash_ws_collect(c, feat_dev, lab_dev, capacity, n_inout); });
+  }
   try {
     std::vector<int> cc(b->n_envs);
     const int cap = b->fp64 ? b->bd.cap : b->bf.cap;

@@ -61,7 +61,8 @@ class flash_params(C.Structure):
                 ("max_inner_iterations", C.c_int32), ("ncp_tol", C.c_double), ("contact_margin", C.c_double),
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
-                ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32)]
+                ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32),
+                ("stream_groups", C.c_int32), ("reserved_params", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -156,7 +157,8 @@ def _dptr(a: np.ndarray):
 
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
-                  fixed_schedule: bool = False, contact_fp32: bool = False) -> flash_params:
+                  fixed_schedule: bool = False, contact_fp32: bool = False,
+                  stream_groups: int = 0) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -173,6 +175,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.inner_tol = inner_tol
     s.fixed_schedule = 1 if fixed_schedule else 0
     s.contact_fp32 = 1 if contact_fp32 else 0
+    s.stream_groups = int(stream_groups)
     return s
 
 
@@ -196,7 +199,7 @@ class Batch:
     def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
                  stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
-                 contact_fp32: bool = False):
+                 contact_fp32: bool = False, stream_groups: int = 0):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -216,7 +219,7 @@ class Batch:
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
-                                contact_fp32)
+                                contact_fp32, stream_groups)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -343,11 +346,11 @@ class Batch:
 
     def schedule_info(self):
         """(columns per tile, rows in flight per wave, work items, tuned, candidate ms per apply launch)."""
-        info = np.zeros(4, dtype=np.int32)
+        info = np.zeros(5, dtype=np.int32)
         ms = np.zeros(6)
         _check(lib().flash_schedule_info(self._h, info.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(ms)))
         return dict(tile_cols=int(info[0]), unroll=int(info[1]), work_items=int(info[2]), tuned=bool(info[3]),
-                    candidate_ms=ms.tolist())
+                    stream_groups=int(info[4]), candidate_ms=ms.tolist())
 
     def phase_times(self):
         out = np.zeros(16)
@@ -463,10 +466,10 @@ class Mlp:
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
-               fixed_schedule: bool = False, contact_fp32: bool = False) -> Batch:
+               fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
-              fixed_schedule=fixed_schedule, contact_fp32=contact_fp32)
+              fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:

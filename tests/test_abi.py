@@ -63,6 +63,6 @@ def test_struct_layouts_match_header_field_order():
     # the ctypes mirrors follow the header's field order; sizes are those of the C structs on LP64
     assert C.sizeof(F.flash_obstacle) == 8 + 8 * (3 + 9 + 3 + 3)
     assert C.sizeof(F.flash_env_desc) == 16 + 16 + 8 * 6
-    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8
+    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8
     assert C.sizeof(F.flash_contact) == 16 + 8 * (3 + 3 + 1 + 3 + 3)
     assert C.sizeof(F.flash_env_stats) == 24 + 8

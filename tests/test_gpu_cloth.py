@@ -134,3 +134,54 @@ def test_autotuned_schedule_is_bitwise_identical():
     assert it["work_items"] == n_tiles
     assert np.array_equal(tuned.get_state()[0], fixed.get_state()[0])
     assert np.array_equal(tuned.get_state()[1], fixed.get_state()[1])
+
+
+@pytest.mark.parametrize("groups", [2, 3])
+def test_stream_groups_match_one_group(groups):
+    """A batch split into env groups on separate streams gives the bits of one batch, and the
+    ABI's per-env and all-env calls address the same envs."""
+    torch = pytest.importorskip("torch")
+    F = _F()
+    parts = [scenes.cloth_drop(n=10, seed=9), scenes.drop_cube(seed=10, hexes=3, drop_height=0.002),
+             scenes.squeeze_blocks(2, seed=11, hexes=4), scenes.cloth_drop(n=7, seed=12)]
+    envs, xs, vs, obs = [], [], [], []
+    for p in parts:
+        envs += p.envs; xs += p.x0; vs += p.v0; obs += p.obstacles
+    sc = scenes.Scene(envs, xs, vs, obs, scenes.Params(lg_iterations=6))
+    one = F.from_scene(sc)
+    grp = F.from_scene(sc, stream_groups=groups, use_graph=True)
+    one.ws_record(True)
+    grp.ws_record(True)
+    for b in (one, grp):
+        b.step(5)
+    cap = 5 * 320
+    rows = []
+    for b in (one, grp):
+        fd = torch.zeros((cap, 16), dtype=torch.float32, device="cuda")
+        ld = torch.zeros((cap, 3), dtype=torch.float32, device="cuda")
+        n = b.ws_collect(fd, ld, cap, 0)
+        rows.append((n, fd[:n].cpu().numpy(), ld[:n].cpu().numpy()))
+    assert rows[0][0] == rows[1][0] and np.array_equal(rows[0][1], rows[1][1]) and np.array_equal(rows[0][2], rows[1][2])
+    # per-env state round trip through the groups
+    x3, v3 = grp.get_state(env=3)
+    assert np.array_equal(x3, one.get_state(env=3)[0])
+    grp.set_state(x3, v3, env=3)
+    one.set_state(x3, v3, env=3)
+    for b in (one, grp):
+        b.step(4)
+    xo, vo = one.get_state()
+    xg, vg = grp.get_state()
+    assert np.array_equal(xo, xg) and np.array_equal(vo, vg)
+    co, cg = one.contacts(), grp.contacts()
+    for k in ("env", "vertex", "obstacle", "lambda"):
+        assert np.array_equal(co[k], cg[k]), k
+    for e in (0, 4):
+        assert np.array_equal(one.contacts(e)["vertex"], grp.contacts(e)["vertex"])
+        assert np.array_equal(np.array([o.center for o in one.get_obstacles(e)]),
+                              np.array([o.center for o in grp.get_obstacles(e)]))
+    so, sg = one.stats(), grp.stats()
+    assert [s["contacts"] for s in so] == [s["contacts"] for s in sg]
+    assert [s["residual"] for s in so] == [s["residual"] for s in sg]
+    assert one.residual_history(full=True) == grp.residual_history(full=True)
+    info = grp.schedule_info()
+    assert info["stream_groups"] == groups
