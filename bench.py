@@ -13,7 +13,7 @@ update), finalisation).  The state is resident in HBM before the timed region.
 
 Arms, each on a fresh batch over the same steps (10 warm-up, then the timed
 steps): plain (previous-step warm start, one launch per phase, no graph, one
-stream), batched (the envs in 2 groups, each stepped on its own stream as one
+stream), batched (the envs in 3 groups, each stepped on its own stream as one
 captured HIP graph per step) and batched + learned warm start.  The learned arm's network is trained first, on the GPU, from a
 recorded rollout with seeds disjoint from the timed workload; recording and
 training are reported separately and excluded from the timed region.
@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
-    ap.add_argument("--groups", type=int, default=2, help="env groups on separate streams in the batched arms")
+    ap.add_argument("--groups", type=int, default=3, help="env groups on separate streams in the batched arms")
     ap.add_argument("--quick", action="store_true",
                     help="plain eager arm only (no graph or learned arm, no breakdown, no network roofline)")
     args = ap.parse_args()
@@ -259,7 +259,7 @@ def main():
     value, dt_v, mx_v, over_v, dtype_arm = v_plain, dt, mx1, over1, "plain_eager"
     training, mlp_roof = None, None
     if not args.quick:
-        # A2: batched (each of 2 env groups on its own stream, its step captured in a HIP graph),
+        # A2: batched (each env group on its own stream, its step captured in a HIP graph),
         # previous-step warm start
         b, dt2, _, mx2, over2, its2 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV,
                                               groups=args.groups)
