@@ -199,6 +199,10 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
           B.cobs[j] = o;
           T* F = B.cframe + 9 * (size_t)j;
           for (int k = 0; k < 3; ++k) { F[k] = (T)n[k]; F[3 + k] = (T)t1[k]; F[6 + k] = (T)t2[k]; }
+          if (sizeof(T) == 4 && B.cframe64) {
+            double* F64 = B.cframe64 + 9 * (size_t)j;
+            for (int k = 0; k < 3; ++k) { F64[k] = n[k]; F64[3 + k] = t1[k]; F64[6 + k] = t2[k]; }
+          }
           B.cd0[j] = (T)d;
           B.cd0d[j] = d;
           const double* dob = sh_dob[o];
@@ -270,11 +274,12 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
   for (int jj = threadIdx.x; jj < c; jj += kBlock) {
     const int j = e * B.cap + jj;
     const int vi = v0 + B.cvert[j];
-    const T* F = B.cframe + 9 * (size_t)j;
+    double F[9];
+    for (int k = 0; k < 9; ++k) F[k] = B.cframe64 ? B.cframe64[9 * (size_t)j + k] : (double)B.cframe[9 * (size_t)j + k];
     double uw[3] = {(double)B.u[vi], (double)B.u[B.NV + vi], (double)B.u[2 * B.NV + vi]};
     double Y[3];
     for (int a = 0; a < 3; ++a)
-      Y[a] = (double)F[3 * a] * uw[0] + (double)F[3 * a + 1] * uw[1] + (double)F[3 * a + 2] * uw[2];
+      Y[a] = F[3 * a] * uw[0] + F[3 * a + 1] * uw[1] + F[3 * a + 2] * uw[2];
     double s = h * h / (double)B.mass[vi];
     double ln = B.clam[3 * j], l1 = B.clam[3 * j + 1], l2 = B.clam[3 * j + 2];
     double cn = B.cd0d[j] + Y[0];

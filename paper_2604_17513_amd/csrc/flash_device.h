@@ -83,6 +83,8 @@ struct DevBatch {
   int* cvert;                 // local vertex index
   int* cobs;
   T* cframe;                  // [9 per contact] columns n, t1, t2: frame[3*a + k] = column a, comp k
+  double* cframe64;           // the same frames in FP64 (FP32 batches with an FP64 contact solve; else
+                              // nullptr, or cframe itself in FP64 batches)
   T* cd0;
   T* cdob;                    // [2 per contact] T^T dobs
   T* cs;                      // residual scale h^2/m_v

@@ -674,6 +674,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.cnew = dalloc<int>(ne * cap, own);
   B.cd0d = dalloc<double>(ne * cap, own);
   B.csp64 = (sizeof(T) == 8 || !b->p.contact_fp32) ? 1 : 0;
+  if constexpr (sizeof(T) == 8) B.cframe64 = reinterpret_cast<double*>(B.cframe);
+  else B.cframe64 = B.csp64 ? dalloc<double>(9 * ne * cap, own) : nullptr;
   const size_t cts = B.csp64 ? sizeof(double) : sizeof(T);
   B.Gc = dalloc<unsigned char>(ne * cap * cap * cts, own);
   B.Ginv = dalloc<unsigned char>(ne * cap * cap * cts, own);

@@ -6,6 +6,8 @@
 // system A q = b + h^2 H^T lambda becomes
 //     A u = M u~ + h^2 sum_e w_e G_e^T (p_e - G_e x_t) + h^2 H^T lambda,
 // u~ = h v + h^2 g, which keeps FP32 relative precision on small quantities.
+#include <type_traits>
+
 #include "flash_device.h"
 #include "flash_launch.h"
 
@@ -900,7 +902,12 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   const CT hh = (CT)(B.h * B.h), ihh = CT(1) / hh;
   const CT mu = mu_env[e];
   const double dmaxf = B.max_force;
-  const T* Fr = B.cframe + 9 * cb;
+  // contact frames in the solve's precision: FP32 frames are orthonormal only to ~1e-7, and the
+  // Woodbury step applies the base inverse as F^T (.) F, which amplifies that by the condition
+  // of the contact-space operator (~1e5 for stiff bending against light vertices)
+  const CT* Fr;
+  if constexpr (std::is_same<CT, T>::value) Fr = B.cframe + 9 * cb;
+  else Fr = B.cframe64 + 9 * cb;
   CT* yfg = static_cast<CT*>(B.cyf) + 3 * cb;     // free displacement y_free in contact frames
   const int tid = threadIdx.x;
   // per-phase wall-clock accounting (thread 0, when enabled)
@@ -929,7 +936,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   int nb = sh_nb;
   for (int j = tid; j < c; j += kBlock) {
     S.pos[j] = -1;
-    const T* F = Fr + 9 * j;
+    const CT* F = Fr + 9 * j;
     const int vi = v0 + B.cvert[cb + j];
     CT zw0 = B.z[vi], zw1 = B.z[B.NV + vi], zw2 = B.z[2 * B.NV + vi];
     for (int a = 0; a < 3; ++a) {
@@ -949,7 +956,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
   // Y = y_free + W lambda (fw = F lambda world; Gc symmetric -> coalesced column reads)
   auto apply_W = [&](const auto* vin, CT* vout) {
     for (int j = tid; j < c; j += kBlock) {
-      const T* F = Fr + 9 * j;
+      const CT* F = Fr + 9 * j;
       const CT l0 = (CT)vin[3 * j], l1 = (CT)vin[3 * j + 1], l2 = (CT)vin[3 * j + 2];
       for (int k = 0; k < 3; ++k) S.fw[3 * j + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
     }
@@ -960,7 +967,7 @@ __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, 
         const CT g = Gc[(size_t)k * c + j];
         d0 += g * S.fw[3 * k]; d1 += g * S.fw[3 * k + 1]; d2 += g * S.fw[3 * k + 2];
       }
-      const T* F = Fr + 9 * j;
+      const CT* F = Fr + 9 * j;
       for (int a = 0; a < 3; ++a) vout[3 * j + a] = hh * (F[3 * a] * d0 + F[3 * a + 1] * d1 + F[3 * a + 2] * d2);
     }
     __syncthreads();
@@ -1218,7 +1225,7 @@ restart:
           const int ja = Rj[q], j = ja / 3, a = ja - 3 * (ja / 3);
           CT K[3][3], E[3][3];
           contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
-          const T* F = Fr + 9 * j;
+          const CT* F = Fr + 9 * j;
           CT* rv = Rv + 16 * q;
           for (int k = 0; k < 3; ++k) {
             rv[k] = E[a][0] * F[k] + E[a][1] * F[3 + k] + E[a][2] * F[6 + k];
@@ -1255,7 +1262,7 @@ restart:
     auto wsolve = [&](const CT* rin, CT* dout) {
       for (int p = tid; p < nb; p += kBlock) {
         const int j = S.bas[p];
-        const T* F = Fr + 9 * j;
+        const CT* F = Fr + 9 * j;
         const CT r0 = rin[3 * j], r1 = rin[3 * j + 1], r2 = rin[3 * j + 2];
         for (int k = 0; k < 3; ++k) S.fw[3 * p + k] = F[k] * r0 + F[3 + k] * r1 + F[6 + k] * r2;
       }
@@ -1267,7 +1274,7 @@ restart:
           w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
         }
         const int j = S.bas[p];
-        const T* F = Fr + 9 * j;
+        const CT* F = Fr + 9 * j;
         for (int a = 0; a < 3; ++a) S.x0[3 * j + a] = ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
       }
       __syncthreads();
@@ -1290,7 +1297,7 @@ restart:
             w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
           }
           const int j = S.bas[p];
-          const T* F = Fr + 9 * j;
+          const CT* F = Fr + 9 * j;
           for (int a = 0; a < 3; ++a)
             dout[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
         }
@@ -1389,7 +1396,7 @@ restart:
   }
   // ---- write back ----
   for (int j = tid; j < c; j += kBlock) {
-    const T* F = Fr + 9 * j;
+    const CT* F = Fr + 9 * j;
     const CT l0 = (CT)S.lam[3 * j], l1 = (CT)S.lam[3 * j + 1], l2 = (CT)S.lam[3 * j + 2];
     for (int a = 0; a < 3; ++a) B.clam[3 * (cb + j) + a] = S.lam[3 * j + a];
     for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);

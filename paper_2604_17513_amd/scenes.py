@@ -289,3 +289,53 @@ def single_tet_scene(kind: str = "ground", seed: int = 0, tang_speed: float = 0.
                   mu=float(rng.uniform(0.1, 0.9)))
     params = Params(lg_iterations=2)
     return Scene([env], [x0], [v0], [[ground()]], params, name="single_tet")
+
+
+def uneven_batch(n_envs: int, seed: int = 0, max_tet_vertices: int = 8000, max_cloth_side: int = 48,
+                 lg_iterations: int = 10) -> Scene:
+    """Mixed batch of cloth sheets and tet blocks with log-uniform sizes.
+
+    Per env (seeded): a cloth sheet of n x n vertices, n = round(exp U(ln 16, ln max_cloth_side)),
+    or a tet block of about exp U(ln 500, ln max_tet_vertices) vertices, realised as a lattice of
+    a x b x c hexes with aspect ratios in [1, 2] and E ~ U(5e4, 5e5); resting 2 mm above the ground
+    (blocks) or 5 cm above it (cloth), with 1-3 kinematic boxes or capsules (2-10 cm) at random
+    poses above the body moving at |v| <= 5 cm/s for 30 steps, plus the ground.  Per env
+    mu ~ U(0.3, 0.8).  Every obstacle starts clear of the body whatever its rotation: its centre
+    sits 0.9 of its size (a rotated cube reaches sqrt(3)/2 of its side below its centre, a capsule
+    of radius size/4 and half-length size/2 three quarters) plus 5-25 mm above the body's top.
+    """
+    rng = np.random.default_rng(seed)
+    envs, xs, vs, obs = [], [], [], []
+    for _ in range(n_envs):
+        if rng.random() < 0.5:
+            n = int(round(np.exp(rng.uniform(np.log(16), np.log(max_cloth_side)))))
+            side = 0.01 * n
+            rest, tris = cloth_grid(n, side, (-side / 2, -side / 2), 0.0)
+            x0 = rest + np.array([0.0, 0.05, 0.0])
+            env = EnvDesc(TRI, rest, tris, density=1000.0, thickness=1e-3, young=3e4, poisson=0.4,
+                          bending=0.2, mu=float(rng.uniform(0.3, 0.8)))
+            top = 0.05
+        else:
+            nv = float(np.exp(rng.uniform(np.log(500), np.log(max_tet_vertices))))
+            r = rng.uniform(1.0, 2.0, size=3)
+            k = (nv / np.prod(r)) ** (1.0 / 3.0)
+            nx, ny, nz = (max(2, int(round(k * ri)) - 1) for ri in r)
+            h = 0.01
+            rest, tets = hex_lattice(nx, ny, nz, (nx * h, ny * h, nz * h), (-nx * h / 2, 0.0, -nz * h / 2))
+            x0 = rest + np.array([0.0, 0.002, 0.0])
+            env = EnvDesc(TET, rest, tets, density=1000.0, young=float(rng.uniform(5e4, 5e5)),
+                          poisson=float(rng.uniform(0.30, 0.45)), mu=float(rng.uniform(0.3, 0.8)))
+            top = ny * h + 0.002
+        lst = [ground()]
+        for _ in range(int(rng.integers(1, 4))):
+            size = rng.uniform(0.02, 0.10)
+            c = np.array([rng.uniform(-0.1, 0.1), top + 0.9 * size + rng.uniform(0.005, 0.025),
+                          rng.uniform(-0.1, 0.1)])
+            d = rng.normal(size=3)
+            vel = d / np.linalg.norm(d) * rng.uniform(0.0, 0.05)
+            if rng.random() < 0.5:
+                lst.append(box(c, (size / 2,) * 3, vel=vel, move_steps=30, rot=random_rotation(rng)))
+            else:
+                lst.append(capsule(c, size / 4, size / 2, vel=vel, move_steps=30, rot=random_rotation(rng)))
+        envs.append(env); xs.append(x0); vs.append(np.zeros_like(x0)); obs.append(lst)
+    return Scene(envs, xs, vs, obs, Params(lg_iterations=lg_iterations), name="uneven_batch")

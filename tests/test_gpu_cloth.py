@@ -28,6 +28,9 @@ def _say(*a):
 
 
 def _check_step(b, sc, oes, envs, rel, label):
+    """One GPU step and the oracle step of `envs`: same contact list, positions within `rel` of
+    the body's extent, and the oracle's NCP residual of the GPU positions and multipliers
+    <= 1e-6 m."""
     x0, v0 = b.get_state()
     xs, vs = b.split(x0), b.split(v0)
     obs = {e: b.get_obstacles(e) for e in envs}
@@ -185,3 +188,59 @@ def test_stream_groups_match_one_group(groups):
     assert one.residual_history(full=True) == grp.residual_history(full=True)
     info = grp.schedule_info()
     assert info["stream_groups"] == groups
+
+
+def test_uneven_batch_fp64_matches_oracle():
+    """64 envs of the uneven recipe (cloth 16^2-17^2, tet blocks 500-1200 vertices, 1-3 moving
+    boxes or capsules each) in FP64, grouped on 3 streams with one graph per group per step:
+    sampled sheets and tet envs against the oracle at 1e-9, and every env-step of the batch at
+    the NCP tolerance.  (Sheets stay within the 320 contacts per env that the LDS-resident
+    contact solve holds: a sheet lying on the ground touches it with every vertex.)"""
+    F = _F()
+    sc = scenes.uneven_batch(64, seed=5, max_tet_vertices=1200, max_cloth_side=17, lg_iterations=10)
+    b = F.from_scene(sc, precision=F.FLASH_FP64, use_graph=True, stream_groups=3)
+    cloth = [e for e, d in enumerate(sc.envs) if d.elem == 1]
+    tets = [e for e, d in enumerate(sc.envs) if d.elem == 0]
+    sample = cloth[:2] + tets[:2] + [cloth[-1], tets[-1]]
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in sample}
+    b.step(5)
+    _check_step(b, sc, oes, sample, 1e-9, "uneven fp64 step 5")
+    b.step(3)
+    _check_step(b, sc, oes, sample, 1e-9, "uneven fp64 step 9")
+    mx, over = b.residual_history(reset=True)
+    _say(f"uneven fp64 64: worst residual {mx:.2e}, env-steps above tolerance {over}")
+    assert mx <= sc.params.ncp_tol and over == 0
+
+
+def test_uneven_batch_fp32_bench_configuration():
+    """256 envs of the uneven recipe in FP32 in the batched launch configuration (3 stream
+    groups, graphs, autotuned schedule): every env-step ends at the library's FP64 NCP residual
+    <= 1e-6 m, no env exceeds its contact capacity, and sampled sheets and tet envs have the
+    oracle's contact lists and its positions within 1e-5 relative."""
+    F = _F()
+    sc = scenes.uneven_batch(256, seed=6, max_tet_vertices=1200, max_cloth_side=17, lg_iterations=10)
+    b = F.from_scene(sc, use_graph=True, stream_groups=3)
+    cloth = [e for e, d in enumerate(sc.envs) if d.elem == 1]
+    tets = [e for e, d in enumerate(sc.envs) if d.elem == 0]
+    sample = cloth[:2] + tets[:2] + [cloth[-1], tets[-1]]
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in sample}
+    b.step(6)
+    x0, v0 = b.get_state()
+    xs, vs = b.split(x0), b.split(v0)
+    obs = {e: b.get_obstacles(e) for e in sample}
+    b.step(1)
+    x1s = b.split(b.get_state()[0])
+    for e in sample:
+        ref = O.step(oes[e], xs[e], vs[e], obs[e], sc.params, tol=1e-12)
+        L = np.linalg.norm(sc.envs[e].rest_x.max(0) - sc.envs[e].rest_x.min(0))
+        err = np.abs(x1s[e] - ref.x).max()
+        gc = b.contacts(e)
+        _say(f"uneven fp32 env {e} ({'cloth' if e in cloth else 'tets'}): {len(gc['vertex'])} contacts, "
+             f"max|dq| {err:.3e}")
+        assert gc["vertex"].tolist() == ref.contacts.vertex.tolist()
+        assert err <= 1e-5 * max(np.abs(ref.x).max(), L)
+    b.step(3)
+    mx, over = b.residual_history(reset=True)
+    _say(f"uneven fp32 256: worst residual {mx:.2e}, env-steps above tolerance {over}")
+    assert mx <= 1e-6 and over == 0
+    assert not any(s_["flags"] & 4 for s_ in b.stats())
