@@ -83,15 +83,19 @@ def _oracle_env(e, n_steps):
         return time.time() - t0, r.residual
 
 
-def kernel_source_hash(path, name):
-    """sha256 (12 hex digits) of one kernel template's source text (from its template line to the
-    closing brace at column 0), used to tell whether committed counter data still applies."""
+def kernel_source_hash(path, *names):
+    """sha256 (12 hex digits) of the source text of the named templates (each from its template
+    line to the closing brace at column 0), used to tell whether committed counter data still
+    applies to the kernel."""
     import hashlib
     src = open(path).read()
-    i = src.index(f"{name}(")
-    i = src.rfind("template <", 0, i)
-    j = src.index("\n}\n", i)
-    return hashlib.sha256(src[i:j + 3].encode()).hexdigest()[:12]
+    parts = []
+    for name in names:
+        i = src.index(f"{name}(")
+        i = src.rfind("template <", 0, i)
+        j = src.index("\n}\n", i)
+        parts.append(src[i:j + 3])
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:12]
 
 
 def committed_traffic(path, src_hash):
@@ -286,7 +290,7 @@ def main():
         mlp_roof = mlp_roofline(F, torch)
         log(f"network forward: {mlp_roof['achieved']} TFLOP/s")
 
-    gemv_hash = kernel_source_hash(os.path.join(ROOT, "paper_2604_17513_amd", "csrc", "flash_kernels.hip"), "k_gemv")
+    gemv_hash = kernel_source_hash(os.path.join(ROOT, "paper_2604_17513_amd", "csrc", "flash_kernels.hip"), "gemv_tile", "k_gemv")
     traffic, _ = committed_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_squeeze_blocks_1024.md"), gemv_hash)
     if args.envs != 1024:
         traffic = None

@@ -126,7 +126,12 @@ typedef struct {
                                      one group: envs never couple.  With the HIP runtime's default
                                      of 4 hardware queues per process, G = 2 or 3 pays off; at 4
                                      the groups share queues and throughput drops. */
-  int32_t reserved_params;
+  int32_t fused_lg;               /* 0 (default): every phase of the local-global loop is one batched
+                                     launch (K x project, assemble, apply, contact solve, position
+                                     update).  1: the whole loop is one launch with one workgroup per
+                                     env, so that no env waits for the slowest env of the batch
+                                     between phases; bitwise the same results.  Steps that record
+                                     warm-start training pairs use the per-phase launches. */
 } flash_params;
 
 /* One contact of the last step.  impulse = h F lambda in the world frame (N s);

@@ -20,7 +20,7 @@ constexpr int kWsMaxFail = 3;   // learned-start failures after which an env kee
 // Kernel classes for event timing (flash_kernel_name order).
 enum KernelId {
   K_DETECT = 0, K_GATHER, K_PROJECT, K_ASSEMBLE, K_APPLY, K_CSP, K_CORRECT, K_FINALIZE,
-  K_MLP, K_COUNT
+  K_MLP, K_FUSED, K_COUNT
 };
 
 template <class T>

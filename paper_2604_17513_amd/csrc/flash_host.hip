@@ -288,7 +288,7 @@ T* dalloc(size_t count, std::vector<void*>& owned) {
 }
 
 const char* kNames[K_COUNT] = {"detect", "gather", "project", "assemble", "apply", "csp", "correct",
-                               "finalize", "mlp"};
+                               "finalize", "mlp", "lg_fused"};
 
 }  // namespace
 
@@ -393,6 +393,13 @@ struct flash_batch {
       });
     }
     launch(K_GATHER, [&] { launch_gather<T>(B, stream); });
+    if (p.fused_lg && !ws_record) {
+      // the whole local-global loop in one launch, one workgroup per env
+      launch(K_FUSED, [&] { launch_lg_fused<T>(B, mu_d, stream); });
+      launch(K_FINALIZE, [&] { launch_finalize<T>(B, mu_d, stream); });
+      HIPCHK(hipGetLastError());
+      return;
+    }
     for (int k = 0; k < p.lg_iterations; ++k) {
       launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
       launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });

@@ -6,6 +6,7 @@
 // system A q = b + h^2 H^T lambda becomes
 //     A u = M u~ + h^2 sum_e w_e G_e^T (p_e - G_e x_t) + h^2 H^T lambda,
 // u~ = h v + h^2 g, which keeps FP32 relative precision on small quantities.
+#include <algorithm>
 #include <type_traits>
 
 #include "flash_device.h"
@@ -296,10 +297,9 @@ __device__ void project_tri(const DevBatch<T>& B, int t, const int* id) {
   for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
 }
 
+// Local step of one element t (tet or membrane triangle): projection and its slot forces.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
-  const int t = blockIdx.x * kBlock + threadIdx.x;
-  if (t >= B.NT) return;
+__device__ void project_element(const DevBatch<T>& B, int t) {
   const int NT = B.NT, NV = B.NV;
   int id[4];
   for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * NT + t];
@@ -359,6 +359,12 @@ __global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
   for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
 }
 
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_project(DevBatch<T> B) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t < B.NT) project_element(B, t);
+}
+
 // Bending hinges have the target p = 0, so in displacement form each contributes the
 // constant (per step) force w_h G_h^T (0 - G_h x) = -w_h alpha_a (sum_b alpha_b x_b) to its
 // four vertices; written once per step into the hinge slots that the assembly gathers.
@@ -391,16 +397,16 @@ void launch_hinge(const DevBatch<T>& B, hipStream_t s) {
 
 // b = M u~ + h^2 sum over incident tets (fixed incidence order; the forces of
 // vertex i occupy the contiguous slots inc_off[i] .. inc_off[i+1]-1).
+constexpr int kAsmChunk = 1024;   // incidence slots staged per pass (3 values each)
+
+// Right-hand side of the vertices vbeg .. vend-1 (at most kBlock, one per thread):
+// their incidence slots form one contiguous range, staged through LDS (s_f: 3 *
+// kAsmChunk values) in coalesced chunks; each thread then sums its own slots in slot
+// order (the same order, hence the same bits, as a direct per-vertex loop).  Every
+// thread of the workgroup must call it.
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
-  // The workgroup's 256 vertices own one contiguous range of incidence slots: it is
-  // staged through LDS in coalesced chunks, then each thread sums its own slots in
-  // slot order (the same order, hence the same bits, as a direct per-vertex loop).
-  constexpr int CH = 1024;
-  __shared__ T s_f[3 * CH];
-  const int vbeg = blockIdx.x * kBlock;
-  if (vbeg >= B.NV) return;
-  const int vend = min(vbeg + kBlock, B.NV);
+__device__ void assemble_vertices(const DevBatch<T>& B, int vbeg, int vend, T* s_f) {
+  constexpr int CH = kAsmChunk;
   const int i = vbeg + threadIdx.x;
   const int pb = B.inc_off[vbeg], pe = B.inc_off[vend];
   int my0 = 0, my1 = 0;
@@ -409,7 +415,23 @@ __global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
   for (int c0 = pb; c0 < pe; c0 += CH) {
     const int c1 = min(c0 + CH, pe);
     __syncthreads();
-    for (int q = threadIdx.x; q < 3 * (c1 - c0); q += kBlock) s_f[q] = B.fel[3 * (size_t)c0 + q];
+    {
+      // every load of the chunk in flight before the LDS stores
+      constexpr int NQ = 3 * CH / kBlock;
+      const int nq = 3 * (c1 - c0);
+      T tv[NQ];
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const int q = (int)threadIdx.x + u * kBlock;
+        if (q < nq) tv[u] = B.fel[3 * (size_t)c0 + q];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < NQ; ++u) {
+        const int q = (int)threadIdx.x + u * kBlock;
+        if (q < nq) s_f[q] = tv[u];
+      }
+    }
     __syncthreads();
     const int a = max(my0, c0), b = min(my1, c1);
     for (int p = a; p < b; ++p) {
@@ -426,6 +448,14 @@ __global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
   B.b[i] = m * B.ut[i] + hh * s0;
   B.b[NV + i] = m * B.ut[NV + i] + hh * s1;
   B.b[2 * NV + i] = m * B.ut[2 * NV + i] + hh * s2;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_assemble(DevBatch<T> B) {
+  __shared__ T s_f[3 * kAsmChunk];
+  const int vbeg = blockIdx.x * kBlock;
+  if (vbeg >= B.NV) return;
+  assemble_vertices(B, vbeg, min(vbeg + kBlock, B.NV), s_f);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,14 +478,13 @@ struct alignas(VW * sizeof(T) >= 16 ? 16 : VW * sizeof(T)) GVec {
   T v[VW];
 };
 
+// One column tile (columns tile0 .. tile0 + 64 VW - 1) of env e's product with the
+// workgroup: z = Gbar b (ROWS = false) or u = z + h^2 Gbar[:, contacts] (F lambda)
+// (ROWS = true).  LDS: s_vec 3 * kChunk values, s_row kChunk ints, s_red
+// 3 * 3 * 64 VW values.  Every thread of the workgroup must call it.
 template <class T, bool ROWS, int VW, int UNROLL>
-__global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* items) {
+__device__ void gemv_tile(const DevBatch<T>& B, int e, int tile0, T* s_vec, int* s_row, T* s_red) {
   constexpr int TILE = 64 * VW;
-  __shared__ T s_vec[3][kChunk];
-  __shared__ int s_row[kChunk];
-  __shared__ T s_red[kBlock / 64 - 1][3][TILE];
-  const int2 item = items[blockIdx.x];
-  const int e = item.x, tile0 = item.y;
   const int v0 = B.voff[e];
   const int n = B.voff[e + 1] - v0;
   const int ld = B.gld[e];
@@ -473,26 +502,42 @@ __global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* item
       if (ROWS) {
         const int j = e * B.cap + r0 + r;
         s_row[r] = B.cvert[j];
-        s_vec[0][r] = B.cforce[3 * j];
-        s_vec[1][r] = B.cforce[3 * j + 1];
-        s_vec[2][r] = B.cforce[3 * j + 2];
+        s_vec[r] = B.cforce[3 * j];
+        s_vec[kChunk + r] = B.cforce[3 * j + 1];
+        s_vec[2 * kChunk + r] = B.cforce[3 * j + 2];
       } else {
         s_row[r] = r0 + r;
-        s_vec[0][r] = B.b[v0 + r0 + r];
-        s_vec[1][r] = B.b[B.NV + v0 + r0 + r];
-        s_vec[2][r] = B.b[2 * B.NV + v0 + r0 + r];
+        s_vec[r] = B.b[v0 + r0 + r];
+        s_vec[kChunk + r] = B.b[B.NV + v0 + r0 + r];
+        s_vec[2 * kChunk + r] = B.b[2 * B.NV + v0 + r0 + r];
       }
     }
     __syncthreads();
     if (active) {
-#pragma unroll UNROLL
-      for (int r = wid; r < nr; r += kBlock / 64) {
-        const GVec<T, VW> g = *reinterpret_cast<const GVec<T, VW>*>(G + (size_t)s_row[r] * ld + col0);
-        const T b0 = s_vec[0][r], b1 = s_vec[1][r], b2 = s_vec[2][r];
-        for (int q = 0; q < VW; ++q) {
-          acc[q][0] += g.v[q] * b0;
-          acc[q][1] += g.v[q] * b1;
-          acc[q][2] += g.v[q] * b2;
+      // UNROLL rows per batch: every load of the batch is issued before the first use (the
+      // scheduling barrier keeps the compiler from interleaving them with the products, which
+      // it does under the register pressure of the fused loop); rows are still summed in
+      // increasing order
+      constexpr int WS = kBlock / 64;
+      for (int rb = wid; rb < nr; rb += WS * UNROLL) {
+        GVec<T, VW> g[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int r = rb + WS * u;
+          if (r < nr) g[u] = *reinterpret_cast<const GVec<T, VW>*>(G + (size_t)s_row[r] * ld + col0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+          const int r = rb + WS * u;
+          if (r < nr) {
+            const T b0 = s_vec[r], b1 = s_vec[kChunk + r], b2 = s_vec[2 * kChunk + r];
+            for (int q = 0; q < VW; ++q) {
+              acc[q][0] += g[u].v[q] * b0;
+              acc[q][1] += g[u].v[q] * b1;
+              acc[q][2] += g[u].v[q] * b2;
+            }
+          }
         }
       }
     }
@@ -501,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* item
   __syncthreads();
   if (wid > 0)
     for (int q = 0; q < VW; ++q)
-      for (int k = 0; k < 3; ++k) s_red[wid - 1][k][lane * VW + q] = acc[q][k];
+      for (int k = 0; k < 3; ++k) s_red[((wid - 1) * 3 + k) * TILE + lane * VW + q] = acc[q][k];
   __syncthreads();
   if (wid == 0) {
     const T hh = (T)(B.h * B.h);
@@ -510,13 +555,22 @@ __global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* item
       if (col >= n) continue;
       for (int k = 0; k < 3; ++k) {
         T s = acc[q][k];
-        for (int w = 0; w < kBlock / 64 - 1; ++w) s += s_red[w][k][lane * VW + q];
+        for (int w = 0; w < kBlock / 64 - 1; ++w) s += s_red[(w * 3 + k) * TILE + lane * VW + q];
         const size_t o = (size_t)k * B.NV + v0 + col;
         if (ROWS) B.u[o] = B.z[o] + hh * s;
         else B.z[o] = s;
       }
     }
   }
+}
+
+template <class T, bool ROWS, int VW, int UNROLL>
+__global__ void __launch_bounds__(kBlock) k_gemv(DevBatch<T> B, const int2* items) {
+  __shared__ T s_vec[3 * kChunk];
+  __shared__ int s_row[kChunk];
+  __shared__ T s_red[(kBlock / 64 - 1) * 3 * 64 * VW];
+  const int2 item = items[blockIdx.x];
+  gemv_tile<T, ROWS, VW, UNROLL>(B, item.x, item.y, s_vec, s_row, s_red);
 }
 
 // Gbar restricted to the contacts of each env: Gc[j][k] = Gbar[v_j][v_k]
@@ -643,6 +697,7 @@ template <class T>
 __device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
   const int tid = threadIdx.x;
   constexpr int PS = kBK + 1;   // odd panel row stride: column accesses spread over the LDS banks
+  __shared__ T sh_ui[kBK * kBK];
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
     const int pr_rows = n - k0;
@@ -687,8 +742,31 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, d
       }
     }
     __syncthreads();
-    // write the factored panel back; apply the block's row swaps to the other columns
-    for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
+    // The diagonal block is stored as the inverses of its factors (strictly lower part: the
+    // unit lower inverse, upper part: the upper inverse), so that every triangular solve with
+    // it (U12 below, wg_lu_apply) is a small matrix-vector product instead of a serial
+    // substitution.  Lane cc forms column cc of both inverses by substitution; a zero pivot
+    // gives a zero row (the solve then sets that unknown to zero).
+    if (tid < kb) {
+      const int cc = tid;
+      T* LI = L11;      // unit lower inverse, kept for U12
+      T* UI = sh_ui;
+      for (int i = 0; i < kb; ++i) {
+        T v = (i == cc) ? T(1) : T(0);
+        for (int s2 = 0; s2 < i; ++s2) v -= pan[i * PS + s2] * LI[s2 * kBK + cc];
+        LI[i * kBK + cc] = v;
+      }
+      for (int i = kb - 1; i >= 0; --i) {
+        T v = (i == cc) ? T(1) : T(0);
+        for (int s2 = i + 1; s2 < kb; ++s2) v -= pan[i * PS + s2] * UI[s2 * kBK + cc];
+        const T d = pan[i * PS + i];
+        UI[i * kBK + cc] = d != T(0) ? v / d : T(0);
+      }
+      for (int i = 0; i < kb; ++i)
+        A[(size_t)(k0 + i) * n + k0 + cc] = (cc < i) ? LI[i * kBK + cc] : UI[i * kBK + cc];
+    }
+    // write the rest of the factored panel back; apply the block's row swaps to the other columns
+    for (int idx = kb * kb + tid; idx < pr_rows * kb; idx += kBlock) {
       const int i = idx / kb, t = idx - i * kb;
       A[(size_t)(k0 + i) * n + k0 + t] = pan[i * PS + t];
     }
@@ -703,18 +781,15 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, d
         }
       }
     }
-    for (int idx = tid; idx < kb * kb; idx += kBlock) {
-      const int i = idx / kb, j = idx - i * kb;
-      L11[i * kBK + j] = pan[i * PS + j];
-    }
     __syncthreads();
-    // U12 = L11^-1 A12 (unit lower)
+    // U12 = L11^-1 A12 with the unit lower inverse in L11 (rows taken last to first, so that
+    // col[s < t] still holds the input)
     for (int j = k0 + kb + tid; j < n; j += kBlock) {
       T col[kBK];
       for (int t = 0; t < kb; ++t) col[t] = A[(size_t)(k0 + t) * n + j];
-      for (int t = 0; t < kb; ++t) {
+      for (int t = kb - 1; t > 0; --t) {
         T v = col[t];
-        for (int s2 = 0; s2 < t; ++s2) v -= L11[t * kBK + s2] * col[s2];
+        for (int s2 = 0; s2 < t; ++s2) v += L11[t * kBK + s2] * col[s2];
         col[t] = v;
       }
       for (int t = 0; t < kb; ++t) A[(size_t)(k0 + t) * n + j] = col[t];
@@ -764,9 +839,11 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, d
 
 // Solves A y = r with the factors of wg_lu_factor.  r[16 q + 6] holds the
 // right-hand side; the solution goes to r[16 q + 7].  perm: the row gather of the
-// pivoting; ys: scratch of n values; D: LDS kBK * kBK.
+// pivoting; ys: scratch of n values.  The diagonal blocks hold the inverses of their
+// factors, so each block step is a 16-lane matrix-vector product followed by the update
+// of the remaining rows.
 template <class T>
-__device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys, T* D) {
+__device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
   const int tid = threadIdx.x;
   __syncthreads();
   for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * perm[q] + 6];
@@ -774,17 +851,14 @@ __device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys, T* 
   // forward substitution with the unit lower factor
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
-    for (int idx = tid; idx < kb * kb; idx += kBlock) {
-      const int i = idx / kb, j = idx - i * kb;
-      D[i * kBK + j] = A[(size_t)(k0 + i) * n + k0 + j];
+    T v = 0;
+    if (tid < kb) {
+      const T* Ar = A + (size_t)(k0 + tid) * n + k0;
+      v = ys[k0 + tid];
+      for (int s2 = 0; s2 < tid; ++s2) v += Ar[s2] * ys[k0 + s2];
     }
     __syncthreads();
-    if (tid == 0)
-      for (int t = 0; t < kb; ++t) {
-        T y = ys[k0 + t];
-        for (int s2 = 0; s2 < t; ++s2) y -= D[t * kBK + s2] * ys[k0 + s2];
-        ys[k0 + t] = y;
-      }
+    if (tid < kb) ys[k0 + tid] = v;
     __syncthreads();
     for (int i = k0 + kb + tid; i < n; i += kBlock) {
       T acc = 0;
@@ -797,18 +871,13 @@ __device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys, T* 
   const int nblk = (n + kBK - 1) / kBK;
   for (int bk = nblk - 1; bk >= 0; --bk) {
     const int k0 = bk * kBK, kb = min(kBK, n - k0);
-    for (int idx = tid; idx < kb * kb; idx += kBlock) {
-      const int i = idx / kb, j = idx - i * kb;
-      D[i * kBK + j] = A[(size_t)(k0 + i) * n + k0 + j];
+    T v = 0;
+    if (tid < kb) {
+      const T* Ar = A + (size_t)(k0 + tid) * n + k0;
+      for (int s2 = tid; s2 < kb; ++s2) v += Ar[s2] * ys[k0 + s2];
     }
     __syncthreads();
-    if (tid == 0)
-      for (int t = kb - 1; t >= 0; --t) {
-        T y = ys[k0 + t];
-        for (int s2 = t + 1; s2 < kb; ++s2) y -= D[t * kBK + s2] * ys[k0 + s2];
-        const T d = D[t * kBK + t];
-        ys[k0 + t] = d != T(0) ? y / d : T(0);
-      }
+    if (tid < kb) ys[k0 + tid] = v;
     __syncthreads();
     for (int i = tid; i < k0; i += kBlock) {
       T acc = 0;
@@ -864,12 +933,12 @@ __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y
   }
 }
 
+// The contact subproblem of env e by the whole workgroup; smem_raw: csp_smem_bytes<CT>
+// of LDS.  own_cost: add the solve's wall-clock time to the env's scheduling cost.
 template <class T, class CT>
-__global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  // workgroups take envs in the order of the last step's solve times, longest first
-  const int e = B.order ? B.order[blockIdx.x] : blockIdx.x;
-  const unsigned long long t_start = (B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
+__device__ void csp_env(const DevBatch<T>& B, const T* mu_env, int first_lg, int e, unsigned char* smem_raw,
+                        bool own_cost) {
+  const unsigned long long t_start = (own_cost && B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
   const int c = B.ccount[e];
   if (c == 0) {
     if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~1;
@@ -1286,8 +1355,8 @@ restart:
           for (int b = 0; b < 3; ++b) rr += rv[8 + b] * rin[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
           rv[6] = rr;
         }
-        if (big) wg_lu_apply(Cm, nR, perm, Rv, gys, sh_blk);
-        else wg_lu_apply(Cm, nR, perm, Rv, S.ys, sh_blk);
+        if (big) wg_lu_apply(Cm, nR, perm, Rv, gys);
+        else wg_lu_apply(Cm, nR, perm, Rv, S.ys);
         for (int p = tid; p < nb; p += kBlock) {
           CT w0 = 0, w1 = 0, w2 = 0;
           for (int s = 0; s < nR; ++s) {
@@ -1418,7 +1487,7 @@ restart:
       cnt[7] += 1;
     }
     if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
-    if (B.cost) B.cost[e] += wall_clock64() - t_start;
+    if (own_cost && B.cost) B.cost[e] += wall_clock64() - t_start;
     if (first_lg && B.ws_state) {
       int w = B.ws_state[e] & ~1;
       if (learned && !learned_failed) w |= 1;
@@ -1426,6 +1495,83 @@ restart:
       if ((w & 0xff00) >= (kWsMaxFail << 8)) w |= 2;   // previous-iterate start only from now on
       B.ws_state[e] = w;
     }
+  }
+}
+
+template <class T, class CT>
+__global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  // workgroups take envs in the order of the last step's solve times, longest first
+  const int e = B.order ? B.order[blockIdx.x] : blockIdx.x;
+  csp_env<T, CT>(B, mu_env, first_lg, e, smem_raw, true);
+}
+
+// ---------------------------------------------------------------------------
+// The whole local-global loop of a step (Alg. 1: K x (project, assemble, global
+// apply, contact solve, position update)) with one workgroup per env.  Each phase
+// runs the same device code, on the same data, as its batched kernel, so results
+// are bitwise those of the kernel-per-phase step; what changes is that an env
+// never waits for the slowest env of the batch between phases.  Envs never couple,
+// and every phase of env e reads only what earlier phases of env e wrote (made
+// visible within the workgroup by its barriers).  Workgroups take envs longest
+// first by the previous step's whole-loop times.
+template <class T, int VW>
+constexpr size_t fused_gemv_lds() {
+  return 3 * kChunk * sizeof(T) + kChunk * sizeof(int) + (size_t)(kBlock / 64 - 1) * 3 * 64 * VW * sizeof(T);
+}
+
+template <class T, class CT, int VW, int UNROLL>
+__global__ void __launch_bounds__(kBlock) k_lg_fused(DevBatch<T> B, const T* mu_env) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  constexpr int TILE = 64 * VW;
+  const int e = B.order ? B.order[blockIdx.x] : blockIdx.x;
+  const unsigned long long t_start = (B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
+  const int v0 = B.voff[e], v1 = B.voff[e + 1], t0 = B.toff[e], t1 = B.toff[e + 1];
+  T* s_vec = reinterpret_cast<T*>(smem_raw);
+  int* s_row = reinterpret_cast<int*>(s_vec + 3 * kChunk);
+  T* s_red = reinterpret_cast<T*>(s_row + kChunk);
+  for (int k = 0; k < B.lg_iterations; ++k) {
+    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) project_element(B, t);
+    __syncthreads();
+    for (int vb = v0; vb < v1; vb += kBlock) assemble_vertices(B, vb, min(vb + kBlock, v1), s_vec);
+    __syncthreads();
+    for (int c0 = 0; c0 < v1 - v0; c0 += TILE) gemv_tile<T, false, VW, UNROLL>(B, e, c0, s_vec, s_row, s_red);
+    __syncthreads();
+    csp_env<T, CT>(B, mu_env, k == 0 ? 1 : 0, e, smem_raw, false);
+    __syncthreads();
+    for (int c0 = 0; c0 < v1 - v0; c0 += TILE) gemv_tile<T, true, VW, UNROLL>(B, e, c0, s_vec, s_row, s_red);
+    __syncthreads();
+  }
+  if (B.cost && threadIdx.x == 0) B.cost[e] += wall_clock64() - t_start;
+}
+
+// columns per lane of the fused loop's products (32 bytes per lane) and rows in flight per
+// wave: the loop runs one wave per SIMD (the contact solve's register budget), so each wave
+// keeps more loads in flight than the batched apply does
+template <class T>
+constexpr int fused_vw() { return (int)(32 / sizeof(T)); }
+#ifndef FLASH_FUSED_UNROLL
+#define FLASH_FUSED_UNROLL 8
+#endif
+constexpr int kFusedUnroll = FLASH_FUSED_UNROLL;
+
+template <class T, class CT>
+size_t fused_smem_bytes(const DevBatch<T>& B) {
+  size_t a = csp_smem_bytes<CT>(B.cap, B.rlds);
+  a = std::max(a, fused_gemv_lds<T, fused_vw<T>()>());
+  a = std::max(a, (size_t)3 * kAsmChunk * sizeof(T));
+  return a;
+}
+
+template <class T>
+void launch_lg_fused(const DevBatch<T>& B, const T* mu_env, hipStream_t s) {
+  constexpr int VW = fused_vw<T>();
+  if (B.csp64) {
+    const size_t sm = fused_smem_bytes<T, double>(B);
+    hipLaunchKernelGGL((k_lg_fused<T, double, VW, kFusedUnroll>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env);
+  } else {
+    const size_t sm = fused_smem_bytes<T, T>(B);
+    hipLaunchKernelGGL((k_lg_fused<T, T, VW, kFusedUnroll>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env);
   }
 }
 
@@ -1531,6 +1677,12 @@ void prepare_csp(int cap, int rmax) {
                                        (int)csp_smem_bytes<double>(cap, rmax));
   err = hipFuncSetAttribute((const void*)k_csp<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)csp_smem_bytes<T>(cap, rmax));
+  constexpr int VW = fused_vw<T>();
+  const size_t g = std::max(fused_gemv_lds<T, VW>(), (size_t)3 * kAsmChunk * sizeof(T));
+  err = hipFuncSetAttribute((const void*)k_lg_fused<T, double, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)std::max(csp_smem_bytes<double>(cap, rmax), g));
+  err = hipFuncSetAttribute((const void*)k_lg_fused<T, T, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)std::max(csp_smem_bytes<T>(cap, rmax), g));
   (void)err;
 }
 
@@ -1543,7 +1695,8 @@ void prepare_csp(int cap, int rmax) {
   template void launch_assemble<T>(const DevBatch<T>&, hipStream_t);     \
   template void launch_apply<T>(const DevBatch<T>&, const GemvSchedule&, hipStream_t);   \
   template void launch_correct<T>(const DevBatch<T>&, const GemvSchedule&, hipStream_t); \
-  template void launch_csp<T>(const DevBatch<T>&, const T*, int, hipStream_t);
+  template void launch_csp<T>(const DevBatch<T>&, const T*, int, hipStream_t);      \
+  template void launch_lg_fused<T>(const DevBatch<T>&, const T*, hipStream_t);
 INST(float)
 INST(double)
 

@@ -24,7 +24,10 @@ template <class T> constexpr int gemv_tile(int vw) { return 64 * (int)((8 << vw)
 template <class T> void launch_apply(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
 template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s);
 template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
-// Raises the dynamic LDS limit of the contact-solve kernel for `cap` contacts per env.
+// The whole local-global loop of a step, one workgroup per env (bitwise equal to the
+// kernel-per-phase sequence project, assemble, apply, csp, correct repeated K times).
+template <class T> void launch_lg_fused(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
+// Raises the dynamic LDS limit of the contact-solve kernels for `cap` contacts per env.
 template <class T> void prepare_csp(int cap, int rmax);
 
 }  // namespace flash

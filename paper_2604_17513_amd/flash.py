@@ -62,7 +62,7 @@ class flash_params(C.Structure):
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
                 ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32),
-                ("stream_groups", C.c_int32), ("reserved_params", C.c_int32)]
+                ("stream_groups", C.c_int32), ("fused_lg", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -158,7 +158,7 @@ def _dptr(a: np.ndarray):
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                   fixed_schedule: bool = False, contact_fp32: bool = False,
-                  stream_groups: int = 0) -> flash_params:
+                  stream_groups: int = 0, fused_lg: bool = False) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -176,6 +176,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.fixed_schedule = 1 if fixed_schedule else 0
     s.contact_fp32 = 1 if contact_fp32 else 0
     s.stream_groups = int(stream_groups)
+    s.fused_lg = 1 if fused_lg else 0
     return s
 
 
@@ -199,7 +200,7 @@ class Batch:
     def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
                  stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
-                 contact_fp32: bool = False, stream_groups: int = 0):
+                 contact_fp32: bool = False, stream_groups: int = 0, fused_lg: bool = False):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -219,7 +220,7 @@ class Batch:
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
-                                contact_fp32, stream_groups)
+                                contact_fp32, stream_groups, fused_lg)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -466,10 +467,12 @@ class Mlp:
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
-               fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0) -> Batch:
+               fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0,
+               fused_lg: bool = False) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
-              fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups)
+              fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups,
+              fused_lg=fused_lg)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:
