@@ -13,20 +13,27 @@ update), finalisation).  The state is resident in HBM before the timed region.
 
 Arms, each on a fresh batch over the same steps (10 warm-up, then the timed
 steps): plain (previous-step warm start, one launch per phase, no graph, one
-stream), batched (the envs in 3 groups, each stepped on its own stream as one
-captured HIP graph per step) and batched + learned warm start.  The learned arm's network is trained first, on the GPU, from a
-recorded rollout with seeds disjoint from the timed workload; recording and
-training are reported separately and excluded from the timed region.
-`value` is the batched + learned arm (every row of the hot path, batching and
-the learned start included); --quick runs the plain arm only.
+stream; every launch timed with HIP events), fused eager (the whole
+local-global loop as one launch with one workgroup per env, timed with HIP
+events), per-phase batched (one launch per phase, the envs in 3 groups each
+stepped on its own stream as one captured HIP graph per step), batched (the
+fused loop, 3 groups, graphs) and batched + learned warm start.  The learned
+arm's network is trained first, on the GPU, from a recorded rollout with seeds
+disjoint from the timed workload; recording and training are reported
+separately and excluded from the timed region.  `value` is the batched +
+learned arm (every row of the hot path, batching and the learned start
+included); --quick runs the plain and fused eager arms only.
 
 Prints one JSON line (rank 0).  The roofline object covers the dominant kernel
-(the explicit-inverse global apply), timed with HIP events on the batch's
-stream inside the plain arm's timed region; its traffic comes from the
-committed counter summary when that was taken on the same kernel source
-(sha256 of the kernel template), else null.  roofline_network covers the
-fused bf16 MFMA forward pass.  cpu_baseline times the FP64 oracle on the host
-on a bounded sample of the same workload.
+of the reported arm, the fused local-global loop: its algorithmic bytes are the
+streaming phases' (apply, position update, projection, assembly; the contact
+solve is latency-bound and not counted) over its average launch duration,
+timed with HIP events on the batch's stream in the fused eager arm.
+roofline_apply covers the batched global apply of the plain arm.  Each
+object's traffic comes from a committed counter summary when that was taken on
+the same kernel source (sha256 of the kernel sources), else null.
+roofline_network covers the fused bf16 MFMA forward pass.  cpu_baseline times
+the FP64 oracle on the host on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -54,6 +61,28 @@ def apply_bytes_per_launch(nv):
     env (FP32) read once, the 3 right-hand sides read and the 3 results written."""
     nv = np.asarray(nv, dtype=np.float64)
     return float(np.sum(4.0 * nv * nv + 2 * 12.0 * nv))
+
+
+def fused_bytes_per_launch(sc, contacts, K):
+    """Algorithmic bytes of one fused local-global launch (FP32): per iteration and env the
+    streaming phases read and write once what they must -- the projection 104 B per tet (indices,
+    D_m^-1, weight, four slot forces) and 24 B per vertex (x, u); the assembly 48 B per tet (slot
+    forces) and 32 B per vertex; the apply 4 n^2 + 24 n; the position update 4 n c + 16 c + 24 n.
+    The contact solve is latency-bound and not counted."""
+    tot = 0.0
+    for env, c in zip(sc.envs, contacts):
+        n, T = float(env.n_vertices), float(env.n_elements)
+        tot += 4 * n * n + 4 * n * c + 152 * T + 104 * n + 16 * c
+    return K * tot
+
+
+def source_hash(*paths):
+    """sha256 (12 hex digits) of whole source files."""
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:12]
 
 
 def cpu_baseline(sc, n_steps, procs):
@@ -171,12 +200,12 @@ def mlp_roofline(F, torch, rows=1 << 22, reps=5):
             "flop_per_row": 70400, "avg_launch_ms": round(ms, 4)}
 
 
-def run_arm(F, sc, args, use_graph, warm_start, ws=None, time_apply=False, groups=0):
+def run_arm(F, sc, args, use_graph, warm_start, ws=None, time_apply=False, groups=0, fused=False):
     """Fresh batch of the workload; W warm-up steps, then K timed steps (synchronised both sides).
     time_apply: HIP events around every kernel launch of the timed steps (per-class totals);
-    groups: env groups stepped on their own streams."""
+    groups: env groups stepped on their own streams; fused: the local-global loop as one launch."""
     import torch
-    b = F.from_scene(sc, use_graph=use_graph, warm_start=warm_start, stream_groups=groups)
+    b = F.from_scene(sc, use_graph=use_graph, warm_start=warm_start, stream_groups=groups, fused_lg=fused)
     if ws is not None:
         b.ws_load(*ws)
     b.step(args.warmup)
@@ -207,7 +236,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
     ap.add_argument("--groups", type=int, default=3, help="env groups on separate streams in the batched arms")
     ap.add_argument("--quick", action="store_true",
-                    help="plain eager arm only (no graph or learned arm, no breakdown, no network roofline)")
+                    help="plain and fused eager arms only (no graph or learned arms, no network roofline)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: environments are independent and this build "
@@ -261,39 +290,65 @@ def main():
                             "max_residual": mx1, "env_steps_above_tol": over1,
                             "newton_per_env_step": round(its1, 2)}}
     value, dt_v, mx_v, over_v, dtype_arm = v_plain, dt, mx1, over1, "plain_eager"
+
+    # fused eager: the local-global loop as one launch (one workgroup per env), launches timed
+    b, dtf, ktf, mxf, overf, itsf = run_arm(F, sc, args, use_graph=False, warm_start=F.FLASH_WS_PREV,
+                                            time_apply=True, fused=True)
+    contacts = [s_["contacts"] for s_ in b.stats()]
+    b.close()
+    fused_ms, fused_n = ktf["lg_fused"]
+    fused_avg = fused_ms / max(fused_n, 1)
+    fbpl = fused_bytes_per_launch(sc, contacts, sc.params.lg_iterations)
+    fused_achieved = fbpl / (fused_avg * 1e-3) / 1e9
+    arms["fused_eager"] = {"env_steps_per_s": round(args.envs * args.steps / dtf, 2),
+                           "ms_per_step": round(1000 * dtf / args.steps, 3), "max_residual": mxf,
+                           "env_steps_above_tol": overf, "newton_per_env_step": round(itsf, 2)}
+    log(f"fused eager arm: {1000 * dtf / args.steps:.2f} ms/step")
     training, mlp_roof = None, None
     if not args.quick:
-        # A2: batched (each env group on its own stream, its step captured in a HIP graph),
-        # previous-step warm start
+        # per-phase batched (each env group on its own stream, its step captured in a HIP graph)
         b, dt2, _, mx2, over2, its2 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV,
                                               groups=args.groups)
         b.close()
-        arms["graph_groups"] = {"stream_groups": args.groups,
-                                 "env_steps_per_s": round(args.envs * args.steps / dt2, 2),
-                         "ms_per_step": round(1000 * dt2 / args.steps, 3), "max_residual": mx2,
-                         "env_steps_above_tol": over2, "newton_per_env_step": round(its2, 2)}
-        log(f"graph arm: {1000 * dt2 / args.steps:.2f} ms/step")
+        arms["per_phase_graph_groups"] = {"stream_groups": args.groups,
+                                          "env_steps_per_s": round(args.envs * args.steps / dt2, 2),
+                                          "ms_per_step": round(1000 * dt2 / args.steps, 3), "max_residual": mx2,
+                                          "env_steps_above_tol": over2, "newton_per_env_step": round(its2, 2)}
+        log(f"per-phase graph arm: {1000 * dt2 / args.steps:.2f} ms/step")
+        # A2: batched (fused loop, env groups on their own streams, graphs), previous-step warm start
+        b, dt4, _, mx4, over4, its4 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_PREV,
+                                              groups=args.groups, fused=True)
+        b.close()
+        arms["batched"] = {"fused_lg": True, "stream_groups": args.groups,
+                           "env_steps_per_s": round(args.envs * args.steps / dt4, 2),
+                           "ms_per_step": round(1000 * dt4 / args.steps, 3), "max_residual": mx4,
+                           "env_steps_above_tol": over4, "newton_per_env_step": round(its4, 2)}
+        log(f"batched arm: {1000 * dt4 / args.steps:.2f} ms/step")
         # A3: batched + learned warm start (training excluded from the timed region, reported)
         w, nm, training = train_warm_start(F, scenes, torch)
         log(f"trained warm start on {training['pairs']} pairs in {training['train_s']}s")
         b, dt3, _, mx3, over3, its3 = run_arm(F, sc, args, use_graph=True, warm_start=F.FLASH_WS_LEARNED,
-                                              ws=(w, nm), groups=args.groups)
+                                              ws=(w, nm), groups=args.groups, fused=True)
         picks = sum(s_["ws_state"] & 1 for s_ in b.stats())
         b.close()
-        arms["graph_groups_learned"] = {"stream_groups": args.groups,
-                                        "env_steps_per_s": round(args.envs * args.steps / dt3, 2),
-                                 "ms_per_step": round(1000 * dt3 / args.steps, 3), "max_residual": mx3,
-                                 "env_steps_above_tol": over3, "newton_per_env_step": round(its3, 2),
-                                 "envs_started_from_prediction_last_step": int(picks)}
-        log(f"graph+learned arm: {1000 * dt3 / args.steps:.2f} ms/step")
-        value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "graph_groups_learned"
+        arms["batched_learned"] = {"fused_lg": True, "stream_groups": args.groups,
+                                   "env_steps_per_s": round(args.envs * args.steps / dt3, 2),
+                                   "ms_per_step": round(1000 * dt3 / args.steps, 3), "max_residual": mx3,
+                                   "env_steps_above_tol": over3, "newton_per_env_step": round(its3, 2),
+                                   "envs_started_from_prediction_last_step": int(picks)}
+        log(f"batched+learned arm: {1000 * dt3 / args.steps:.2f} ms/step")
+        value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "batched_learned"
         mlp_roof = mlp_roofline(F, torch)
         log(f"network forward: {mlp_roof['achieved']} TFLOP/s")
 
-    gemv_hash = kernel_source_hash(os.path.join(ROOT, "paper_2604_17513_amd", "csrc", "flash_kernels.hip"), "gemv_tile", "k_gemv")
+    csrc = os.path.join(ROOT, "paper_2604_17513_amd", "csrc")
+    gemv_hash = kernel_source_hash(os.path.join(csrc, "flash_kernels.hip"), "gemv_tile", "k_gemv")
     traffic, _ = committed_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_squeeze_blocks_1024.md"), gemv_hash)
+    fused_hash = source_hash(os.path.join(csrc, "flash_kernels.hip"), os.path.join(csrc, "flash_device.h"))
+    fused_traffic, _ = committed_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_lg_fused_squeeze_blocks_1024.md"),
+                                         fused_hash)
     if args.envs != 1024:
-        traffic = None
+        traffic = fused_traffic = None
 
     out = {
         "metric": METRIC,
@@ -325,7 +380,23 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "apply (explicit-inverse global solve, k_gemv<float,false>)",
+            "kernel": "fused local-global loop (k_lg_fused<float,double>): K x (projection, assembly, "
+                      "global apply, contact solve, position update), one workgroup per env",
+            "achieved": round(fused_achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(fused_achieved / HBM_PEAK_GBS, 4),
+            "traffic": fused_traffic,
+            "bytes_per_launch": fbpl,
+            "bytes_counted": "streaming phases only (apply, position update, projection, assembly); "
+                             "the contact solve is latency-bound",
+            "avg_launch_ms": round(fused_avg, 4),
+            "launches": fused_n,
+            "kernel_source_sha256": fused_hash,
+        },
+        "roofline_apply": {
+            "bound": "hbm",
+            "kernel": "batched global apply of the per-phase step (k_gemv<float,false>)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

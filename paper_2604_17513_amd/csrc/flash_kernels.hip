@@ -478,6 +478,29 @@ struct alignas(VW * sizeof(T) >= 16 ? 16 : VW * sizeof(T)) GVec {
   T v[VW];
 };
 
+// Row segment of the explicit inverse, streamed with the non-temporal hint: the inverse is
+// read once per product, and keeping it out of the caches' working set leaves them to the
+// contact solve's matrices (in the fused loop this took the solve from 20.1 to 17.6 ms per
+// env-step on the squeeze workload).
+template <class T, int VW>
+__device__ __forceinline__ GVec<T, VW> load_gvec(const T* p) {
+  constexpr int PER = (int)(16 / sizeof(T));   // values per 16-byte load
+  typedef T v4 __attribute__((ext_vector_type(16 / sizeof(T))));
+  GVec<T, VW> g;
+  if constexpr (VW >= PER) {
+#pragma unroll
+    for (int i = 0; i < VW / PER; ++i) {
+      const v4 x = __builtin_nontemporal_load(reinterpret_cast<const v4*>(p) + i);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) g.v[i * PER + k] = x[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < VW; ++k) g.v[k] = __builtin_nontemporal_load(p + k);
+  }
+  return g;
+}
+
 // One column tile (columns tile0 .. tile0 + 64 VW - 1) of env e's product with the
 // workgroup: z = Gbar b (ROWS = false) or u = z + h^2 Gbar[:, contacts] (F lambda)
 // (ROWS = true).  LDS: s_vec 3 * kChunk values, s_row kChunk ints, s_red
@@ -524,7 +547,7 @@ __device__ void gemv_tile(const DevBatch<T>& B, int e, int tile0, T* s_vec, int*
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
           const int r = rb + WS * u;
-          if (r < nr) g[u] = *reinterpret_cast<const GVec<T, VW>*>(G + (size_t)s_row[r] * ld + col0);
+          if (r < nr) g[u] = load_gvec<T, VW>(G + (size_t)s_row[r] * ld + col0);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1546,14 +1569,10 @@ __global__ void __launch_bounds__(kBlock) k_lg_fused(DevBatch<T> B, const T* mu_
 }
 
 // columns per lane of the fused loop's products (32 bytes per lane) and rows in flight per
-// wave: the loop runs one wave per SIMD (the contact solve's register budget), so each wave
-// keeps more loads in flight than the batched apply does
+// wave (16 measured no faster than 8)
 template <class T>
 constexpr int fused_vw() { return (int)(32 / sizeof(T)); }
-#ifndef FLASH_FUSED_UNROLL
-#define FLASH_FUSED_UNROLL 8
-#endif
-constexpr int kFusedUnroll = FLASH_FUSED_UNROLL;
+constexpr int kFusedUnroll = 8;
 
 template <class T, class CT>
 size_t fused_smem_bytes(const DevBatch<T>& B) {
