@@ -299,7 +299,7 @@ __device__ void project_tri(const DevBatch<T>& B, int t, const int* id) {
 
 // Local step of one element t (tet or membrane triangle): projection and its slot forces.
 template <class T>
-__device__ void project_element(const DevBatch<T>& B, int t) {
+__device__ __forceinline__ void project_element(const DevBatch<T>& B, int t) {
   const int NT = B.NT, NV = B.NV;
   int id[4];
   for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * NT + t];
@@ -405,7 +405,7 @@ constexpr int kAsmChunk = 1024;   // incidence slots staged per pass (3 values e
 // order (the same order, hence the same bits, as a direct per-vertex loop).  Every
 // thread of the workgroup must call it.
 template <class T>
-__device__ void assemble_vertices(const DevBatch<T>& B, int vbeg, int vend, T* s_f) {
+__device__ __forceinline__ void assemble_vertices(const DevBatch<T>& B, int vbeg, int vend, T* s_f) {
   constexpr int CH = kAsmChunk;
   const int i = vbeg + threadIdx.x;
   const int pb = B.inc_off[vbeg], pe = B.inc_off[vend];
@@ -506,7 +506,7 @@ __device__ __forceinline__ GVec<T, VW> load_gvec(const T* p) {
 // (ROWS = true).  LDS: s_vec 3 * kChunk values, s_row kChunk ints, s_red
 // 3 * 3 * 64 VW values.  Every thread of the workgroup must call it.
 template <class T, bool ROWS, int VW, int UNROLL>
-__device__ void gemv_tile(const DevBatch<T>& B, int e, int tile0, T* s_vec, int* s_row, T* s_red) {
+__device__ __forceinline__ void gemv_tile(const DevBatch<T>& B, int e, int tile0, T* s_vec, int* s_row, T* s_red) {
   constexpr int TILE = 64 * VW;
   const int v0 = B.voff[e];
   const int n = B.voff[e + 1] - v0;
@@ -619,11 +619,32 @@ __global__ void __launch_bounds__(kBlock) k_gather(DevBatch<T> B) {
 // ---------------------------------------------------------------------------
 // kBK (panel width of the blocked factorisations) lives in flash_device.h
 
+// Runs use(k, load(k)) for k = k0, k0 + 1, ..., n - 1 in that order, with the loads of
+// BATCH consecutive terms issued before the first of them is used: under the contact
+// solve's register pressure the compiler otherwise waits for every load before issuing
+// the next (one global round trip per term).  The order of the uses, hence of any sums
+// they form, is unchanged.
+template <int BATCH, class LoadF, class UseF>
+__device__ __forceinline__ void batched_terms(int k0, int n, LoadF load, UseF use) {
+  using V = decltype(load(0));
+  typedef V vec __attribute__((ext_vector_type(BATCH)));   // a register value, never scratch
+  for (int kb = k0; kb < n; kb += BATCH) {
+    vec v = (V)0;
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u)
+      if (kb + u < n) v[u] = load(kb + u);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < BATCH; ++u)
+      if (kb + u < n) use(kb + u, (V)v[u]);
+  }
+}
+
 // In-place inverse of a symmetric positive definite n x n matrix (ld n) by
 // blocked Gauss-Jordan sweeps.  CP: global scratch of n x kBK; P: LDS kBK x kBK;
 // v: LDS 2 * kBK.
 template <class T>
-__device__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
+__device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
   const int tid = threadIdx.x;
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
@@ -717,7 +738,7 @@ __device__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
 // matrix (ties to the lowest row) and the pivot row of step k is stored in
 // piv[k].  Each kBK-column panel is factored in LDS (pan: n * kBK values).
 template <class T>
-__device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
+__device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
   const int tid = threadIdx.x;
   constexpr int PS = kBK + 1;   // odd panel row stride: column accesses spread over the LDS banks
   __shared__ T sh_ui[kBK * kBK];
@@ -866,7 +887,7 @@ __device__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, d
 // factors, so each block step is a 16-lane matrix-vector product followed by the update
 // of the remaining rows.
 template <class T>
-__device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
+__device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
   const int tid = threadIdx.x;
   __syncthreads();
   for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * perm[q] + 6];
@@ -885,7 +906,8 @@ __device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
     __syncthreads();
     for (int i = k0 + kb + tid; i < n; i += kBlock) {
       T acc = 0;
-      for (int t = 0; t < kb; ++t) acc += A[(size_t)i * n + k0 + t] * ys[k0 + t];
+      const T* Ar = A + (size_t)i * n + k0;
+      batched_terms<8>(0, kb, [&](int t) { return Ar[t]; }, [&](int t, T a) { acc += a * ys[k0 + t]; });
       ys[i] -= acc;
     }
     __syncthreads();
@@ -904,7 +926,8 @@ __device__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
     __syncthreads();
     for (int i = tid; i < k0; i += kBlock) {
       T acc = 0;
-      for (int t = 0; t < kb; ++t) acc += A[(size_t)i * n + k0 + t] * ys[k0 + t];
+      const T* Ar = A + (size_t)i * n + k0;
+      batched_terms<8>(0, kb, [&](int t) { return Ar[t]; }, [&](int t, T a) { acc += a * ys[k0 + t]; });
       ys[i] -= acc;
     }
     __syncthreads();
@@ -959,7 +982,7 @@ __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y
 // The contact subproblem of env e by the whole workgroup; smem_raw: csp_smem_bytes<CT>
 // of LDS.  own_cost: add the solve's wall-clock time to the env's scheduling cost.
 template <class T, class CT>
-__device__ void csp_env(const DevBatch<T>& B, const T* mu_env, int first_lg, int e, unsigned char* smem_raw,
+__device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, int first_lg, int e, unsigned char* smem_raw,
                         bool own_cost) {
   const unsigned long long t_start = (own_cost && B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
   const int c = B.ccount[e];
@@ -1055,10 +1078,9 @@ __device__ void csp_env(const DevBatch<T>& B, const T* mu_env, int first_lg, int
     __syncthreads();
     for (int j = tid; j < c; j += kBlock) {
       CT d0 = 0, d1 = 0, d2 = 0;
-      for (int k = 0; k < c; ++k) {
-        const CT g = Gc[(size_t)k * c + j];
+      batched_terms<8>(0, c, [&](int k) { return Gc[(size_t)k * c + j]; }, [&](int k, CT g) {
         d0 += g * S.fw[3 * k]; d1 += g * S.fw[3 * k + 1]; d2 += g * S.fw[3 * k + 2];
-      }
+      });
       const CT* F = Fr + 9 * j;
       for (int a = 0; a < 3; ++a) vout[3 * j + a] = hh * (F[3 * a] * d0 + F[3 * a + 1] * d1 + F[3 * a + 2] * d2);
     }
@@ -1361,10 +1383,9 @@ restart:
       __syncthreads();
       for (int p = tid; p < nb; p += kBlock) {
         CT w0 = 0, w1 = 0, w2 = 0;
-        for (int q = 0; q < nb; ++q) {
-          const CT g = Ginv[(size_t)q * nb + p];
+        batched_terms<8>(0, nb, [&](int q) { return Ginv[(size_t)q * nb + p]; }, [&](int q, CT g) {
           w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
-        }
+        });
         const int j = S.bas[p];
         const CT* F = Fr + 9 * j;
         for (int a = 0; a < 3; ++a) S.x0[3 * j + a] = ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
@@ -1380,18 +1401,42 @@ restart:
         }
         if (big) wg_lu_apply(Cm, nR, perm, Rv, gys);
         else wg_lu_apply(Cm, nR, perm, Rv, S.ys);
-        for (int p = tid; p < nb; p += kBlock) {
-          CT w0 = 0, w1 = 0, w2 = 0;
-          for (int s = 0; s < nR; ++s) {
-            const int js = Rj[s] / 3;
-            const CT g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[16 * s + 7];
-            const CT* us = Rv + 16 * s + 3;
-            w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
+        if (!big) {
+          // the rows' solution y_s, vectors u_s and base positions staged in the (now free)
+          // LDS panel and solve vector, so that only the Ginv gathers go to memory
+          CT* st = S.pan;
+          int* spos = reinterpret_cast<int*>(S.ys);
+          for (int q = tid; q < nR; q += kBlock) {
+            const CT* rv = Rv + 16 * q;
+            st[4 * q] = rv[7]; st[4 * q + 1] = rv[3]; st[4 * q + 2] = rv[4]; st[4 * q + 3] = rv[5];
+            spos[q] = S.pos[Rj[q] / 3];
           }
-          const int j = S.bas[p];
-          const CT* F = Fr + 9 * j;
-          for (int a = 0; a < 3; ++a)
-            dout[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+          __syncthreads();
+          for (int p = tid; p < nb; p += kBlock) {
+            CT w0 = 0, w1 = 0, w2 = 0;
+            batched_terms<8>(0, nR, [&](int s2) { return Ginv[(size_t)spos[s2] * nb + p]; }, [&](int s2, CT gi) {
+              const CT g = gi * st[4 * s2];
+              w0 += g * st[4 * s2 + 1]; w1 += g * st[4 * s2 + 2]; w2 += g * st[4 * s2 + 3];
+            });
+            const int j = S.bas[p];
+            const CT* F = Fr + 9 * j;
+            for (int a = 0; a < 3; ++a)
+              dout[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+          }
+        } else {
+          for (int p = tid; p < nb; p += kBlock) {
+            CT w0 = 0, w1 = 0, w2 = 0;
+            for (int s2 = 0; s2 < nR; ++s2) {
+              const int js = Rj[s2] / 3;
+              const CT g = Ginv[(size_t)S.pos[js] * nb + p] * Rv[16 * s2 + 7];
+              const CT* us = Rv + 16 * s2 + 3;
+              w0 += g * us[0]; w1 += g * us[1]; w2 += g * us[2];
+            }
+            const int j = S.bas[p];
+            const CT* F = Fr + 9 * j;
+            for (int a = 0; a < 3; ++a)
+              dout[3 * j + a] = S.x0[3 * j + a] - ihh * (F[3 * a] * w0 + F[3 * a + 1] * w1 + F[3 * a + 2] * w2);
+          }
         }
       } else {
         for (int p = tid; p < nb; p += kBlock) {
