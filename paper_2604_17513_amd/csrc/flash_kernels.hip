@@ -673,9 +673,15 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
         __builtin_amdgcn_wave_barrier();
       }
     }
-    for (int idx = tid; idx < n * kb; idx += kBlock) {
-      const int i = idx / kb, t = idx - i * kb;
-      CP[(size_t)i * kBK + t] = M[(size_t)i * n + k0 + t];
+    {
+      const int cnt = (n * kb - tid + kBlock - 1) / kBlock;   // this thread's elements
+      batched_terms<8>(0, cnt, [&](int k) {
+        const int idx = tid + k * kBlock, i = idx / kb, t = idx - i * kb;
+        return M[(size_t)i * n + k0 + t];
+      }, [&](int k, T v) {
+        const int idx = tid + k * kBlock, i = idx / kb, t = idx - i * kb;
+        CP[(size_t)i * kBK + t] = v;
+      });
     }
     __syncthreads();
     // row panel: M[k0+t][j] <- sum_s Pinv[t][s] M[k0+s][j] for j outside the block
@@ -697,14 +703,22 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
       T acc[4][4];
       for (int p = 0; p < 4; ++p)
         for (int q = 0; q < 4; ++q) acc[p][q] = 0;
-      for (int t = 0; t < kb; ++t) {
-        T a[4], r[4];
-        for (int q = 0; q < 4; ++q) {
-          a[q] = (i0 + q < n) ? CP[(size_t)(i0 + q) * kBK + t] : T(0);
-          r[q] = (j0 + q < n) ? M[(size_t)(k0 + t) * n + j0 + q] : T(0);
-        }
-        for (int p = 0; p < 4; ++p)
-          for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * r[q];
+      // panel columns and rows in batches of 8, every load of a batch issued before the products
+      for (int t0 = 0; t0 < kb; t0 += 8) {
+        T av[8][4], rv[8][4];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            av[u][q] = (t0 + u < kb && i0 + q < n) ? CP[(size_t)(i0 + q) * kBK + t0 + u] : T(0);
+            rv[u][q] = (t0 + u < kb && j0 + q < n) ? M[(size_t)(k0 + t0 + u) * n + j0 + q] : T(0);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (t0 + u < kb)
+            for (int p = 0; p < 4; ++p)
+              for (int q = 0; q < 4; ++q) acc[p][q] += av[u][p] * rv[u][q];
       }
       for (int p = 0; p < 4; ++p) {
         const int i = i0 + p;
@@ -746,9 +760,15 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
     const int kb = min(kBK, n - k0);
     const int pr_rows = n - k0;
     __syncthreads();
-    for (int idx = tid; idx < pr_rows * kb; idx += kBlock) {
-      const int i = idx / kb, t = idx - i * kb;
-      pan[i * PS + t] = A[(size_t)(k0 + i) * n + k0 + t];
+    {
+      const int cnt = (pr_rows * kb - tid + kBlock - 1) / kBlock;   // this thread's elements
+      batched_terms<8>(0, cnt, [&](int k) {
+        const int idx = tid + k * kBlock, i = idx / kb, t = idx - i * kb;
+        return A[(size_t)(k0 + i) * n + k0 + t];
+      }, [&](int k, T v) {
+        const int idx = tid + k * kBlock, i = idx / kb, t = idx - i * kb;
+        pan[i * PS + t] = v;
+      });
     }
     __syncthreads();
     if (tid < 64) {
@@ -848,14 +868,24 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
         T acc[4][4];
         for (int p = 0; p < 4; ++p)
           for (int q = 0; q < 4; ++q) acc[p][q] = 0;
-        for (int t = 0; t < kb; ++t) {
-          T a[4], b[4];
-          for (int q = 0; q < 4; ++q) {
-            a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * PS + t] : T(0);
-            b[q] = (j0 + q < n) ? A[(size_t)(k0 + t) * n + j0 + q] : T(0);
+        // U12 rows in batches of 8, every load of a batch issued before the products
+        for (int t0 = 0; t0 < kb; t0 += 8) {
+          T bv[8][4];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              bv[u][q] = (t0 + u < kb && j0 + q < n) ? A[(size_t)(k0 + t0 + u) * n + j0 + q] : T(0);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            if (t0 + u < kb) {
+              T a[4];
+              for (int q = 0; q < 4; ++q) a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * PS + t0 + u] : T(0);
+              for (int p = 0; p < 4; ++p)
+                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * bv[u][q];
+            }
           }
-          for (int p = 0; p < 4; ++p)
-            for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
         }
         for (int p = 0; p < 4; ++p) {
           if (i0 + p >= n) continue;
@@ -1250,12 +1280,16 @@ restart:
       }
       nb = sh_nb;
       // Ginv = inverse of Gc[base, base] (+1e-4 relative on repeated vertices), Gauss-Jordan
-      for (int idx = tid; idx < nb * nb; idx += kBlock) {
-        const int p = idx / nb, q = idx - p * nb;
-        const int jp = S.bas[p], jq = S.bas[q];
-        CT g = Gc[(size_t)jp * c + jq];
-        if (p == q && p > 0 && B.cvert[cb + jp] == B.cvert[cb + S.bas[p - 1]]) g *= CT(1.0001);
-        Ginv[idx] = g;
+      {
+        const int cnt = (nb * nb - tid + kBlock - 1) / kBlock;   // this thread's entries
+        batched_terms<8>(0, cnt, [&](int k) {
+          const int idx = tid + k * kBlock, p = idx / nb, q = idx - p * nb;
+          return Gc[(size_t)S.bas[p] * c + S.bas[q]];
+        }, [&](int k, CT g) {
+          const int idx = tid + k * kBlock, p = idx / nb, q = idx - p * nb;
+          if (p == q && p > 0 && B.cvert[cb + S.bas[p]] == B.cvert[cb + S.bas[p - 1]]) g *= CT(1.0001);
+          Ginv[idx] = g;
+        });
       }
       wg_spd_inverse(Ginv, nb, static_cast<CT*>(B.scr) + cb * kBK, sh_blk, sh_vv);
       if (tid == 0) lust[3] += 1;
@@ -1265,16 +1299,25 @@ restart:
 
     mark(2);
     // ---- decoupled contacts (outside the base): local rows E = sp I ----
+    int anydec = 0;
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) {
         const CT isp = CT(1) / S.sp[j];
-        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = -S.ph[3 * j + a] * isp;
+        for (int a = 0; a < 3; ++a) {
+          S.dl[3 * j + a] = -S.ph[3 * j + a] * isp;
+          anydec |= S.dl[3 * j + a] != CT(0) ? 1 : 0;
+        }
       } else {
         for (int a = 0; a < 3; ++a) S.dl[3 * j + a] = 0;
       }
     }
     __syncthreads();
-    apply_W(S.dl, S.Wd);   // W * (decoupled part)
+    if (block_max((double)anydec, sh_red) > 0) {
+      apply_W(S.dl, S.Wd);   // W * (decoupled part)
+    } else {                 // no decoupled update: the product is exactly zero
+      for (int q = tid; q < 3 * c; q += kBlock) S.Wd[q] = 0;
+      __syncthreads();
+    }
     // rhs on base rows: r = -Phi - K (W dl_D)
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) continue;
@@ -1348,18 +1391,47 @@ restart:
             rv[11 + k] = E[a][k];
           }
           RjF[q] = ja;
+          if (!big) {
+            // also staged in the (still free) LDS panel for the build below: vR, uR, K row;
+            // contact, component and base position
+            CT* sv = S.pan + 9 * q;
+            int* si = reinterpret_cast<int*>(S.pan + 9 * nR) + 3 * q;
+            for (int k = 0; k < 6; ++k) sv[k] = rv[k];
+            for (int k = 0; k < 3; ++k) sv[6 + k] = K[a][k];
+            si[0] = j;
+            si[1] = a;
+            si[2] = S.pos[j];
+          }
         }
         __syncthreads();
         // C[q][s] = [same contact] K[a][b] + h^-2 Ginv[pj][pk] (vR_q . uR_s)
-        for (int idx = tid; idx < nR * nR; idx += kBlock) {
-          const int q = idx / nR, s2 = idx - q * nR;
-          const int jaq = Rj[q], jas = Rj[s2];
-          const int jq = jaq / 3, js = jas / 3, as = jas - 3 * js;
-          const CT* vq = Rv + 16 * q;
-          const CT* us = Rv + 16 * s2 + 3;
-          CT v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
-          if (jq == js) v += vq[8 + as];
-          Cm[idx] = v;
+        if (!big) {
+          // each entry reads memory once (its Ginv gather, batched)
+          const CT* sv = S.pan;
+          const int* si = reinterpret_cast<const int*>(S.pan + 9 * nR);
+          const int cnt = (nR * nR - tid + kBlock - 1) / kBlock;   // this thread's entries
+          batched_terms<8>(0, cnt, [&](int k) {
+            const int idx = tid + k * kBlock, q = idx / nR, s2 = idx - q * nR;
+            return Ginv[(size_t)si[3 * q + 2] * nb + si[3 * s2 + 2]];
+          }, [&](int k, CT g) {
+            const int idx = tid + k * kBlock, q = idx / nR, s2 = idx - q * nR;
+            const CT* vq = sv + 9 * q;
+            const CT* us = sv + 9 * s2 + 3;
+            CT v = ihh * g * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
+            if (si[3 * q] == si[3 * s2]) v += vq[6 + si[3 * s2 + 1]];
+            Cm[idx] = v;
+          });
+        } else {
+          for (int idx = tid; idx < nR * nR; idx += kBlock) {
+            const int q = idx / nR, s2 = idx - q * nR;
+            const int jaq = Rj[q], jas = Rj[s2];
+            const int jq = jaq / 3, js = jas / 3, as = jas - 3 * js;
+            const CT* vq = Rv + 16 * q;
+            const CT* us = Rv + 16 * s2 + 3;
+            CT v = ihh * Ginv[(size_t)S.pos[jq] * nb + S.pos[js]] * (vq[0] * us[0] + vq[1] * us[1] + vq[2] * us[2]);
+            if (jq == js) v += vq[8 + as];
+            Cm[idx] = v;
+          }
         }
         __syncthreads();
         mark(4);
@@ -1449,7 +1521,9 @@ restart:
     wsolve(S.rv, S.dl);
     mark(5);
     // one step of iterative refinement against the current Jacobian (exact W products):
-    // res_B = -Phi_B - K (W dl) - E dl_B ; dl_B += Z^-1 res_B
+    // res_B = -Phi_B - K (W dl) - E dl_B ; dl_B += Z^-1 res_B.  It is needed even right after a
+    // factorisation: on stiff sheets the Woodbury direction alone loses too many digits (an FP64
+    // cloth drop missed the oracle by 1e-3 m without it)
     apply_W(S.dl, S.Wd);
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) continue;
