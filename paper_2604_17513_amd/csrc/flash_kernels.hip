@@ -688,10 +688,14 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
     for (int j = tid; j < n; j += kBlock) {
       if (j >= k0 && j < k0 + kb) continue;
       T col[kBK];
-      for (int s2 = 0; s2 < kb; ++s2) col[s2] = M[(size_t)(k0 + s2) * n + j];
+#pragma unroll
+      for (int s2 = 0; s2 < kBK; ++s2) col[s2] = s2 < kb ? M[(size_t)(k0 + s2) * n + j] : T(0);
+      __builtin_amdgcn_sched_barrier(0);
       for (int t = 0; t < kb; ++t) {
         T acc = 0;
-        for (int s2 = 0; s2 < kb; ++s2) acc += P[t * kBK + s2] * col[s2];
+#pragma unroll
+        for (int s2 = 0; s2 < kBK; ++s2)
+          if (s2 < kb) acc += P[t * kBK + s2] * col[s2];
         M[(size_t)(k0 + t) * n + j] = acc;
       }
     }
@@ -731,12 +735,19 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
       }
     }
     // column panel: M[i][k0+t] <- -sum_s M_old[i][k0+s] Pinv[s][t]
-    for (int idx = tid; idx < n * kb; idx += kBlock) {
-      const int i = idx / kb, t = idx - i * kb;
+    for (int i = tid; i < n; i += kBlock) {
       if (i >= k0 && i < k0 + kb) continue;
-      T acc = 0;
-      for (int s2 = 0; s2 < kb; ++s2) acc += CP[(size_t)i * kBK + s2] * P[s2 * kBK + t];
-      M[(size_t)i * n + k0 + t] = -acc;
+      T cp[kBK];
+#pragma unroll
+      for (int s2 = 0; s2 < kBK; ++s2) cp[s2] = s2 < kb ? CP[(size_t)i * kBK + s2] : T(0);
+      __builtin_amdgcn_sched_barrier(0);
+      for (int t = 0; t < kb; ++t) {
+        T acc = 0;
+#pragma unroll
+        for (int s2 = 0; s2 < kBK; ++s2)
+          if (s2 < kb) acc += cp[s2] * P[s2 * kBK + t];
+        M[(size_t)i * n + k0 + t] = -acc;
+      }
     }
     __syncthreads();
     for (int idx = tid; idx < kb * kb; idx += kBlock) {
@@ -1108,7 +1119,7 @@ __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, i
     __syncthreads();
     for (int j = tid; j < c; j += kBlock) {
       CT d0 = 0, d1 = 0, d2 = 0;
-      batched_terms<8>(0, c, [&](int k) { return Gc[(size_t)k * c + j]; }, [&](int k, CT g) {
+      batched_terms<16>(0, c, [&](int k) { return Gc[(size_t)k * c + j]; }, [&](int k, CT g) {
         d0 += g * S.fw[3 * k]; d1 += g * S.fw[3 * k + 1]; d2 += g * S.fw[3 * k + 2];
       });
       const CT* F = Fr + 9 * j;
@@ -1455,7 +1466,7 @@ restart:
       __syncthreads();
       for (int p = tid; p < nb; p += kBlock) {
         CT w0 = 0, w1 = 0, w2 = 0;
-        batched_terms<8>(0, nb, [&](int q) { return Ginv[(size_t)q * nb + p]; }, [&](int q, CT g) {
+        batched_terms<16>(0, nb, [&](int q) { return Ginv[(size_t)q * nb + p]; }, [&](int q, CT g) {
           w0 += g * S.fw[3 * q]; w1 += g * S.fw[3 * q + 1]; w2 += g * S.fw[3 * q + 2];
         });
         const int j = S.bas[p];
@@ -1486,7 +1497,7 @@ restart:
           __syncthreads();
           for (int p = tid; p < nb; p += kBlock) {
             CT w0 = 0, w1 = 0, w2 = 0;
-            batched_terms<8>(0, nR, [&](int s2) { return Ginv[(size_t)spos[s2] * nb + p]; }, [&](int s2, CT gi) {
+            batched_terms<16>(0, nR, [&](int s2) { return Ginv[(size_t)spos[s2] * nb + p]; }, [&](int s2, CT gi) {
               const CT g = gi * st[4 * s2];
               w0 += g * st[4 * s2 + 1]; w1 += g * st[4 * s2 + 2]; w2 += g * st[4 * s2 + 3];
             });
