@@ -761,9 +761,11 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
 // Factors a general n x n matrix A (ld n, overwritten) by a blocked
 // right-looking LU with partial pivoting: rows are swapped across the whole
 // matrix (ties to the lowest row) and the pivot row of step k is stored in
-// piv[k].  Each kBK-column panel is factored in LDS (pan: n * kBK values).
+// piv[k].  Each kBK-column panel is factored in LDS (pan: n * (kBK + 1) values; with lds_cap > 0
+// values available from pan on, the panel's U12 block is kept beside it when it fits).
 template <class T>
-__device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, double* sh_red, int* sh_i, int* sh_piv) {
+__device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T* L11, T* pan, int lds_cap, double* sh_red,
+                                             int* sh_i, int* sh_piv) {
   const int tid = threadIdx.x;
   constexpr int PS = kBK + 1;   // odd panel row stride: column accesses spread over the LDS banks
   __shared__ T sh_ui[kBK * kBK];
@@ -805,13 +807,17 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
         }
         __builtin_amdgcn_wave_barrier();
         const T pv = pan[t * PS + t];
-        const int w = kb - t - 1;
+        // the pivot row right of the diagonal, in registers (fixed-size loops, so that the array is
+        // never indexed dynamically and stays out of scratch)
         T urow[kBK];
-        for (int q = 0; q < w; ++q) urow[q] = pan[t * PS + t + 1 + q];
+#pragma unroll
+        for (int q = 0; q < kBK; ++q) urow[q] = (t + 1 + q < kb) ? pan[t * PS + t + 1 + q] : T(0);
         for (int i = t + 1 + tid; i < pr_rows; i += 64) {
           const T l = pv != T(0) ? pan[i * PS + t] / pv : T(0);
           pan[i * PS + t] = l;
-          for (int q = 0; q < w; ++q) pan[i * PS + t + 1 + q] -= l * urow[q];
+#pragma unroll
+          for (int q = 0; q < kBK; ++q)
+            if (t + 1 + q < kb) pan[i * PS + t + 1 + q] -= l * urow[q];
         }
         __builtin_amdgcn_wave_barrier();
       }
@@ -858,7 +864,11 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
     }
     __syncthreads();
     // U12 = L11^-1 A12 with the unit lower inverse in L11 (rows taken last to first, so that
-    // col[s < t] still holds the input)
+    // col[s < t] still holds the input).  When it fits beside the panel in LDS (lds_cap values
+    // from pan on), U12 is also kept there for the trailing update.
+    const int m0 = k0 + kb, mm = n - m0;
+    T* u12 = pan + pr_rows * PS;
+    const bool u12_lds = lds_cap > 0 && pr_rows * PS + kb * mm <= lds_cap;
     for (int j = k0 + kb + tid; j < n; j += kBlock) {
       T col[kBK];
       for (int t = 0; t < kb; ++t) col[t] = A[(size_t)(k0 + t) * n + j];
@@ -867,41 +877,90 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
         for (int s2 = 0; s2 < t; ++s2) v += L11[t * kBK + s2] * col[s2];
         col[t] = v;
       }
-      for (int t = 0; t < kb; ++t) A[(size_t)(k0 + t) * n + j] = col[t];
+      for (int t = 0; t < kb; ++t) {
+        A[(size_t)(k0 + t) * n + j] = col[t];
+        if (u12_lds) u12[t * mm + (j - m0)] = col[t];
+      }
     }
     __syncthreads();
-    // A22 -= L21 U12 (L21 read from the LDS panel)
-    const int m0 = k0 + kb, mm = n - m0;
+    // A22 -= L21 U12 (L21 read from the LDS panel) in 4 x 4 tiles
     if (mm > 0) {
       const int nt = (mm + 3) / 4;
-      for (int tile = tid; tile < nt * nt; tile += kBlock) {
-        const int i0 = m0 + (tile / nt) * 4, j0 = m0 + (tile - (tile / nt) * nt) * 4;
-        T acc[4][4];
-        for (int p = 0; p < 4; ++p)
-          for (int q = 0; q < 4; ++q) acc[p][q] = 0;
-        // U12 rows in batches of 8, every load of a batch issued before the products
-        for (int t0 = 0; t0 < kb; t0 += 8) {
-          T bv[8][4];
+      if (u12_lds) {
+        // both operands in LDS: the tile's 16 entries of A22 are loaded together before the
+        // products, one round trip per tile
+        auto tile_origin = [&](int tile, int& ti, int& tj) {
+          ti = m0 + (tile / nt) * 4;
+          tj = m0 + (tile - (tile / nt) * nt) * 4;
+        };
+        auto load_tile = [&](int ti, int tj, T (&v)[4][4]) {
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[p][q] = (ti + p < n && tj + q < n) ? A[(size_t)(ti + p) * n + tj + q] : T(0);
+        };
+        auto update_tile = [&](int ti, int tj, const T (&v)[4][4]) {
+          T acc[4][4];
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+          for (int t = 0; t < kb; ++t) {
+            T a[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              a[q] = (ti + q < n) ? pan[(ti + q - k0) * PS + t] : T(0);
+              b[q] = (tj + q < n) ? u12[t * mm + (tj + q - m0)] : T(0);
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-              bv[u][q] = (t0 + u < kb && j0 + q < n) ? A[(size_t)(k0 + t0 + u) * n + j0 + q] : T(0);
+              if (ti + p < n && tj + q < n) A[(size_t)(ti + p) * n + tj + q] = v[p][q] - acc[p][q];
+        };
+        for (int tile = tid; tile < nt * nt; tile += kBlock) {
+          int ti, tj;
+          tile_origin(tile, ti, tj);
+          T v[4][4];
+          load_tile(ti, tj, v);
           __builtin_amdgcn_sched_barrier(0);
+          update_tile(ti, tj, v);
+        }
+      } else {
+        for (int tile = tid; tile < nt * nt; tile += kBlock) {
+          const int ti0 = m0 + (tile / nt) * 4, tj0 = m0 + (tile - (tile / nt) * nt) * 4;
+          T acc[4][4];
+          for (int p = 0; p < 4; ++p)
+            for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+          // U12 rows in batches of 8, every load of a batch issued before the products
+          for (int t0 = 0; t0 < kb; t0 += 8) {
+            T bv[8][4];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            if (t0 + u < kb) {
-              T a[4];
-              for (int q = 0; q < 4; ++q) a[q] = (i0 + q < n) ? pan[(i0 + q - k0) * PS + t0 + u] : T(0);
-              for (int p = 0; p < 4; ++p)
-                for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * bv[u][q];
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                bv[u][q] = (t0 + u < kb && tj0 + q < n) ? A[(size_t)(k0 + t0 + u) * n + tj0 + q] : T(0);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              if (t0 + u < kb) {
+                T a[4];
+                for (int q = 0; q < 4; ++q) a[q] = (ti0 + q < n) ? pan[(ti0 + q - k0) * PS + t0 + u] : T(0);
+                for (int p = 0; p < 4; ++p)
+                  for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * bv[u][q];
+              }
             }
           }
-        }
-        for (int p = 0; p < 4; ++p) {
-          if (i0 + p >= n) continue;
-          for (int q = 0; q < 4; ++q)
-            if (j0 + q < n) A[(size_t)(i0 + p) * n + j0 + q] -= acc[p][q];
+          for (int p = 0; p < 4; ++p) {
+            if (ti0 + p >= n) continue;
+            for (int q = 0; q < 4; ++q)
+              if (tj0 + q < n) A[(size_t)(ti0 + p) * n + tj0 + q] -= acc[p][q];
+          }
         }
       }
     }
@@ -1446,8 +1505,8 @@ restart:
         }
         __syncthreads();
         mark(4);
-        if (big) wg_lu_factor(Cm, nR, piv, perm, sh_blk, gpan, sh_red, sh_i, &sh_piv);
-        else wg_lu_factor(Cm, nR, piv, perm, sh_blk, S.pan, sh_red, sh_i, &sh_piv);
+        if (big) wg_lu_factor(Cm, nR, piv, perm, sh_blk, gpan, 0, sh_red, sh_i, &sh_piv);
+        else wg_lu_factor(Cm, nR, piv, perm, sh_blk, S.pan, B.rlds * (kBK + 2), sh_red, sh_i, &sh_piv);
         if (tid == 0) { lust[0] = 1; lust[1] = nR; lust[2] = lust[3]; ++nfact; sum_nr += nR; max_nr = max(max_nr, nR); }
       } else if (tid == 0) {
         ++nreuse;
