@@ -985,19 +985,33 @@ __device__ __forceinline__ void wg_lu_factor(T* A, int n, int* piv, int* perm, T
 // right-hand side; the solution goes to r[16 q + 7].  perm: the row gather of the
 // pivoting; ys: scratch of n values.  The diagonal blocks hold the inverses of their
 // factors, so each block step is a 16-lane matrix-vector product followed by the update
-// of the remaining rows.
+// of the remaining rows.  dstage (LDS of 16 n values, or nullptr): the diagonal blocks are
+// first staged there in one pass, so that the sequential block steps read them from LDS.
 template <class T>
-__device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys) {
+__device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, T* r, T* ys, T* dstage) {
   const int tid = threadIdx.x;
+  const int nblk = (n + kBK - 1) / kBK;
   __syncthreads();
   for (int q = tid; q < n; q += kBlock) ys[q] = r[16 * perm[q] + 6];
+  if (dstage) {
+    const int cnt = (nblk * kBK * kBK - tid + kBlock - 1) / kBlock;   // this thread's entries
+    batched_terms<8>(0, cnt, [&](int k) {
+      const int idx = tid + k * kBlock, b = idx / (kBK * kBK), ii = (idx / kBK) % kBK, jj = idx % kBK;
+      const int k0 = b * kBK, kb = min(kBK, n - k0);
+      return (ii < kb && jj < kb) ? A[(size_t)(k0 + ii) * n + k0 + jj] : T(0);
+    }, [&](int k, T v) { dstage[tid + k * kBlock] = v; });
+  }
   __syncthreads();
+  // diagonal-block row tid of block b (kb columns), from LDS or memory
+  auto drow = [&](int b, int k0) -> const T* {
+    return dstage ? dstage + (size_t)b * kBK * kBK + tid * kBK : A + (size_t)(k0 + tid) * n + k0;
+  };
   // forward substitution with the unit lower factor
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
     T v = 0;
     if (tid < kb) {
-      const T* Ar = A + (size_t)(k0 + tid) * n + k0;
+      const T* Ar = drow(k0 / kBK, k0);
       v = ys[k0 + tid];
       for (int s2 = 0; s2 < tid; ++s2) v += Ar[s2] * ys[k0 + s2];
     }
@@ -1013,12 +1027,11 @@ __device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, 
     __syncthreads();
   }
   // back substitution with the upper factor
-  const int nblk = (n + kBK - 1) / kBK;
   for (int bk = nblk - 1; bk >= 0; --bk) {
     const int k0 = bk * kBK, kb = min(kBK, n - k0);
     T v = 0;
     if (tid < kb) {
-      const T* Ar = A + (size_t)(k0 + tid) * n + k0;
+      const T* Ar = drow(bk, k0);
       for (int s2 = tid; s2 < kb; ++s2) v += Ar[s2] * ys[k0 + s2];
     }
     __syncthreads();
@@ -1541,8 +1554,13 @@ restart:
           for (int b = 0; b < 3; ++b) rr += rv[8 + b] * rin[3 * j + b] + rv[11 + b] * S.x0[3 * j + b];
           rv[6] = rr;
         }
-        if (big) wg_lu_apply(Cm, nR, perm, Rv, gys);
-        else wg_lu_apply(Cm, nR, perm, Rv, S.ys);
+        if (big) wg_lu_apply(Cm, nR, perm, Rv, gys, static_cast<CT*>(nullptr));
+        else {
+          // the LDS panel (rlds (kBK + 1) values) is free during the solve; it holds the staged
+          // diagonal blocks unless the system is too small for a whole block to fit
+          const bool fits = ((nR + kBK - 1) / kBK) * kBK * kBK <= B.rlds * (kBK + 1);
+          wg_lu_apply(Cm, nR, perm, Rv, S.ys, fits ? S.pan : static_cast<CT*>(nullptr));
+        }
         if (!big) {
           // the rows' solution y_s, vectors u_s and base positions staged in the (now free)
           // LDS panel and solve vector, so that only the Ginv gathers go to memory
