@@ -237,17 +237,48 @@ __device__ void ortho_cols64(const double* F, double* R) {
 // p = the closest matrix with orthonormal columns, F S^-1/2 with S = F^T F in closed form
 // (sqrt S = (S + sqrt(det S) I) / sqrt(tr S + 2 sqrt(det S))); nearly rank-deficient F
 // (det S < 1e-4 (tr S / 2)^2) goes to the FP64 eigen path.  Forces w (p - F_x) gradN_a.
+// Inputs of an element's local step, all loaded before any of its arithmetic, so that a loop
+// over elements can load the next element while it computes the current one.
 template <class T>
-__device__ void project_tri(const DevBatch<T>& B, int t, const int* id) {
+struct ElemIn {
+  int tri;               // 1: membrane triangle (vertices 0..2)
+  int slot[4];           // incidence slots of the element's vertices
+  T dx[3][3], du[3][3];  // x and u of vertices 1.. minus those of vertex 0 (a triangle uses two)
+  T Bm[9];               // D_m^-1 (a triangle uses the first 4 entries)
+  T w;
+};
+
+template <class T>
+__device__ __forceinline__ void elem_ids(const DevBatch<T>& B, int t, int id[4]) {
+  for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * B.NT + t];
+}
+
+template <class T>
+__device__ __forceinline__ void elem_load(const DevBatch<T>& B, int t, const int id[4], ElemIn<T>& in) {
   const int NT = B.NT, NV = B.NV;
-  T dx[2][3], du[2][3];
-  for (int a = 0; a < 2; ++a)
+  in.tri = id[3] < 0 ? 1 : 0;
+  const int ne = in.tri ? 2 : 3, nb = in.tri ? 4 : 9;
+  T X0[3], U0[3];
+  for (int k = 0; k < 3; ++k) { X0[k] = B.x[k * NV + id[0]]; U0[k] = B.u[k * NV + id[0]]; }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      dx[a][k] = B.x[k * NV + id[a + 1]] - B.x[k * NV + id[0]];
-      du[a][k] = B.u[k * NV + id[a + 1]] - B.u[k * NV + id[0]];
+      in.dx[a][k] = a < ne ? B.x[k * NV + id[a + 1]] - X0[k] : T(0);
+      in.du[a][k] = a < ne ? B.u[k * NV + id[a + 1]] - U0[k] : T(0);
     }
-  T Bm[4];
-  for (int k = 0; k < 4; ++k) Bm[k] = B.tet_B[k * NT + t];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) in.Bm[k] = k < nb ? B.tet_B[k * NT + t] : T(0);
+  in.w = B.tet_w[t];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) in.slot[a] = a <= ne ? B.slot[4 * (size_t)t + a] : 0;
+}
+
+template <class T>
+__device__ __forceinline__ void project_tri(const DevBatch<T>& B, int t, const ElemIn<T>& in) {
+  const T(&dx)[3][3] = in.dx;
+  const T(&du)[3][3] = in.du;
+  const T* Bm = in.Bm;
   T F[6], Fx[6];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 2; ++c) {
@@ -281,38 +312,30 @@ __device__ void project_tri(const DevBatch<T>& B, int t, const int* id) {
     for (int k = 0; k < 6; ++k) R[k] = (T)Rd[k];
     atomicAdd(&B.fp64_polar[B.tet_env[t]], 1);
   }
-  const T w = B.tet_w[t];
+  const T w = in.w;
   T P[6];
   for (int k = 0; k < 6; ++k) P[k] = w * (R[k] - Fx[k]);
   T f0[3] = {0, 0, 0};
   for (int a = 0; a < 2; ++a) {
-    T* dst = B.fel + 3 * (size_t)B.slot[4 * (size_t)t + a + 1];
+    T* dst = B.fel + 3 * (size_t)in.slot[a + 1];
     for (int r = 0; r < 3; ++r) {
       const T fa = P[2 * r] * Bm[2 * a] + P[2 * r + 1] * Bm[2 * a + 1];
       dst[r] = fa;
       f0[r] -= fa;
     }
   }
-  T* dst0 = B.fel + 3 * (size_t)B.slot[4 * (size_t)t];
+  T* dst0 = B.fel + 3 * (size_t)in.slot[0];
   for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
 }
 
-// Local step of one element t (tet or membrane triangle): projection and its slot forces.
+// Local step of element t (tet or membrane triangle) from its loaded inputs: projection and
+// its slot forces.
 template <class T>
-__device__ __forceinline__ void project_element(const DevBatch<T>& B, int t) {
-  const int NT = B.NT, NV = B.NV;
-  int id[4];
-  for (int a = 0; a < 4; ++a) id[a] = B.tet_idx[a * NT + t];
-  if (id[3] < 0) { project_tri(B, t, id); return; }
-  T X0[3], U0[3], dx[3][3], du[3][3];
-  for (int k = 0; k < 3; ++k) { X0[k] = B.x[k * NV + id[0]]; U0[k] = B.u[k * NV + id[0]]; }
-  for (int a = 0; a < 3; ++a)
-    for (int k = 0; k < 3; ++k) {
-      dx[a][k] = B.x[k * NV + id[a + 1]] - X0[k];
-      du[a][k] = B.u[k * NV + id[a + 1]] - U0[k];
-    }
-  T Bm[9];
-  for (int k = 0; k < 9; ++k) Bm[k] = B.tet_B[k * NT + t];
+__device__ __forceinline__ void elem_compute(const DevBatch<T>& B, int t, const ElemIn<T>& in) {
+  if (in.tri) { project_tri(B, t, in); return; }
+  const T(&dx)[3][3] = in.dx;
+  const T(&du)[3][3] = in.du;
+  const T* Bm = in.Bm;
   // F = D_s B with D_s[:, a] = dx_a + du_a ; F_x = D_x B
   T F[9], Fx[9];
   for (int r = 0; r < 3; ++r)
@@ -342,21 +365,31 @@ __device__ __forceinline__ void project_element(const DevBatch<T>& B, int t) {
     for (int k = 0; k < 9; ++k) R[k] = (T)Rd[k];
     atomicAdd(&B.fp64_polar[B.tet_env[t]], 1);
   }
-  const T w = B.tet_w[t];
+  const T w = in.w;
   T P[9];
   for (int k = 0; k < 9; ++k) P[k] = w * (R[k] - Fx[k]);
   // vertex forces go to their slots in the vertex-ordered incidence list
   T f0[3] = {0, 0, 0};
   for (int a = 0; a < 3; ++a) {
-    T* dst = B.fel + 3 * (size_t)B.slot[4 * (size_t)t + a + 1];
+    T* dst = B.fel + 3 * (size_t)in.slot[a + 1];
     for (int r = 0; r < 3; ++r) {
       T fa = P[3 * r] * Bm[3 * a] + P[3 * r + 1] * Bm[3 * a + 1] + P[3 * r + 2] * Bm[3 * a + 2];
       dst[r] = fa;
       f0[r] -= fa;
     }
   }
-  T* dst0 = B.fel + 3 * (size_t)B.slot[4 * (size_t)t];
+  T* dst0 = B.fel + 3 * (size_t)in.slot[0];
   for (int r = 0; r < 3; ++r) dst0[r] = f0[r];
+}
+
+// Local step of one element t: its inputs, then its projection and slot forces.
+template <class T>
+__device__ __forceinline__ void project_element(const DevBatch<T>& B, int t) {
+  int id[4];
+  elem_ids(B, t, id);
+  ElemIn<T> in;
+  elem_load(B, t, id, in);
+  elem_compute(B, t, in);
 }
 
 template <class T>
@@ -1006,7 +1039,16 @@ __device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, 
   auto drow = [&](int b, int k0) -> const T* {
     return dstage ? dstage + (size_t)b * kBK * kBK + tid * kBK : A + (size_t)(k0 + tid) * n + k0;
   };
+  // Each thread's first row of the next block step is loaded one step ahead (the loads do not
+  // depend on the solution), so that they complete under the current step's barriers; further
+  // rows of a thread (systems above kBlock + kBK rows) are loaded when used.
+  T pre[kBK];
+  auto prefetch = [&](int row, int k0n, int kbn) {
+#pragma unroll
+    for (int t = 0; t < kBK; ++t) pre[t] = (row < n && t < kbn) ? A[(size_t)row * n + k0n + t] : T(0);
+  };
   // forward substitution with the unit lower factor
+  prefetch(min(kBK, n) + tid, 0, min(kBK, n));
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
     T v = 0;
@@ -1018,7 +1060,19 @@ __device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, 
     __syncthreads();
     if (tid < kb) ys[k0 + tid] = v;
     __syncthreads();
-    for (int i = k0 + kb + tid; i < n; i += kBlock) {
+    {
+      const int i = k0 + kb + tid;
+      if (i < n) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < kBK; ++t)
+          if (t < kb) acc += pre[t] * ys[k0 + t];
+        ys[i] -= acc;
+      }
+      const int k0n = k0 + kBK, kbn = min(kBK, n - k0n);
+      if (k0n < n) prefetch(k0n + kbn + tid, k0n, kbn);
+    }
+    for (int i = k0 + kb + kBlock + tid; i < n; i += kBlock) {
       T acc = 0;
       const T* Ar = A + (size_t)i * n + k0;
       batched_terms<8>(0, kb, [&](int t) { return Ar[t]; }, [&](int t, T a) { acc += a * ys[k0 + t]; });
@@ -1027,6 +1081,7 @@ __device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, 
     __syncthreads();
   }
   // back substitution with the upper factor
+  if (nblk > 1) prefetch(tid < (nblk - 1) * kBK ? tid : n, (nblk - 1) * kBK, min(kBK, n - (nblk - 1) * kBK));
   for (int bk = nblk - 1; bk >= 0; --bk) {
     const int k0 = bk * kBK, kb = min(kBK, n - k0);
     T v = 0;
@@ -1037,7 +1092,18 @@ __device__ __forceinline__ void wg_lu_apply(const T* A, int n, const int* perm, 
     __syncthreads();
     if (tid < kb) ys[k0 + tid] = v;
     __syncthreads();
-    for (int i = tid; i < k0; i += kBlock) {
+    {
+      const int i = tid;
+      if (i < k0) {
+        T acc = 0;
+#pragma unroll
+        for (int t = 0; t < kBK; ++t)
+          if (t < kb) acc += pre[t] * ys[k0 + t];
+        ys[i] -= acc;
+      }
+      if (bk > 0) prefetch(tid < k0 - kBK ? tid : n, k0 - kBK, kBK);
+    }
+    for (int i = kBlock + tid; i < k0; i += kBlock) {
       T acc = 0;
       const T* Ar = A + (size_t)i * n + k0;
       batched_terms<8>(0, kb, [&](int t) { return Ar[t]; }, [&](int t, T a) { acc += a * ys[k0 + t]; });
@@ -1761,7 +1827,18 @@ __global__ void __launch_bounds__(kBlock) k_lg_fused(DevBatch<T> B, const T* mu_
   int* s_row = reinterpret_cast<int*>(s_vec + 3 * kChunk);
   T* s_red = reinterpret_cast<T*>(s_row + kChunk);
   for (int k = 0; k < B.lg_iterations; ++k) {
-    for (int t = t0 + (int)threadIdx.x; t < t1; t += kBlock) project_element(B, t);
+    {
+      // the next element's indices are loaded while the current element computes
+      int t = t0 + (int)threadIdx.x;
+      int idn[4];
+      if (t < t1) elem_ids(B, t, idn);
+      for (; t < t1; t += kBlock) {
+        ElemIn<T> cur;
+        elem_load(B, t, idn, cur);
+        if (t + kBlock < t1) elem_ids(B, t + kBlock, idn);
+        elem_compute(B, t, cur);
+      }
+    }
     __syncthreads();
     for (int vb = v0; vb < v1; vb += kBlock) assemble_vertices(B, vb, min(vb + kBlock, v1), s_vec);
     __syncthreads();
