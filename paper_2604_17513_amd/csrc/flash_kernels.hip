@@ -675,10 +675,15 @@ __device__ __forceinline__ void batched_terms(int k0, int n, LoadF load, UseF us
 
 // In-place inverse of a symmetric positive definite n x n matrix (ld n) by
 // blocked Gauss-Jordan sweeps.  CP: global scratch of n x kBK; P: LDS kBK x kBK;
-// v: LDS 2 * kBK.
+// v: LDS 2 * kBK.  lds (lds_cap values, or nullptr): when 2 kBK n values fit, the
+// panel column copy and the new row panel live there, so that the trailing update reads
+// memory only for the entries it updates.
 template <class T>
-__device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
+__device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v, T* lds, int lds_cap) {
   const int tid = threadIdx.x;
+  const bool in_lds = lds && 2 * kBK * n <= lds_cap;
+  T* rp = in_lds ? lds + (size_t)kBK * n : nullptr;   // new row panel, rp[t * n + j]
+  if (in_lds) CP = lds;
   for (int k0 = 0; k0 < n; k0 += kBK) {
     const int kb = min(kBK, n - k0);
     __syncthreads();
@@ -730,11 +735,54 @@ __device__ __forceinline__ void wg_spd_inverse(T* M, int n, T* CP, T* P, T* v) {
         for (int s2 = 0; s2 < kBK; ++s2)
           if (s2 < kb) acc += P[t * kBK + s2] * col[s2];
         M[(size_t)(k0 + t) * n + j] = acc;
+        if (in_lds) rp[t * n + j] = acc;
       }
     }
+    if (in_lds)   // the block's own columns of the row panel enter only discarded products
+      for (int idx = tid; idx < kb * kb; idx += kBlock) rp[(idx / kb) * n + k0 + idx % kb] = T(0);
     __syncthreads();
     // trailing update M[i][j] -= sum_t M_old[i][k0+t] * M_new[k0+t][j]
     const int nt = (n + 3) / 4;
+    if (in_lds) {
+      for (int tile = tid; tile < nt * nt; tile += kBlock) {
+        const int i0 = (tile / nt) * 4, j0 = (tile - (tile / nt) * nt) * 4;
+        T mv[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = i0 + p, j = j0 + q;
+            const bool upd = i < n && j < n && !(i >= k0 && i < k0 + kb) && !(j >= k0 && j < k0 + kb);
+            mv[p][q] = upd ? M[(size_t)i * n + j] : T(0);
+          }
+        __builtin_amdgcn_sched_barrier(0);
+        T acc[4][4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[p][q] = 0;
+        for (int t = 0; t < kb; ++t) {
+          T a[4], r[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a[q] = (i0 + q < n) ? CP[(size_t)(i0 + q) * kBK + t] : T(0);
+            r[q] = (j0 + q < n) ? rp[t * n + j0 + q] : T(0);
+          }
+#pragma unroll
+          for (int p = 0; p < 4; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * r[q];
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = i0 + p, j = j0 + q;
+            if (i < n && j < n && !(i >= k0 && i < k0 + kb) && !(j >= k0 && j < k0 + kb))
+              M[(size_t)i * n + j] = mv[p][q] - acc[p][q];
+          }
+      }
+    } else
     for (int tile = tid; tile < nt * nt; tile += kBlock) {
       const int i0 = (tile / nt) * 4, j0 = (tile - (tile / nt) * nt) * 4;
       T acc[4][4];
@@ -1440,7 +1488,7 @@ restart:
           Ginv[idx] = g;
         });
       }
-      wg_spd_inverse(Ginv, nb, static_cast<CT*>(B.scr) + cb * kBK, sh_blk, sh_vv);
+      wg_spd_inverse(Ginv, nb, static_cast<CT*>(B.scr) + cb * kBK, sh_blk, sh_vv, S.pan, B.rlds * (kBK + 2));
       if (tid == 0) lust[3] += 1;
       __syncthreads();
       ++nref;

@@ -140,3 +140,21 @@ def test_fused_learned_start_and_recording():
     assert rows[0][0] == rows[1][0] > 0
     assert np.array_equal(rows[0][1], rows[1][1]) and np.array_equal(rows[0][2], rows[1][2])
     _same(a, b, "after recording")
+
+
+def test_tiny_contact_capacity_fallbacks():
+    """A contact capacity of 4 (capacitance systems of at most 12 rows, too small for the staged
+    16 x 16 diagonal blocks) takes the memory paths of the capacitance solves: the run stays
+    finite, flags the overflow, and fused equals per-phase bitwise."""
+    F = _F()
+    sc = scenes.drop_cube(seed=45, hexes=3, drop_height=0.0005, jitter=0.0)
+    a = F.from_scene(sc, max_contacts=4)
+    b = F.from_scene(sc, max_contacts=4, fused_lg=True)
+    a.step(4)
+    b.step(4)
+    _same(a, b, "tiny capacity")
+    x = b.get_state()[0]
+    st = b.stats()
+    _say("tiny capacity contacts", [s_["contacts"] for s_ in st], "flags", [s_["flags"] for s_ in st])
+    assert np.all(np.isfinite(x))
+    assert st[0]["contacts"] == 4 and st[0]["flags"] & 4
