@@ -66,3 +66,31 @@ def test_struct_layouts_match_header_field_order():
     assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8
     assert C.sizeof(F.flash_contact) == 16 + 8 * (3 + 3 + 1 + 3 + 3)
     assert C.sizeof(F.flash_env_stats) == 24 + 8
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every field of the ctypes structures sits at the offset the C header gives it (offsetof
+    from a small program compiled against include/flash.h with the host compiler)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [F.flash_env_desc, F.flash_obstacle, F.flash_params, F.flash_contact, F.flash_env_stats]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "flash.h"', "int main(void) {"]
+    expect = []
+    for S in structs:
+        cname = S.__name__
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        expect.append(C.sizeof(S))
+        for fname, _ in S._fields_:
+            cfield = "lambda" if fname == "lambda_" else fname
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {cfield}));')
+            expect.append(getattr(S, fname).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
