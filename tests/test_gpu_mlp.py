@@ -271,6 +271,47 @@ def test_learned_warm_start_step_matches_oracle():
     assert picked >= 1
 
 
+def test_learned_start_gain_on_cold_starts():
+    """What the trained network gains over the method without it, measured where it is used:
+    from identical mid-squeeze states with the multiplier history dropped (every contact starts
+    cold), one step with the learned start and one with the plain previous-step start (which then
+    has no history either).  Both solve every step to the tolerance; the Newton iterations of
+    both are reported, and the learned start may not cost more than a quarter more."""
+    torch = _torch()
+    F = _F()
+    sc_train = scenes.squeeze_blocks(4, seed=25, hexes=6)
+    bt = F.from_scene(sc_train, warm_start=F.FLASH_WS_ZERO)
+    m, n, losses = _train_quick(bt, sc_train, torch, F)
+    sc = scenes.squeeze_blocks(4, seed=26, hexes=6)
+    bl = F.from_scene(sc, warm_start=F.FLASH_WS_LEARNED)
+    bl.ws_load(m.params_bf16(), m.norm())
+    bp = F.from_scene(sc, warm_start=F.FLASH_WS_PREV)
+    its_l = its_p = 0
+    picked = 0
+    for s in range(18):
+        if s % 6 == 5:
+            x0, v0 = bp.get_state()
+            bl.set_obstacles([bp.get_obstacles(e) for e in range(sc.n_envs)])
+            for b in (bl, bp):
+                b.set_state(x0, v0)          # identical states and obstacles, no multiplier history
+                b.residual_history(reset=True)
+                b.step(1)
+            for b, name in ((bl, "learned"), (bp, "plain")):
+                mx, over, newton, steps = b.residual_history(reset=True, full=True)
+                assert mx <= sc.params.ncp_tol and over == 0, name
+                if name == "learned":
+                    its_l += newton
+                else:
+                    its_p += newton
+            picked += sum(st["ws_state"] & 1 for st in bl.stats())
+        else:
+            bp.step(1)
+    _say(f"cold-start steps: Newton iterations learned {its_l}, plain {its_p}; prediction chosen in "
+         f"{picked} of 12 env-steps")
+    assert picked >= 1
+    assert its_l <= 1.25 * its_p
+
+
 def test_learned_warm_start_rejects_non_finite_predictions():
     F = _F()
     sc = scenes.squeeze_blocks(2, seed=23, hexes=4)
