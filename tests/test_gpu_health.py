@@ -7,7 +7,9 @@ host; every kernel still runs to completion).
   steps above the tolerance and is reported as not converged;
 * a get/set state round trip is bitwise, and resuming after it (which drops the multiplier
   history) agrees with the uninterrupted run within the solve tolerance;
-* invalid env indices and too small output capacities are rejected with their status.
+* invalid env indices and too small output capacities are rejected with their status;
+* 128 envs run the squeeze's whole 500-step horizon in the batched configuration with every
+  env-step at the tolerance.
 """
 import ctypes as C
 import sys
@@ -113,3 +115,22 @@ def test_invalid_env_and_capacity_are_rejected():
     st = L.flash_contacts(b._h, 0, out, 1, C.byref(n))
     assert st == F.FLASH_ERR_CAPACITY
     assert n.value == len(b.contacts(0)["vertex"]) > 1
+
+
+def test_full_squeeze_horizon_in_the_batched_configuration():
+    """128 envs of the squeeze workload through its whole 500-step horizon (closing, then
+    holding) with the fused loop, 3 stream groups and graphs: every env-step ends at the NCP
+    tolerance and the state stays finite."""
+    F = _F()
+    sc = scenes.squeeze_blocks(128, seed=35)
+    b = F.from_scene(sc, fused_lg=True, use_graph=True, stream_groups=3)
+    b.residual_history(reset=True)
+    for blk in range(5):
+        b.step(100)
+        mx, over, newton, steps = b.residual_history(reset=False, full=True)
+        _say(f"squeeze horizon step {100 * (blk + 1)}: worst residual {mx:.2e}, above tolerance {over}, "
+             f"Newton per env-step {newton / steps:.2f}")
+    assert steps == 128 * 500
+    assert mx <= sc.params.ncp_tol and over == 0
+    x, v = b.get_state()
+    assert np.all(np.isfinite(x)) and np.all(np.isfinite(v))
