@@ -22,7 +22,10 @@ arm's network is trained first, on the GPU, from a recorded rollout with seeds
 disjoint from the timed workload; recording and training are reported
 separately and excluded from the timed region.  `value` is the batched +
 learned arm (every row of the hot path, batching and the learned start
-included); --quick runs the plain and fused eager arms only.
+included); --quick runs the plain and fused eager arms only.  Beside the
+headline, `arms.uneven_batched` times a second workload in the batched
+configuration: 4096 envs of the uneven mixed recipe (cloth sheets and tet
+blocks of different sizes, moving obstacles).
 
 Prints one JSON line (rank 0).  The roofline object covers the dominant kernel
 of the reported arm, the fused local-global loop: its algorithmic bytes are the
@@ -235,6 +238,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16)
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain 1 GiB device copy")
     ap.add_argument("--groups", type=int, default=3, help="env groups on separate streams in the batched arms")
+    ap.add_argument("--uneven-envs", type=int, default=4096,
+                    help="envs of the uneven mixed batch reported beside the headline (0: skip)")
     ap.add_argument("--quick", action="store_true",
                     help="plain and fused eager arms only (no graph or learned arms, no network roofline)")
     args = ap.parse_args()
@@ -339,6 +344,23 @@ def main():
         log(f"batched+learned arm: {1000 * dt3 / args.steps:.2f} ms/step")
         value, dt_v, mx_v, over_v, dtype_arm = args.envs * args.steps / dt3, dt3, mx3, over3, "batched_learned"
         mlp_roof = mlp_roofline(F, torch)
+        # a second workload, outside the headline: an uneven mixed batch (cloth sheets and tet blocks
+        # of different sizes) in the batched configuration
+        if args.uneven_envs > 0:
+            su = scenes.uneven_batch(args.uneven_envs, seed=7, max_tet_vertices=1200, max_cloth_side=17,
+                                     lg_iterations=10)
+            b, dtu, _, mxu, overu, itsu = run_arm(F, su, args, use_graph=True, warm_start=F.FLASH_WS_PREV,
+                                                  groups=args.groups, fused=True)
+            b.close()
+            arms["uneven_batched"] = {
+                "workload": f"uneven_batch: {args.uneven_envs} envs (seed 7), cloth sheets 16^2-17^2 and tet blocks "
+                            f"of 500-1200 vertices, 1-3 moving boxes or capsules each, K=10, FP32",
+                "vertices": int(sum(e.n_vertices for e in su.envs)),
+                "fused_lg": True, "stream_groups": args.groups,
+                "env_steps_per_s": round(args.uneven_envs * args.steps / dtu, 2),
+                "ms_per_step": round(1000 * dtu / args.steps, 3), "max_residual": mxu,
+                "env_steps_above_tol": overu, "newton_per_env_step": round(itsu, 2)}
+            log(f"uneven batched arm: {1000 * dtu / args.steps:.2f} ms/step")
         log(f"network forward: {mlp_roof['achieved']} TFLOP/s")
 
     csrc = os.path.join(ROOT, "paper_2604_17513_amd", "csrc")
