@@ -303,6 +303,8 @@ def uneven_batch(n_envs: int, seed: int = 0, max_tet_vertices: int = 8000, max_c
     mu ~ U(0.3, 0.8).  Every obstacle starts clear of the body whatever its rotation: its centre
     sits 0.9 of its size (a rotated cube reaches sqrt(3)/2 of its side below its centre, a capsule
     of radius size/4 and half-length size/2 three quarters) plus 5-25 mm above the body's top.
+    Contact solves may take up to 100 Newton iterations (a sheet lying flat on the ground couples
+    all its n^2 contacts; 50 left one of 122,880 env-steps of a 4096-env batch at its cap).
     """
     rng = np.random.default_rng(seed)
     envs, xs, vs, obs = [], [], [], []
@@ -338,4 +340,5 @@ def uneven_batch(n_envs: int, seed: int = 0, max_tet_vertices: int = 8000, max_c
             else:
                 lst.append(capsule(c, size / 4, size / 2, vel=vel, move_steps=30, rot=random_rotation(rng)))
         envs.append(env); xs.append(x0); vs.append(np.zeros_like(x0)); obs.append(lst)
-    return Scene(envs, xs, vs, obs, Params(lg_iterations=lg_iterations), name="uneven_batch")
+    return Scene(envs, xs, vs, obs, Params(lg_iterations=lg_iterations, max_inner_iterations=100),
+                 name="uneven_batch")
