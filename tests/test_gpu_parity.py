@@ -107,6 +107,38 @@ def test_fp32_full_size_block_sampled_envs():
     assert mx <= 1e-6
 
 
+def test_bench_workload_in_the_batched_learned_configuration():
+    """The timed workload at its full size (1024 squeeze envs, seed 0) in the headline launch
+    configuration: fused local-global loop, 3 env groups on their own streams, HIP graphs and
+    the learned warm start (a small fixed network here; the start changes only iteration
+    counts).  After the 10 warm-up steps, the first, a middle and the last env of one step
+    match the oracle's step from the same state, and every env-step of the run ends at the
+    NCP tolerance."""
+    F = _flash()
+    from oracle import mlp_oracle as M
+    rng = np.random.default_rng(46)
+    theta = rng.normal(scale=0.05, size=M.N_PARAMS)
+    w16 = (np.asarray(theta, dtype=np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    norm = np.zeros(35, dtype=np.float32)
+    norm[16:35] = 1.0
+    sc = scenes.squeeze_blocks(1024, seed=0)
+    b = F.from_scene(sc, use_graph=True, stream_groups=3, fused_lg=True, warm_start=F.FLASH_WS_LEARNED)
+    b.ws_load(w16, norm)
+    b.residual_history(reset=True)
+    b.step(10)
+    sample = [0, 511, 1023]
+    oes = {e: O.precompute(sc.envs[e], sc.params.h) for e in sample}
+    for err, tol, same, r, ref in _compare_step(b, sc, oes, sample, 1e-5, "bench workload"):
+        assert same
+        assert err <= tol
+        assert r <= 1e-6
+    mx, over, newton, steps = b.residual_history(reset=True, full=True)
+    _say(f"bench workload: {steps} env-steps, worst residual {mx:.2e}, above tolerance {over}, "
+         f"Newton per env-step {newton / steps:.2f}")
+    assert steps == 1024 * 11
+    assert mx <= sc.params.ncp_tol and over == 0
+
+
 def test_free_flight_no_contacts_closed_form():
     F = _flash()
     sc = scenes.drop_cube(jitter=0.0, drop_height=5.0)
