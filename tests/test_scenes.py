@@ -1,6 +1,11 @@
 """Host-side checks of the seeded scene recipes (no GPU): the uneven mixed batch starts with
 every body clear of every moving obstacle and above the ground, so each contact the batch sees
-comes from motion within the run, never from an overlap built into the initial pose."""
+comes from motion within the run, never from an overlap built into the initial pose; and every
+cloth sheet, in every recipe, carries the cloth material, gravity and force clamp the paper
+prints (fixture under tests/golden/, with its citation)."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -25,3 +30,26 @@ def test_uneven_batch_starts_clear(n_envs, seed):
     assert kinds == {O.BOX, O.CAPSULE}
     elems = {d.elem for d in sc.envs}
     assert elems == {scenes.TET, scenes.TRI}
+
+
+def test_cloth_recipes_use_the_papers_parameters():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "flash_cloth_parameters.json")) as f:
+        g = json.load(f)
+    c = g["cloth"]
+    sheets = [scenes.cloth_drop(n=12, seed=42)]
+    sheets.append(scenes.uneven_batch(32, seed=8, max_tet_vertices=1200, max_cloth_side=17))
+    n_tri = 0
+    for sc in sheets:
+        assert tuple(sc.params.gravity) == tuple(g["gravity"])
+        assert sc.params.max_force == g["maxforce"]
+        for d in sc.envs:
+            if d.elem != scenes.TRI:
+                continue
+            n_tri += 1
+            assert d.young == c["young"] and d.poisson == c["poisson"] and d.bending == c["bending"]
+            assert d.density == c["obj_mass"]
+            assert d.thickness > 0
+    assert n_tri >= 2
+    # defaults that a new scene starts from
+    p = scenes.Params()
+    assert tuple(p.gravity) == tuple(g["gravity"]) and p.max_force == g["maxforce"]
