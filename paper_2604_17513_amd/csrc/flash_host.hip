@@ -510,9 +510,9 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.n_envs = ne;
   B.NV = b->NV;
   B.NT = b->NT;
-  B.cap = b->p.max_contacts_per_env > 0 ? b->p.max_contacts_per_env : 320;
-  B.rmax = std::min(3 * B.cap, 1536);
-  B.rlds = std::min(B.rmax, 480);
+  B.cap = csp_capacity(b->p.max_contacts_per_env);
+  B.rmax = csp_rows(B.cap);
+  B.rlds = csp_lds_rows(B.rmax);
   B.max_newton = b->p.max_inner_iterations > 0 ? b->p.max_inner_iterations : 50;
   B.lg_iterations = b->p.lg_iterations;
   B.h = b->p.h;
@@ -924,6 +924,17 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     return fail(FLASH_ERR_INVALID_ARG, "invalid solver parameters");
   if (p->precision != FLASH_FP32 && p->precision != FLASH_FP64)
     return fail(FLASH_ERR_INVALID_ARG, "precision must be FLASH_FP32 or FLASH_FP64");
+  {
+    // one workgroup holds an env's contact data in LDS: the capacity must fit one CU's LDS
+    const int cap = csp_capacity(p->max_contacts_per_env);
+    const int rlds = csp_lds_rows(csp_rows(cap));
+    const bool ct64 = p->precision == FLASH_FP64 || !p->contact_fp32;
+    const size_t need = ct64 ? csp_smem_bytes<double>(cap, rlds) : csp_smem_bytes<float>(cap, rlds);
+    if (need > kLdsBytes)
+      return fail(FLASH_ERR_INVALID_ARG, "max_contacts_per_env " + std::to_string(cap) + " needs " +
+                                             std::to_string(need) + " bytes of LDS per contact solve; a CU has " +
+                                             std::to_string(kLdsBytes));
+  }
   for (int e = 0; e < n_envs; ++e) {
     const flash_env_desc& d = envs[e];
     if (d.elem != FLASH_TET && d.elem != FLASH_TRI) return fail(FLASH_ERR_INVALID_ARG, "unknown element kind");
@@ -987,7 +998,8 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS of the contact solve above the default limit
-    if (b->fp64) prepare_csp<double>(b->bd.cap, b->bd.rlds); else prepare_csp<float>(b->bf.cap, b->bf.rlds);
+    if (b->fp64) HIPCHK(prepare_csp<double>(b->bd.cap, b->bd.rlds));
+    else HIPCHK(prepare_csp<float>(b->bf.cap, b->bf.rlds));
     *out = b;
     return FLASH_OK;
   } catch (const FlashError& ex) {

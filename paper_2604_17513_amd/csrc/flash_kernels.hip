@@ -1182,12 +1182,6 @@ struct CspSmem {
   int *cls, *pos, *bas;                       // [cap]
 };
 
-template <class T>
-__host__ __device__ size_t csp_smem_bytes(int cap, int rmax) {
-  return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(T) + (size_t)rmax * (kBK + 2) * sizeof(T) +
-         (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
-}
-
 // class bits: 1 normal active, 2 tangential stick, 4 tangential slip (neither: rho = 0)
 template <class T>
 __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y1, T K[3][3], T E[3][3]) {
@@ -2023,22 +2017,25 @@ void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t
 }
 
 template <class T>
-void prepare_csp(int cap, int rmax) {
-  hipError_t err = hipFuncSetAttribute((const void*)k_csp<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)csp_smem_bytes<double>(cap, rmax));
-  err = hipFuncSetAttribute((const void*)k_csp<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)csp_smem_bytes<T>(cap, rmax));
+hipError_t prepare_csp(int cap, int rmax) {
   constexpr int VW = fused_vw<T>();
   const size_t g = std::max(fused_gemv_lds<T, VW>(), (size_t)3 * kAsmChunk * sizeof(T));
-  err = hipFuncSetAttribute((const void*)k_lg_fused<T, double, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)std::max(csp_smem_bytes<double>(cap, rmax), g));
-  err = hipFuncSetAttribute((const void*)k_lg_fused<T, T, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)std::max(csp_smem_bytes<T>(cap, rmax), g));
-  (void)err;
+  hipError_t err[4];
+  err[0] = hipFuncSetAttribute((const void*)k_csp<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)csp_smem_bytes<double>(cap, rmax));
+  err[1] = hipFuncSetAttribute((const void*)k_csp<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)csp_smem_bytes<T>(cap, rmax));
+  err[2] = hipFuncSetAttribute((const void*)k_lg_fused<T, double, VW, kFusedUnroll>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(csp_smem_bytes<double>(cap, rmax), g));
+  err[3] = hipFuncSetAttribute((const void*)k_lg_fused<T, T, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)std::max(csp_smem_bytes<T>(cap, rmax), g));
+  for (hipError_t e : err)
+    if (e != hipSuccess) return e;
+  return hipSuccess;
 }
 
 #define INST(T)                                                          \
-  template void prepare_csp<T>(int, int);                                \
+  template hipError_t prepare_csp<T>(int, int);                          \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
   template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_order<T>(const DevBatch<T>&, hipStream_t);        \

@@ -27,7 +27,23 @@ template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule&
 // The whole local-global loop of a step, one workgroup per env (bitwise equal to the
 // kernel-per-phase sequence project, assemble, apply, csp, correct repeated K times).
 template <class T> void launch_lg_fused(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
-// Raises the dynamic LDS limit of the contact-solve kernels for `cap` contacts per env.
-template <class T> void prepare_csp(int cap, int rmax);
+// Contact capacity per env (0 asks for the default), rows of the largest capacitance system
+// one contact solve factors, and the rows of its LU panel staged in LDS.
+inline int csp_capacity(int requested) { return requested > 0 ? requested : 320; }
+inline int csp_rows(int cap) { return 3 * cap < 1536 ? 3 * cap : 1536; }
+inline int csp_lds_rows(int rmax) { return rmax < 480 ? rmax : 480; }
+// Dynamic LDS of one contact solve in its precision CT: FP64 multipliers (3 per contact), the
+// per-contact frames, Jacobian and E blocks (28 values), the staged LU panel (rlds rows of
+// kBK + 2), contact indices (3 per contact) and a 64-value reduction area.
+template <class CT>
+__host__ __device__ constexpr size_t csp_smem_bytes(int cap, int rlds) {
+  return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(CT) + (size_t)rlds * (kBK + 2) * sizeof(CT) +
+         (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
+}
+// LDS of one gfx950 CU: the most one workgroup can be given.
+constexpr size_t kLdsBytes = 160 * 1024;
+// Raises the dynamic LDS limit of the contact-solve kernels for `cap` contacts per env; returns
+// the first error of the runtime calls.
+template <class T> hipError_t prepare_csp(int cap, int rmax);
 
 }  // namespace flash

@@ -59,6 +59,43 @@ def test_invalid_arguments_are_rejected_without_device():
     assert L.flash_residual(None, None, None, None) == F.FLASH_ERR_INVALID_ARG
 
 
+def test_contact_capacity_beyond_lds_is_rejected_without_device():
+    """One workgroup holds an env's contact data in the 160 KB of LDS of a CU: 362 contacts fit
+    when the contact solve runs in FP64 (FP64 batches, and FP32 batches by default), 870 when an
+    FP32 batch solves contacts in FP32; one more is rejected at create, before the device is
+    touched."""
+    L = F.lib()
+
+    def lds(cap, ct_bytes):
+        rlds = min(3 * cap, 1536, 480)
+        return cap * 3 * 8 + cap * 28 * ct_bytes + rlds * 18 * ct_bytes + cap * 3 * 4 + 64 * 8
+
+    assert lds(362, 8) <= 160 * 1024 < lds(363, 8)
+    assert lds(870, 4) <= 160 * 1024 < lds(871, 4)
+    d = (F.flash_env_desc * 1)()
+    d[0].elem = 0
+    d[0].n_vertices = 4
+    d[0].n_elements = 1
+    rest = (C.c_double * 12)(0, 0, 0, 1, 0, 0, 0, 0, 1, 0, 1, 0)
+    tet = (C.c_int32 * 4)(0, 1, 2, 3)
+    d[0].rest_x = C.cast(rest, type(d[0].rest_x))
+    d[0].elements = C.cast(tet, type(d[0].elements))
+    d[0].density, d[0].young, d[0].poisson, d[0].mu = 1000.0, 1e5, 0.3, 0.5
+    for precision, contact_fp32, limit in ((F.FLASH_FP64, 0, 362), (F.FLASH_FP32, 0, 362), (F.FLASH_FP32, 1, 870)):
+        p = F.flash_params()
+        p.h, p.lg_iterations, p.ncp_tol, p.contact_margin = 1.0 / 60, 2, 1e-6, 2e-3
+        p.precision, p.contact_fp32 = precision, contact_fp32
+        p.max_contacts_per_env = limit + 1
+        h = C.c_void_p()
+        assert L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h)) == F.FLASH_ERR_INVALID_ARG
+        assert b"LDS" in L.flash_last_error()
+        p.max_contacts_per_env = limit
+        st = L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h))
+        assert st != F.FLASH_ERR_INVALID_ARG, L.flash_last_error()
+        if st == F.FLASH_OK:
+            L.flash_destroy_batch(h)
+
+
 def test_struct_layouts_match_header_field_order():
     # the ctypes mirrors follow the header's field order; sizes are those of the C structs on LP64
     assert C.sizeof(F.flash_obstacle) == 8 + 8 * (3 + 9 + 3 + 3)
