@@ -521,7 +521,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.tol = b->p.inner_tol > 0 ? b->p.inner_tol : (sizeof(T) == 4 ? 0.25 * b->p.ncp_tol : 1e-12);
   B.max_force = b->p.max_force;
   B.warm_start = b->p.warm_start;
-  B.reuse = getenv("FLASH_CSP_NOREUSE") ? 0 : 1;
+  B.reuse = 1;   // reuse of a capacitance factorisation while the contact classes hold
   const int NV = b->NV, NT = b->NT;
   const size_t cap = (size_t)B.cap;
 
