@@ -108,9 +108,9 @@ typedef struct {
   int32_t use_graph;              /* capture the step in a HIP graph */
   int32_t max_contacts_per_env;   /* contact capacity per env (0: default 320).  One
                                      workgroup holds an env's contact data in the 160 KB of
-                                     LDS of a CU: at most 362 when the contact solve runs in
+                                     LDS of a CU: at most 330 when the contact solve runs in
                                      FP64 (FP64 batches; FP32 batches unless contact_fp32),
-                                     870 with contact_fp32 = 1; larger values return
+                                     814 with contact_fp32 = 1; larger values return
                                      FLASH_ERR_INVALID_ARG from flash_create_batch */
   double inner_tol;               /* stopping tolerance of every contact solve, metres
                                      (0: 0.25 * ncp_tol in FP32, 1e-12 in FP64) */

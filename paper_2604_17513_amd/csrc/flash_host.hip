@@ -929,7 +929,8 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     const int cap = csp_capacity(p->max_contacts_per_env);
     const int rlds = csp_lds_rows(csp_rows(cap));
     const bool ct64 = p->precision == FLASH_FP64 || !p->contact_fp32;
-    const size_t need = ct64 ? csp_smem_bytes<double>(cap, rlds) : csp_smem_bytes<float>(cap, rlds);
+    const size_t need =
+        (ct64 ? csp_smem_bytes<double>(cap, rlds) : csp_smem_bytes<float>(cap, rlds)) + kCspStaticLds;
     if (need > kLdsBytes)
       return fail(FLASH_ERR_INVALID_ARG, "max_contacts_per_env " + std::to_string(cap) + " needs " +
                                              std::to_string(need) + " bytes of LDS per contact solve; a CU has " +
@@ -997,9 +998,9 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
       system_inverse(envs[e], H[e], p->h, nth);
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
-    // dynamic LDS of the contact solve above the default limit
-    if (b->fp64) HIPCHK(prepare_csp<double>(b->bd.cap, b->bd.rlds));
-    else HIPCHK(prepare_csp<float>(b->bf.cap, b->bf.rlds));
+    // dynamic LDS limit of the contact-solve kernels
+    if (b->fp64) HIPCHK(prepare_csp<double>());
+    else HIPCHK(prepare_csp<float>());
     *out = b;
     return FLASH_OK;
   } catch (const FlashError& ex) {

@@ -2017,25 +2017,21 @@ void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t
 }
 
 template <class T>
-hipError_t prepare_csp(int cap, int rmax) {
+hipError_t prepare_csp() {
   constexpr int VW = fused_vw<T>();
-  const size_t g = std::max(fused_gemv_lds<T, VW>(), (size_t)3 * kAsmChunk * sizeof(T));
-  hipError_t err[4];
-  err[0] = hipFuncSetAttribute((const void*)k_csp<T, double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)csp_smem_bytes<double>(cap, rmax));
-  err[1] = hipFuncSetAttribute((const void*)k_csp<T, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)csp_smem_bytes<T>(cap, rmax));
-  err[2] = hipFuncSetAttribute((const void*)k_lg_fused<T, double, VW, kFusedUnroll>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)std::max(csp_smem_bytes<double>(cap, rmax), g));
-  err[3] = hipFuncSetAttribute((const void*)k_lg_fused<T, T, VW, kFusedUnroll>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)std::max(csp_smem_bytes<T>(cap, rmax), g));
-  for (hipError_t e : err)
-    if (e != hipSuccess) return e;
+  const void* kernels[4] = {(const void*)k_csp<T, double>, (const void*)k_csp<T, T>,
+                            (const void*)k_lg_fused<T, double, VW, kFusedUnroll>,
+                            (const void*)k_lg_fused<T, T, VW, kFusedUnroll>};
+  for (const void* k : kernels) {
+    const hipError_t err =
+        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - kCspStaticLds));
+    if (err != hipSuccess) return err;
+  }
   return hipSuccess;
 }
 
 #define INST(T)                                                          \
-  template hipError_t prepare_csp<T>(int, int);                          \
+  template hipError_t prepare_csp<T>();                                  \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
   template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_order<T>(const DevBatch<T>&, hipStream_t);        \

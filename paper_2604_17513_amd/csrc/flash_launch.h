@@ -40,10 +40,15 @@ __host__ __device__ constexpr size_t csp_smem_bytes(int cap, int rlds) {
   return (size_t)cap * 3 * sizeof(double) + (size_t)cap * (24 + 4) * sizeof(CT) + (size_t)rlds * (kBK + 2) * sizeof(CT) +
          (size_t)cap * 3 * sizeof(int) + 64 * sizeof(double);
 }
-// LDS of one gfx950 CU: the most one workgroup can be given.
+// LDS of one gfx950 CU: the most one workgroup can be given, static and dynamic together.
 constexpr size_t kLdsBytes = 160 * 1024;
-// Raises the dynamic LDS limit of the contact-solve kernels for `cap` contacts per env; returns
-// the first error of the runtime calls.
-template <class T> hipError_t prepare_csp(int cap, int rmax);
+// Upper bound of the static LDS of the contact-solve kernels (k_csp and the fused loop: 4160
+// bytes with the FP64 contact solve, 2112 with the FP32 one, from their gfx950 descriptors).
+constexpr size_t kCspStaticLds = 8192;
+// Raises the dynamic LDS limit of the contact-solve kernels (both contact-solve precisions, per
+// kernel and process-wide) to what a CU leaves beside the static reserve, the bound that create
+// checks every capacity against, so batches of different capacities never lower it for each
+// other; returns the first error of the runtime calls.
+template <class T> hipError_t prepare_csp();
 
 }  // namespace flash

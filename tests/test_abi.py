@@ -60,18 +60,19 @@ def test_invalid_arguments_are_rejected_without_device():
 
 
 def test_contact_capacity_beyond_lds_is_rejected_without_device():
-    """One workgroup holds an env's contact data in the 160 KB of LDS of a CU: 362 contacts fit
-    when the contact solve runs in FP64 (FP64 batches, and FP32 batches by default), 870 when an
-    FP32 batch solves contacts in FP32; one more is rejected at create, before the device is
+    """One workgroup holds an env's contact data in the 160 KB of LDS of a CU (dynamic, plus up
+    to 8 KB of static LDS reserved for the kernels' own arrays): 330 contacts fit when the
+    contact solve runs in FP64 (FP64 batches, and FP32 batches by default), 814 when an FP32
+    batch solves contacts in FP32; one more is rejected at create, before the device is
     touched."""
     L = F.lib()
 
     def lds(cap, ct_bytes):
         rlds = min(3 * cap, 1536, 480)
-        return cap * 3 * 8 + cap * 28 * ct_bytes + rlds * 18 * ct_bytes + cap * 3 * 4 + 64 * 8
+        return cap * 3 * 8 + cap * 28 * ct_bytes + rlds * 18 * ct_bytes + cap * 3 * 4 + 64 * 8 + 8192
 
-    assert lds(362, 8) <= 160 * 1024 < lds(363, 8)
-    assert lds(870, 4) <= 160 * 1024 < lds(871, 4)
+    assert lds(330, 8) <= 160 * 1024 < lds(331, 8)
+    assert lds(814, 4) <= 160 * 1024 < lds(815, 4)
     d = (F.flash_env_desc * 1)()
     d[0].elem = 0
     d[0].n_vertices = 4
@@ -81,7 +82,7 @@ def test_contact_capacity_beyond_lds_is_rejected_without_device():
     d[0].rest_x = C.cast(rest, type(d[0].rest_x))
     d[0].elements = C.cast(tet, type(d[0].elements))
     d[0].density, d[0].young, d[0].poisson, d[0].mu = 1000.0, 1e5, 0.3, 0.5
-    for precision, contact_fp32, limit in ((F.FLASH_FP64, 0, 362), (F.FLASH_FP32, 0, 362), (F.FLASH_FP32, 1, 870)):
+    for precision, contact_fp32, limit in ((F.FLASH_FP64, 0, 330), (F.FLASH_FP32, 0, 330), (F.FLASH_FP32, 1, 814)):
         p = F.flash_params()
         p.h, p.lg_iterations, p.ncp_tol, p.contact_margin = 1.0 / 60, 2, 1e-6, 2e-3
         p.precision, p.contact_fp32 = precision, contact_fp32

@@ -158,3 +158,63 @@ def test_tiny_contact_capacity_fallbacks():
     _say("tiny capacity contacts", [s_["contacts"] for s_ in st], "flags", [s_["flags"] for s_ in st])
     assert np.all(np.isfinite(x))
     assert st[0]["contacts"] == 4 and st[0]["flags"] & 4
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_largest_contact_capacity_is_bitwise_default(precision):
+    """The largest contact capacity create accepts with the FP64 contact solve (330 contacts per
+    env: the CU's 160 KB of LDS less the static reserve) runs full-size squeeze blocks with the
+    bits of the default capacity (320): the capacity sets strides and overflow limits only, and
+    these envs (about 219 contacts) reach neither.  Fused loop, 3 envs, 8 steps."""
+    F = _F()
+    sc = scenes.squeeze_blocks(3, seed=47)
+    kw = {} if precision == "fp32" else {"precision": F.FLASH_FP64}
+    a = F.from_scene(sc, fused_lg=True, **kw)
+    b = F.from_scene(sc, fused_lg=True, max_contacts=330, **kw)
+    a.step(8)
+    b.step(8)
+    st = b.stats()
+    _say(f"capacity 330 {precision}: contacts {[s_['contacts'] for s_ in st]}")
+    _same(a, b, f"capacity 330 {precision}")
+    assert all(s_["contacts"] > 150 and not (s_["flags"] & 4) for s_ in st)
+
+
+def test_fp32_contact_solve_at_its_largest_capacity():
+    """An FP32 batch that solves its contacts in FP32 (contact_fp32) at the largest capacity
+    create accepts for it (814 contacts per env): the drop cube through touchdown and settling
+    matches the oracle's steps (same contact lists, positions within 1e-5 relative, NCP residual
+    of the GPU positions and multipliers <= 1e-6 m), and the fused loop gives the bits of the
+    per-phase launches."""
+    F = _F()
+    sc = scenes.drop_cube(seed=49)
+    oes = {0: O.precompute(sc.envs[0], sc.params.h)}
+    a = F.from_scene(sc, contact_fp32=True, max_contacts=814)
+    b = F.from_scene(sc, contact_fp32=True, max_contacts=814, fused_lg=True)
+    checked = 0
+    for s in range(24):
+        if s in (11, 12, 13, 16, 23):
+            xg, vg = b.get_state()
+            x0, v0 = b.split(xg)[0], b.split(vg)[0]
+            obs = b.get_obstacles(0)
+            a.step(1)
+            b.step(1)
+            ref = O.step(oes[0], x0, v0, obs, sc.params, tol=1e-12)
+            x1 = b.split(b.get_state()[0])[0]
+            L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+            err = np.abs(x1 - ref.x).max()
+            gc = b.contacts(0)
+            same = (gc["vertex"].tolist() == ref.contacts.vertex.tolist()
+                    and gc["obstacle"].tolist() == ref.contacts.obstacle.tolist())
+            r = O.contact_residual(oes[0], x0, x1, ref.contacts, gc["lambda"], sc.params.h) if same else np.inf
+            _say(f"contact_fp32 step {s}: {len(gc['vertex'])} contacts, max|dq| {err:.3e}, residual {r:.2e}")
+            assert same
+            assert err <= 1e-5 * max(np.abs(ref.x).max(), L)
+            assert r <= 1e-6
+            checked += 1
+        else:
+            a.step(1)
+            b.step(1)
+        _same(a, b, f"contact_fp32 step {s}")
+    assert checked == 5
+    mx, over = b.residual_history(reset=True)
+    assert mx <= sc.params.ncp_tol and over == 0
