@@ -165,12 +165,14 @@ def test_largest_contact_capacity_is_bitwise_default(precision):
     """The largest contact capacity create accepts with the FP64 contact solve (330 contacts per
     env: the CU's 160 KB of LDS less the static reserve) runs full-size squeeze blocks with the
     bits of the default capacity (320): the capacity sets strides and overflow limits only, and
-    these envs (about 219 contacts) reach neither.  Fused loop, 3 envs, 8 steps."""
+    these envs (about 219 contacts) reach neither.  Fused loop, 3 envs, 8 steps.  The larger
+    batch is created first: creating a smaller one afterwards must not lower the LDS limit it
+    launches with."""
     F = _F()
     sc = scenes.squeeze_blocks(3, seed=47)
     kw = {} if precision == "fp32" else {"precision": F.FLASH_FP64}
-    a = F.from_scene(sc, fused_lg=True, **kw)
     b = F.from_scene(sc, fused_lg=True, max_contacts=330, **kw)
+    a = F.from_scene(sc, fused_lg=True, **kw)
     a.step(8)
     b.step(8)
     st = b.stats()
