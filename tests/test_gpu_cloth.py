@@ -194,8 +194,8 @@ def test_uneven_batch_fp64_matches_oracle():
     """64 envs of the uneven recipe (cloth 16^2-17^2, tet blocks 500-1200 vertices, 1-3 moving
     boxes or capsules each) in FP64, grouped on 3 streams with one graph per group per step:
     sampled sheets and tet envs against the oracle at 1e-9, and every env-step of the batch at
-    the NCP tolerance.  (Sheets stay within the 320 contacts per env that the LDS-resident
-    contact solve holds: a sheet lying on the ground touches it with every vertex.)"""
+    the NCP tolerance.  (Sheets stay within the default capacity of 320 contacts per env: a
+    sheet lying on the ground touches it with every vertex.)"""
     F = _F()
     sc = scenes.uneven_batch(64, seed=5, max_tet_vertices=1200, max_cloth_side=17, lg_iterations=10)
     b = F.from_scene(sc, precision=F.FLASH_FP64, use_graph=True, stream_groups=3)
