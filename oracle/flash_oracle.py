@@ -57,8 +57,8 @@ PLANE, BOX, CAPSULE = 0, 1, 2
 
 
 # =============================================================================
-# O0 - precompute (Sec. III-B, Eq. 3 element maps; Eq. 4 system matrix; Alg. 1
-# "assemble block-diagonal operators")
+# O0 - precompute (Sec. III-B, Eq. 3 element maps; Eq. 4 system matrix; Alg. 1,
+# set-up of the per-env operators)
 # =============================================================================
 
 def tet_rest(rest_x: np.ndarray, tets: np.ndarray):
@@ -234,7 +234,7 @@ def precompute(env, h: float) -> OracleEnv:
 
 
 # =============================================================================
-# O1 - contact detection (Alg. 1 "collision detection, parallel across envs")
+# O1 - contact detection (Alg. 1, per-env detection step)
 # =============================================================================
 
 def obstacle_displacement(ob, h: float) -> np.ndarray:
@@ -383,7 +383,7 @@ def detect(x, v, obstacles, params) -> Contacts:
 
 
 # =============================================================================
-# O3 - local projection and assembly (Eq. 3, Eq. 4; Alg. 1 "project")
+# O3 - local projection and assembly (Eq. 3, Eq. 4; Alg. 1, local step)
 # =============================================================================
 
 def closest_rotation(F: np.ndarray) -> np.ndarray:

@@ -2,6 +2,8 @@
 come from the oracle itself: known bfloat16 roundings, hand-built networks with
 closed-form outputs, central finite differences of the loss, the format's
 precision bound for the bf16 procedure, and Adam's first step."""
+import math
+
 import numpy as np
 import pytest
 
@@ -149,3 +151,73 @@ def test_features_and_labels_of_a_resting_contact():
     res = O.step(oe, x, v, sc.obstacles[0], sc.params)
     assert res.info["lam_first"].shape == (res.contacts.count, 3)
     assert np.all(res.info["lam_first"][:, 0] >= 0)
+
+
+def test_every_feature_column_by_hand():
+    """All 16 feature columns of a hand-built scene, each computed from the scene by hand.
+
+    One tet (legs 2 cm, rho = 1000) lifted 0.5 mm above the ground with uniform velocity
+    (0.1, -0.05, 0.2) m/s; vertex 1 also sits 1 mm from the -x face of a box translating at
+    (-0.03, 0.01, 0.02) m/s.  Contacts, in (vertex, obstacle) order: (0, ground), (1, ground),
+    (1, box), (2, ground).  Frames follow the tangent rule t1 = unit(e_k x n), k = argmin |n_i|
+    (lowest on ties), t2 = n x t1: ground n = +y, t1 = +z, t2 = +x; box face n = -x, t1 = +z,
+    t2 = +y.  The local stiffness column uses Abar built by polarising the element energy
+    w |D_s D_m^-1|^2 (w = 2 mu_L V), not the oracle's assembly.
+    """
+    from paper_2604_17513_amd import scenes
+    from oracle import flash_oracle as O
+    h = 1.0 / 60.0
+    dc = 2e-3
+    L = 0.02
+    rest = np.array([[0.0, 0.0, 0.0], [L, 0.0, 0.0], [0.0, 0.0, L], [0.0, L, 0.0]])
+    env = scenes.EnvDesc(scenes.TET, rest, np.array([[0, 1, 2, 3]], np.int32), density=1000.0,
+                         young=1e5, poisson=0.3, mu=0.6)
+    params = scenes.Params(h=h, contact_margin=dc)
+    x = rest + np.array([0.0, 5e-4, 0.0])
+    vel = np.array([0.1, -0.05, 0.2])
+    v = np.tile(vel, (4, 1))
+    vb = np.array([-0.03, 0.01, 0.02])
+    half = np.array([0.01, 0.05, 0.05])
+    c_next = np.array([L + 1e-3 + half[0], 0.01, 0.0])          # pose at the end of the step
+    bx = scenes.box(c_next - h * vb, half, vel=vb)
+    obs = [scenes.ground(), bx]
+    oe = O.precompute(env, h)
+    con = O.detect(x, v, obs, params)
+    assert list(zip(con.vertex, con.obstacle)) == [(0, 0), (1, 0), (1, 1), (2, 0)]
+    lam_prev = np.array([[0.5, 0.1, -0.05], [0.3, 0.0, 0.02], [0.2, 0.01, 0.0], [0.0, 0.0, 0.0]])
+    has = np.array([True, True, False, False])
+    F = M.features(oe, x, v, obs, params, con, lam_prev, has)
+
+    g = -9.81
+    V = L ** 3 / 6.0
+    m = 1000.0 * V / 4.0
+    s = h * h / m
+    # Abar by polarisation of q -> h^2 w |F(q)|^2 with F(q) = D_s(q) D_m^-1 (one coordinate)
+    mu_L = 1e5 / (2.0 * 1.3)
+    w = 2.0 * mu_L * V
+    Dm_inv = np.linalg.inv(np.column_stack([rest[1] - rest[0], rest[2] - rest[0], rest[3] - rest[0]]))
+
+    def energy(q):
+        Ds = np.array([q[1] - q[0], q[2] - q[0], q[3] - q[0]])
+        return float(np.sum((Ds @ Dm_inv) ** 2))
+
+    E = np.eye(4)
+    Abar = np.diag(np.full(4, m))
+    for a in range(4):
+        for b in range(4):
+            Abar[a, b] += h * h * w * 0.5 * (energy(E[a] + E[b]) - energy(E[a]) - energy(E[b]))
+    Ginv = np.linalg.inv(Abar)
+
+    ground_row = lambda vtx, lp, flag, nc: [
+        5e-4 / dc, (h * vel[1] + h * h * g) / dc, h * vel[1] / dc, h * vel[2] / dc, h * vel[0] / dc,
+        s * lp[0] / dc, s * lp[1] / dc, s * lp[2] / dc, flag, 0.6, math.log10(m * Ginv[vtx, vtx]),
+        math.log10(m / 1e-3), nc, g * h * h / dc, 0.0, 1.0]
+    rel = h * vel - h * vb
+    box_row = [1e-3 / dc, -h * vel[0] / dc, -rel[0] / dc, rel[2] / dc, rel[1] / dc,
+               s * lam_prev[2, 0] / dc, s * lam_prev[2, 1] / dc, s * lam_prev[2, 2] / dc, 0.0, 0.6,
+               math.log10(m * Ginv[1, 1]), math.log10(m / 1e-3), 2, 0.0, h * 0.03 / dc, 1.0]
+    expect = np.array([ground_row(0, lam_prev[0], 1.0, 1), ground_row(1, lam_prev[1], 1.0, 2), box_row,
+                       ground_row(2, lam_prev[3], 0.0, 1)])
+    np.testing.assert_allclose(F, expect, rtol=1e-9, atol=1e-12)
+    # the local-stiffness column is informative: Gbar_vv m_v < 1 strictly for a stiff tet
+    assert np.all(F[:, 10] < -0.5)
