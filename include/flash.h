@@ -176,15 +176,45 @@ flash_status flash_create_batch(const flash_env_desc *envs, int32_t n_envs, cons
                                 void *hip_stream, flash_batch **out);
 flash_status flash_destroy_batch(flash_batch *b);
 
-/* Sets / reads positions and velocities.  env = -1: all envs, concatenated in
- * env order; else the one env.  x, v: [n_vertices*3] doubles (v may be NULL
- * on set to keep velocities, NULL on get to skip).  Setting the state of an env
- * invalidates its warm-start cache. */
+/* Sets / reads the state of the implicit step: positions q_h and velocities v_h
+ * at the start of the next step (Sec. III, Eq. 1, where q~ = q_h + h v_h +
+ * h^2 M^-1 f_ext).  env = -1: all envs, concatenated in env order; else the one
+ * env.  x, v: host arrays [n_vertices*3] of doubles, xyz-interleaved (v may be
+ * NULL on set to keep velocities, NULL on get to skip); both calls synchronise
+ * the batch's stream.  Setting the state of an env invalidates its warm-start
+ * cache (previous-step multipliers and the learned-start fallback state).
+ * Errors: FLASH_ERR_INVALID_ARG for a null batch or x (set), or env outside
+ * [-1, n_envs). */
 flash_status flash_set_state(flash_batch *b, int32_t env, const double *x, const double *v);
 flash_status flash_get_state(flash_batch *b, int32_t env, double *x, double *v);
 
-/* Replaces the obstacles of one env (env >= 0, n <= FLASH_MAX_OBSTACLES) or of
- * every env (env = -1: o holds n_envs * n entries, env-major). */
+/* Zero-copy variants of flash_set_state / flash_get_state for device-resident
+ * buffers such as PyTorch tensors (the same q_h, v_h of Eq. 1).  x_dev, v_dev
+ * are device arrays in structure-of-arrays layout [3][n] (component-major: all
+ * x coordinates, then all y, then all z), n = vertices of the env, or of the
+ * whole batch in env order for env = -1; elem_size 4 = float, 8 = double
+ * (converted to and from the batch's precision on the device: an FP64 batch
+ * read into float rounds to nearest).  The calls only enqueue work on the
+ * batch's stream (each group's stream for a batch with stream_groups >= 2) and
+ * return: the caller must have finished writing x_dev / v_dev before that
+ * work runs (for example by creating the batch on the stream that produces
+ * them) and must keep the buffers alive and unmodified until it has finished
+ * (flash_synchronize).  set: x_dev required, v_dev may be NULL to keep
+ * velocities; invalidates the warm-start cache like flash_set_state.  get:
+ * either output may be NULL, not both.  Errors: FLASH_ERR_INVALID_ARG for a
+ * null batch, missing buffers, env outside [-1, n_envs) or another elem_size;
+ * FLASH_ERR_DEVICE if a launch fails. */
+flash_status flash_set_state_device(flash_batch *b, int32_t env, const void *x_dev, const void *v_dev,
+                                    int32_t elem_size);
+flash_status flash_get_state_device(flash_batch *b, int32_t env, void *x_dev, void *v_dev, int32_t elem_size);
+
+/* Replaces the kinematic obstacles that define the contact constraints of one
+ * env (env >= 0, n <= FLASH_MAX_OBSTACLES) or of every env (env = -1: o holds
+ * n_envs * n entries, env-major): the bodies against which the Signorini-
+ * Coulomb conditions of Eq. 2 are imposed (contact Jacobian H and multipliers
+ * lambda).  Copied; takes effect at the next flash_step.  Errors:
+ * FLASH_ERR_INVALID_ARG for a null batch, env outside [-1, n_envs), n outside
+ * [0, FLASH_MAX_OBSTACLES], a null o with n > 0 or an unknown kind. */
 flash_status flash_set_obstacles(flash_batch *b, int32_t env, const flash_obstacle *o, int32_t n);
 flash_status flash_get_obstacles(flash_batch *b, int32_t env, flash_obstacle *o, int32_t capacity,
                                  int32_t *n_out);
@@ -195,22 +225,38 @@ flash_status flash_get_obstacles(flash_batch *b, int32_t env, flash_obstacle *o,
 flash_status flash_step(flash_batch *b, int32_t n_steps);
 flash_status flash_synchronize(flash_batch *b);
 
-/* Contacts of the last step, sorted by (vertex, obstacle) within an env; env =
- * -1 lists every env in env order.  FLASH_ERR_CAPACITY with *n_out = required
- * count if capacity is too small. */
+/* Contact set of the last step with its multipliers: one record per row block
+ * of the contact Jacobian H (Eq. 2) with the multipliers lambda that solve the
+ * complementarity problem of Eq. 2b at the end of the step, and the impulse
+ * h F lambda.  Sorted by (vertex, obstacle) within an env; env = -1 lists every
+ * env in env order.  out: caller array of `capacity` records (may be NULL with
+ * capacity 0 to query the count).  Synchronises the batch's stream.  Errors:
+ * FLASH_ERR_CAPACITY with *n_out = the required count if capacity is too
+ * small; FLASH_ERR_INVALID_ARG for a null batch or n_out, or env outside
+ * [-1, n_envs). */
 flash_status flash_contacts(flash_batch *b, int32_t env, flash_contact *out, int32_t capacity,
                             int32_t *n_out);
 
-/* Per-env NCP residual of the last step (metres, FP64, evaluated from the end
- * positions and multipliers), its maximum, and Newton iteration counts.  Any
- * argument may be NULL.  Returns FLASH_ERR_NONFINITE if an env holds a
- * non-finite state, FLASH_ERR_NOT_CONVERGED if an env ended above ncp_tol. */
+/* Per-env NCP residual of the last step (metres, FP64), its maximum, and
+ * Newton iteration counts.  The residual is that of the complementarity
+ * function Phi of the contact subproblem (Eq. 2b with the non-smooth Newton
+ * quantities of Eq. 5: min-map Signorini, Alart-Curnier Coulomb, scale
+ * s = h^2 / m_v) evaluated from the end positions and multipliers, max over
+ * contacts of max(|Phi_n|, |Phi_t|); the acceptance tolerance is ncp_tol (the
+ * solver tolerance of the scene configuration).  per_env [n_envs], max_out and
+ * inner_iters [n_envs] are host outputs, any may be NULL.  Synchronises.
+ * Returns, in this order of precedence: FLASH_ERR_NONFINITE if an env holds a
+ * non-finite state (its residual reads NaN); FLASH_ERR_CAPACITY if an env
+ * detected more contacts than max_contacts_per_env (the step ignored the
+ * excess, flag bit 2); FLASH_ERR_NOT_CONVERGED if an env ended above ncp_tol.
+ * The outputs are filled in every case. */
 flash_status flash_residual(flash_batch *b, double *per_env, double *max_out, int32_t *inner_iters);
 flash_status flash_stats(flash_batch *b, flash_env_stats *per_env);
 
 /* Statistics over all envs and steps since the previous reset: worst
- * end-of-step NCP residual (*max_out, metres), env-steps that ended above
- * ncp_tol (*over_out), Newton iterations summed over every contact solve
+ * end-of-step NCP residual (*max_out, metres), failed env-steps (*over_out:
+ * ended above ncp_tol, or dropped contacts beyond the capacity), Newton
+ * iterations summed over every contact solve
  * (*newton_out) and env-steps taken (*env_steps_out).  Any output may be
  * NULL; reset != 0 clears the statistics after reading. */
 flash_status flash_residual_history(flash_batch *b, double *max_out, int64_t *over_out,

@@ -15,6 +15,7 @@ SOURCES = {
     "flash_detect.hip": ["-ffp-contract=off"],
     "flash_kernels.hip": [],
     "flash_host.hip": [],
+    "flash_state.hip": [],
     "flash_mlp.hip": [],
     "flash_mlp_host.hip": [],
 }

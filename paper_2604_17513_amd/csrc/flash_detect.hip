@@ -308,10 +308,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     double m = 0.0;
     for (int w = 0; w < kBlock / 64; ++w) m = fmax(m, sh_red[w]);
     B.resid[e] = m;
-    // worst residual and over-tolerance step count since the last statistics reset
+    // worst residual and failed step count since the last statistics reset; a step that
+    // dropped contacts beyond the capacity (flag bit 2, set by detection) counts as failed
     double* hist = B.resid_hist + 4 * e;
     hist[0] = (m == m) ? fmax(hist[0], m) : INFINITY;
-    if (!(m <= B.ncp_tol)) hist[1] += 1.0;
+    if (!(m <= B.ncp_tol) || (B.flags[e] & 4)) hist[1] += 1.0;
     hist[2] += (double)B.iters[e];
     hist[3] += 1.0;
   }

@@ -999,8 +999,13 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS limit of the contact-solve kernels
-    if (b->fp64) HIPCHK(prepare_csp<double>());
-    else HIPCHK(prepare_csp<float>());
+    size_t static_lds = 0;
+    if (b->fp64) HIPCHK(prepare_csp<double>(&static_lds));
+    else HIPCHK(prepare_csp<float>(&static_lds));
+    if (static_lds > kCspStaticLds)
+      throw FlashError(FLASH_ERR_DEVICE, "contact-solve kernels use " + std::to_string(static_lds) +
+                                             " bytes of static LDS, above the " + std::to_string(kCspStaticLds) +
+                                             " reserved beside the contact data");
     *out = b;
     return FLASH_OK;
   } catch (const FlashError& ex) {
@@ -1079,6 +1084,65 @@ flash_status flash_get_state(flash_batch* b, int32_t env, double* x, double* v) 
   }
   GUARD(if (b->fp64) get_state_t<double>(b, env, x, v); else get_state_t<float>(b, env, x, v));
   return FLASH_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Device-pointer state transfer of env (or of every env for -1) of one ungrouped batch; the
+// caller's arrays are [3][lds] with the first selected vertex at column src0.
+flash_status state_device(flash_batch* b, int env, const void* x, const void* v, void* xo, void* vo_, int elem,
+                          long lds, long src0) {
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->n_envs : env + 1;
+  const int vo = b->voff[e0], n = b->voff[e1] - vo;
+  const size_t es = (size_t)elem;
+  GUARD({
+    if (x || v) {
+      const char* xs = static_cast<const char*>(x) + src0 * es;
+      const char* vs = v ? static_cast<const char*>(v) + src0 * es : nullptr;
+      if (b->fp64) launch_state_in<double>(b->bd, vo, n, e0, e1, xs, vs, elem, lds, b->stream);
+      else launch_state_in<float>(b->bf, vo, n, e0, e1, xs, vs, elem, lds, b->stream);
+    } else {
+      char* xd = xo ? static_cast<char*>(xo) + src0 * es : nullptr;
+      char* vd = vo_ ? static_cast<char*>(vo_) + src0 * es : nullptr;
+      if (b->fp64) launch_state_out<double>(b->bd, vo, n, xd, vd, elem, lds, b->stream);
+      else launch_state_out<float>(b->bf, vo, n, xd, vd, elem, lds, b->stream);
+    }
+    HIPCHK(hipGetLastError());
+  });
+  return FLASH_OK;
+}
+
+flash_status state_device_all(flash_batch* b, int env, const void* x, const void* v, void* xo, void* vo, int elem) {
+  if (!b->groups.empty()) {
+    if (env >= 0) {
+      const int g = group_of(b, env);
+      flash_batch* c = b->groups[g];
+      const int le = env - b->gofs[g];
+      return state_device(c, le, x, v, xo, vo, elem, c->voff[le + 1] - c->voff[le], 0);
+    }
+    return each_group(b, [&](int g, flash_batch* c) {
+      return state_device(c, -1, x, v, xo, vo, elem, b->NV, b->voff[b->gofs[g]]);
+    });
+  }
+  const long n = env < 0 ? b->NV : b->voff[env + 1] - b->voff[env];
+  return state_device(b, env, x, v, xo, vo, elem, n, 0);
+}
+}  // namespace
+
+extern "C" {
+
+flash_status flash_set_state_device(flash_batch* b, int32_t env, const void* x_dev, const void* v_dev,
+                                    int32_t elem_size) {
+  if (!b || !x_dev || bad_env(b, env) || (elem_size != 4 && elem_size != 8))
+    return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env, element size or null x");
+  return state_device_all(b, env, x_dev, v_dev, nullptr, nullptr, elem_size);
+}
+
+flash_status flash_get_state_device(flash_batch* b, int32_t env, void* x_dev, void* v_dev, int32_t elem_size) {
+  if (!b || (!x_dev && !v_dev) || bad_env(b, env) || (elem_size != 4 && elem_size != 8))
+    return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env, element size or no output");
+  return state_device_all(b, env, nullptr, nullptr, x_dev, v_dev, elem_size);
 }
 
 flash_status flash_set_obstacles(flash_batch* b, int32_t env, const flash_obstacle* o, int32_t n) {
@@ -1177,16 +1241,20 @@ flash_status flash_residual(flash_batch* b, double* per_env, double* max_out, in
   flash_status s = flash_stats(b, st.data());
   if (s != FLASH_OK) return s;
   double m = 0.0;
-  bool nonfinite = false, over = false;
+  bool nonfinite = false, over = false, dropped = false;
   for (int e = 0; e < b->n_envs; ++e) {
     if (per_env) per_env[e] = st[e].residual;
     if (inner_iters) inner_iters[e] = st[e].inner_iterations;
     if (!(st[e].residual == st[e].residual) || (st[e].flags & 1)) nonfinite = true;
     else m = std::max(m, st[e].residual);
     if (st[e].residual > b->p.ncp_tol) over = true;
+    if (st[e].flags & 4) dropped = true;
   }
   if (max_out) *max_out = nonfinite ? NAN : m;
   if (nonfinite) return fail(FLASH_ERR_NONFINITE, "an environment holds a non-finite state");
+  if (dropped)
+    return fail(FLASH_ERR_CAPACITY, "an environment detected more contacts than max_contacts_per_env; its step "
+                                    "ignored the excess contacts");
   if (over) return fail(FLASH_ERR_NOT_CONVERGED, "an environment ended above ncp_tol");
   return FLASH_OK;
 }

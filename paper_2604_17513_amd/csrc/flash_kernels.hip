@@ -2017,21 +2017,26 @@ void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t
 }
 
 template <class T>
-hipError_t prepare_csp() {
+hipError_t prepare_csp(size_t* static_lds) {
   constexpr int VW = fused_vw<T>();
   const void* kernels[4] = {(const void*)k_csp<T, double>, (const void*)k_csp<T, T>,
                             (const void*)k_lg_fused<T, double, VW, kFusedUnroll>,
                             (const void*)k_lg_fused<T, T, VW, kFusedUnroll>};
+  size_t most = 0;
   for (const void* k : kernels) {
-    const hipError_t err =
-        hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - kCspStaticLds));
+    hipFuncAttributes fa;
+    hipError_t err = hipFuncGetAttributes(&fa, k);
+    if (err != hipSuccess) return err;
+    most = std::max(most, (size_t)fa.sharedSizeBytes);
+    err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - kCspStaticLds));
     if (err != hipSuccess) return err;
   }
+  if (static_lds) *static_lds = most;
   return hipSuccess;
 }
 
 #define INST(T)                                                          \
-  template hipError_t prepare_csp<T>();                                  \
+  template hipError_t prepare_csp<T>(size_t*);                           \
   template void launch_gather<T>(const DevBatch<T>&, hipStream_t);       \
   template void launch_hinge<T>(const DevBatch<T>&, hipStream_t);        \
   template void launch_order<T>(const DevBatch<T>&, hipStream_t);        \

@@ -4,6 +4,13 @@
 
 namespace flash {
 
+// State of vertices [vo, vo + n) (envs [e0, e1)) from / to caller device arrays [3][lds] of
+// float (elem 4) or double (elem 8); state_in also forgets the warm-start history of those
+// vertices and envs.
+template <class T> void launch_state_in(const DevBatch<T>& B, int vo, int n, int e0, int e1, const void* x,
+                                        const void* v, int elem, long lds, hipStream_t s);
+template <class T> void launch_state_out(const DevBatch<T>& B, int vo, int n, void* x, void* v, int elem, long ldd,
+                                         hipStream_t s);
 template <class T> void launch_detect(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
 template <class T> void launch_finalize(const DevBatch<T>& B, const T* mu_env, hipStream_t s);
 template <class T> void launch_gather(const DevBatch<T>& B, hipStream_t s);
@@ -42,13 +49,15 @@ __host__ __device__ constexpr size_t csp_smem_bytes(int cap, int rlds) {
 }
 // LDS of one gfx950 CU: the most one workgroup can be given, static and dynamic together.
 constexpr size_t kLdsBytes = 160 * 1024;
-// Upper bound of the static LDS of the contact-solve kernels (k_csp and the fused loop: 4160
-// bytes with the FP64 contact solve, 2112 with the FP32 one, from their gfx950 descriptors).
+// Reserve for the static LDS of the contact-solve kernels (k_csp and the fused loop: 4160 bytes
+// with the FP64 contact solve, 2112 with the FP32 one); create checks the kernels' real static
+// LDS against it.
 constexpr size_t kCspStaticLds = 8192;
 // Raises the dynamic LDS limit of the contact-solve kernels (both contact-solve precisions, per
 // kernel and process-wide) to what a CU leaves beside the static reserve, the bound that create
 // checks every capacity against, so batches of different capacities never lower it for each
-// other; returns the first error of the runtime calls.
-template <class T> hipError_t prepare_csp();
+// other; *static_lds receives the largest static LDS of those kernels as the runtime reports it
+// (create fails if it exceeds the reserve); returns the first error of the runtime calls.
+template <class T> hipError_t prepare_csp(size_t* static_lds);
 
 }  // namespace flash

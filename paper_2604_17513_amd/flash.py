@@ -32,6 +32,7 @@ MAX_OBSTACLES = 4
 
 EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
+    "flash_set_state_device", "flash_get_state_device",
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
@@ -104,6 +105,8 @@ def lib():
         L.flash_destroy_batch.argtypes = [P]
         L.flash_set_state.argtypes = [P, I32, D, D]
         L.flash_get_state.argtypes = [P, I32, D, D]
+        L.flash_set_state_device.argtypes = [P, I32, P, P, I32]
+        L.flash_get_state_device.argtypes = [P, I32, P, P, I32]
         L.flash_set_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32]
         L.flash_get_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32, C.POINTER(I32)]
         L.flash_step.argtypes = [P, I32]
@@ -253,6 +256,22 @@ class Batch:
         _check(lib().flash_get_state(self._h, env, _dptr(x), _dptr(v)))
         return x, v
 
+    def set_state_device(self, x_dev, v_dev=None, env: int = -1):
+        """State from device arrays [3][n] (float32 or float64 tensors, component-major); asynchronous."""
+        es = _elem_size(x_dev)
+        if v_dev is not None and _elem_size(v_dev) != es:
+            raise ValueError("x and v must share one element type")
+        _check(lib().flash_set_state_device(self._h, env, C.c_void_p(_devptr(x_dev)),
+                                            C.c_void_p(_devptr(v_dev)) if v_dev is not None else None, es))
+
+    def get_state_device(self, x_dev, v_dev=None, env: int = -1):
+        """State into device arrays [3][n] (float32 or float64 tensors); asynchronous."""
+        ref = x_dev if x_dev is not None else v_dev
+        es = _elem_size(ref)
+        _check(lib().flash_get_state_device(self._h, env,
+                                            C.c_void_p(_devptr(x_dev)) if x_dev is not None else None,
+                                            C.c_void_p(_devptr(v_dev)) if v_dev is not None else None, es))
+
     def split(self, a: np.ndarray) -> List[np.ndarray]:
         return np.split(a, np.cumsum(self.nv)[:-1])
 
@@ -315,12 +334,12 @@ class Batch:
         mx = C.c_double()
         its = np.empty(self.n_envs, dtype=np.int32)
         st = lib().flash_residual(self._h, _dptr(per), C.byref(mx), its.ctypes.data_as(C.POINTER(C.c_int32)))
-        _check(st, allow=(FLASH_ERR_NOT_CONVERGED, FLASH_ERR_NONFINITE))
+        _check(st, allow=(FLASH_ERR_NOT_CONVERGED, FLASH_ERR_NONFINITE, FLASH_ERR_CAPACITY))
         return per, mx.value, its, st
 
     def residual_history(self, reset: bool = True, full: bool = False):
-        """(worst residual, env-steps above ncp_tol) since the last reset; with full=True also
-        (Newton iterations, env-steps)."""
+        """(worst residual, failed env-steps: above ncp_tol or contacts dropped beyond the capacity)
+        since the last reset; with full=True also (Newton iterations, env-steps)."""
         mx = C.c_double()
         over, newton, steps = C.c_int64(), C.c_int64(), C.c_int64()
         _check(lib().flash_residual_history(self._h, C.byref(mx), C.byref(over), C.byref(newton), C.byref(steps),
@@ -389,6 +408,11 @@ class Batch:
 
 def _fptr(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _elem_size(x) -> int:
+    """Bytes per element of a device tensor (4 or 8)."""
+    return int(x.element_size())
 
 
 def _devptr(x) -> int:

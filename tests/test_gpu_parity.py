@@ -57,23 +57,25 @@ def _compare_step(b, sc, oes, env_ids, rel, label=""):
 
 
 def test_fp64_drop_cube_matches_oracle():
+    """The drop cube in FP64 through its whole 120-step horizon (fall, touchdown, settling, rest):
+    every step is checked against the oracle's step from the GPU's start state."""
     F = _flash()
     sc = scenes.drop_cube(seed=0)
     oe = O.precompute(sc.envs[0], sc.params.h)
     b = F.from_scene(sc, precision=F.FLASH_FP64, max_contacts=128)
-    checked = 0
-    for s in range(40):
-        if s in (0, 9, 10, 11, 12, 13, 15, 20, 30, 39):
-            (err, tol, same, r, ref), = _compare_step(b, sc, {0: oe}, [0], 1e-9, f"step {s}")
-            assert same
-            assert err <= tol
-            assert r <= 1e-6
-            checked += 1
-        else:
-            b.step(1)
-    per, mx, its, st = b.residual()
-    assert mx <= 1e-6
-    assert checked == 10
+    checked, worst, touched = 0, 0.0, 0
+    for s in range(120):
+        (err, tol, same, r, ref), = _compare_step(b, sc, {0: oe}, [0], 1e-9, f"step {s}")
+        assert same
+        assert err <= tol
+        assert r <= 1e-6
+        worst = max(worst, err)
+        touched += ref.contacts.count > 0
+        checked += 1
+        per, mx, its, st = b.residual()
+        assert mx <= 1e-6
+    _say(f"drop cube: {checked} steps checked, worst |dq| {worst:.2e}, {touched} steps with contacts")
+    assert checked == 120 and touched > 100
 
 
 def test_fp32_squeeze_blocks_match_oracle():
@@ -194,3 +196,9 @@ def test_ragged_batch_and_capacity_flag():
     assert counts == [9, 16, 32, 32]
     assert all(s["flags"] & 4 for s in st[2:])
     assert all((s["flags"] & 4) == 0 for s in st[:2])
+    # a step that dropped contacts is an error of the residual query and a failed env-step
+    per, mx, its, status = b.residual()
+    assert status == F.FLASH_ERR_CAPACITY
+    mx, failed = b.residual_history(reset=True)
+    _say("failed env-steps", failed)
+    assert failed >= 4
