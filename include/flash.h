@@ -376,6 +376,23 @@ flash_status flash_mlp_forward(flash_mlp *m, const float *x_dev, int64_t n, floa
  * to every parameter (host grad[FLASH_MLP_PARAMS], *loss may be NULL). */
 flash_status flash_mlp_grad(flash_mlp *m, const float *x_dev, const float *target_dev, int64_t n,
                             float *grad, float *loss);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the loss and
+ * gradient of flash_mlp_grad without a trainer object and without any
+ * allocation.  params_dev: FP32 parameters (device, FLASH_MLP_PARAMS values in
+ * the layout above); x_dev [n x 16] normalised inputs and target_dev [n x 3]
+ * scaled labels (device); grad_dev [FLASH_MLP_PARAMS] and loss_dev [1]
+ * (device outputs; loss_dev may be NULL).  1 <= n <= 2048.  Enqueued on
+ * hip_stream (NULL: the null stream) and not synchronised.  Every
+ * intermediate (activations, backward buffers, split-K partial sums, loss
+ * partials: about 9.1 MB) lives in one static device array per GPU, held
+ * until the process ends; calls that overlap on one GPU race on it and must
+ * be serialised by the caller (one stream, or events).  The result is
+ * bitwise that of flash_mlp_grad for the same parameters and rows.  Errors:
+ * FLASH_ERR_INVALID_ARG for a null pointer or n <= 0, FLASH_ERR_CAPACITY for
+ * n > 2048, FLASH_ERR_DEVICE if a launch fails. */
+flash_status flash_mlp_grad_noalloc(const float *params_dev, const float *x_dev, const float *target_dev,
+                                    int64_t n, float *grad_dev, float *loss_dev, void *hip_stream);
 /* Adam on raw (feature, label) rows: per epoch a splitmix64(seed) shuffle,
  * floor(n / batch) minibatches, normalisation by the trainer's norm.
  * epoch_loss (host, epochs entries, may be NULL) receives the mean

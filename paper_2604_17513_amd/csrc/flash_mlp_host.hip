@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -47,6 +48,44 @@ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
+// Scratch of flash_mlp_grad_noalloc, one copy per GPU for the life of the process: the
+// hidden activations H1..H3 and the backward buffers dA, dB (rows x 128 floats each), the
+// network output and its loss gradient (rows x 3 each), the split-K partial sums of the weight
+// gradients (the trainer's size, so that both entry points split every product the same way)
+// and the per-block loss partials.
+constexpr long kNaRows = 2048;
+constexpr long kNaWork = 64L * kHidden * kHidden;
+constexpr long kNaPartials = (3 * kNaRows + 255) / 256 + 1;
+constexpr size_t kNaHid = (size_t)kNaRows * kHidden * sizeof(float);
+constexpr size_t kNaOut = (size_t)kNaRows * kOut * sizeof(float);
+constexpr size_t kNaOffPartial = 0;
+constexpr size_t kNaOffH = 256;
+constexpr size_t kNaOffY = kNaOffH + 5 * kNaHid;
+constexpr size_t kNaOffWork = kNaOffY + 2 * kNaOut + 256;
+constexpr size_t kNaBytes = kNaOffWork + (size_t)kNaWork * sizeof(float);
+static_assert(kNaPartials * sizeof(double) <= kNaOffH, "loss partials fit their slot");
+static_assert(kNaOffWork % 256 == 0 && kNaOffY % 256 == 0, "aligned scratch regions");
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Device address of this GPU's scratch, looked up once per device with that device current.
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mutex;
+unsigned char* g_na_ptr[kNaMaxDevices] = {};
+
+unsigned char* noalloc_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNaMaxDevices) throw FlashError(FLASH_ERR_DEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_na_mutex);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_na_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  return g_na_ptr[dev];
+}
+
 }  // namespace
 
 struct flash_mlp {
@@ -82,6 +121,8 @@ struct flash_mlp {
     mlp_backward(W, X, n, H1, H2, H3, dY, dA, dB, G, work, kWork, stream);
   }
 };
+
+static_assert(kNaWork == flash_mlp::kWork, "the no-allocation gradient splits products like the trainer");
 
 namespace {
 flash_status fail(flash_status s, const std::string& m) { return record_error(s, m); }
@@ -265,6 +306,37 @@ flash_status flash_mlp_grad(flash_mlp* m, const float* x, const float* target, i
     HIPCHK(hipStreamSynchronize(m->stream));
     HIPCHK(hipMemcpy(grad, m->G, MlpLayout::total * sizeof(float), hipMemcpyDeviceToHost));
     if (loss) HIPCHK(hipMemcpy(loss, m->loss, sizeof(float), hipMemcpyDeviceToHost));
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_mlp_grad_noalloc(const float* params, const float* x, const float* target, int64_t n,
+                                    float* grad, float* loss, void* hip_stream) {
+  if (!params || !x || !target || !grad || n <= 0) return fail(FLASH_ERR_INVALID_ARG, "null or empty argument");
+  if (n > kNaRows)
+    return fail(FLASH_ERR_CAPACITY, "flash_mlp_grad_noalloc takes at most " + std::to_string(kNaRows) + " rows, got " +
+                                        std::to_string((long long)n));
+  try {
+    const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    unsigned char* base = noalloc_scratch();
+    prepare_mlp();
+    double* partial = reinterpret_cast<double*>(base + kNaOffPartial);
+    float* H1 = reinterpret_cast<float*>(base + kNaOffH);
+    float* H2 = reinterpret_cast<float*>(base + kNaOffH + kNaHid);
+    float* H3 = reinterpret_cast<float*>(base + kNaOffH + 2 * kNaHid);
+    float* dA = reinterpret_cast<float*>(base + kNaOffH + 3 * kNaHid);
+    float* dB = reinterpret_cast<float*>(base + kNaOffH + 4 * kNaHid);
+    float* Y = reinterpret_cast<float*>(base + kNaOffY);
+    float* dY = reinterpret_cast<float*>(base + kNaOffY + kNaOut);
+    float* work = reinterpret_cast<float*>(base + kNaOffWork);
+    // the loss goes to the caller's buffer, or to a slot after the network output when none is given
+    float* loss_dst = loss ? loss : reinterpret_cast<float*>(base + kNaOffY + 2 * kNaOut);
+    launch_mlp_fused(params, nullptr, x, (long)n, nullptr, Y, H1, H2, H3, s);
+    mlp_loss(Y, target, (long)n, dY, partial, loss_dst, s);
+    mlp_backward(params, x, (long)n, H1, H2, H3, dY, dA, dB, grad, work, kNaWork, s);
+    HIPCHK(hipGetLastError());
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());
   }

@@ -39,7 +39,8 @@ EXPORTED = [
     "flash_ws_record",
     "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
     "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
-    "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_train", "flash_mlp_eval", "flash_last_error",
+    "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_grad_noalloc", "flash_mlp_train", "flash_mlp_eval",
+    "flash_last_error",
     "flash_version",
 ]
 MLP_FEATURES, MLP_HIDDEN, MLP_OUTPUTS, MLP_PARAMS, MLP_NORM = 16, 128, 3, 35587, 35
@@ -136,6 +137,7 @@ def lib():
         L.flash_mlp_fit_norm.argtypes = [P, P, P, I64]
         L.flash_mlp_forward.argtypes = [P, P, I64, P]
         L.flash_mlp_grad.argtypes = [P, P, P, I64, F32, F32]
+        L.flash_mlp_grad_noalloc.argtypes = [P, P, P, I64, P, P, P]
         L.flash_mlp_train.argtypes = [P, P, P, I64, I32, I32, C.c_float, C.c_uint64, F32]
         L.flash_mlp_eval.argtypes = [P, P, P, I64, F32]
         L.flash_last_error.restype = C.c_char_p
@@ -487,6 +489,14 @@ class Mlp:
         _check(lib().flash_mlp_eval(self._h, C.c_void_p(_devptr(feat_dev)), C.c_void_p(_devptr(lab_dev)), int(n),
                                     _fptr(loss)))
         return float(loss[0])
+
+
+def mlp_grad_noalloc(params_dev, x_dev, target_dev, n: int, grad_dev, loss_dev=None, stream: int = 0):
+    """flash_mlp_grad_noalloc: loss and gradient into device arrays, no allocation, asynchronous."""
+    _check(lib().flash_mlp_grad_noalloc(C.c_void_p(_devptr(params_dev)), C.c_void_p(_devptr(x_dev)),
+                                        C.c_void_p(_devptr(target_dev)), int(n), C.c_void_p(_devptr(grad_dev)),
+                                        C.c_void_p(_devptr(loss_dev)) if loss_dev is not None else None,
+                                        C.c_void_p(stream)))
 
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
