@@ -160,10 +160,11 @@ typedef struct {
                                      capacity, bit 3: Newton system above its row capacity
                                      (contact capacity above 512) */
   int32_t ws_state;               /* learned warm start: bit 0 the step's first contact solve started
-                                     from the network's prediction; bits 8-15 count solves from a
-                                     prediction that missed the tolerance and were restarted from the
-                                     plain start; bit 1 the prediction is disabled for this env after 3
-                                     of them (cleared by flash_set_state and flash_ws_load) */
+                                     from the network's prediction; bit 2 this step's solve from the
+                                     prediction missed the tolerance and was restarted from the plain
+                                     start; bits 8-15 count such restarts; bit 1 the prediction is
+                                     disabled for this env after 3 of them (cleared by flash_set_state
+                                     and flash_ws_load) */
   double residual;                /* NCP residual at the end of the step, m (FP64) */
 } flash_env_stats;
 
@@ -337,6 +338,14 @@ enum { FLASH_MLP_FEATURES = 16, FLASH_MLP_HIDDEN = 128, FLASH_MLP_OUTPUTS = 3,
  * bit.  A captured step graph is re-captured at the next flash_step. */
 flash_status flash_ws_load(flash_batch *b, const uint16_t *weights_bf16, size_t n_params,
                            const float *norm);
+
+/* Use of the learned start over all envs and steps since the previous reset:
+ * *started_out = env-steps whose first contact solve started from the
+ * network's prediction, *restarted_out = env-steps whose solve from the
+ * prediction missed the tolerance and was restarted from the plain start.
+ * Either output may be NULL; reset != 0 clears the counts after reading.
+ * Synchronises. */
+flash_status flash_ws_history(flash_batch *b, int64_t *started_out, int64_t *restarted_out, int32_t reset);
 
 /* Training-pair recording.  on != 0: each step also evaluates the features
  * of its contacts at the step start (a captured graph is re-captured).

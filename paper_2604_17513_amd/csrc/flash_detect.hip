@@ -315,6 +315,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     if (!(m <= B.ncp_tol) || (B.flags[e] & 4)) hist[1] += 1.0;
     hist[2] += (double)B.iters[e];
     hist[3] += 1.0;
+    if (B.ws_hist) {
+      const int w = B.ws_state[e];
+      B.ws_hist[2 * e] += (unsigned long long)(w & 1);
+      B.ws_hist[2 * e + 1] += (unsigned long long)((w >> 2) & 1);
+    }
   }
   if (bad) atomicOr(&B.flags[e], 1);
   __syncthreads();

@@ -129,9 +129,12 @@ struct DevBatch {
 
   // learned warm start (optional)
   const double* lam_ml;       // [3 per contact] predicted multipliers (nullptr: off)
-  int* ws_state;              // [n_envs] bit 0: this step started from the prediction; bits 8-15:
-                              // solves from a prediction that missed the tolerance (restarted);
-                              // bit 1: prediction disabled after kWsMaxFail of them
+  int* ws_state;              // [n_envs] bit 0: this step started from the prediction; bit 2: this
+                              // step's solve from the prediction missed the tolerance and restarted;
+                              // bits 8-15: such restarts so far; bit 1: prediction disabled after
+                              // kWsMaxFail of them
+  unsigned long long* ws_hist;  // [2 per env] since the last reset: steps started from the prediction,
+                                // steps restarted from the plain start
 };
 
 }  // namespace flash

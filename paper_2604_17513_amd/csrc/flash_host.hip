@@ -710,6 +710,8 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   HIPCHK(hipMemset(B.resid, 0, ne * sizeof(double)));
   B.resid_hist = dalloc<double>(4 * (size_t)ne, own);
   HIPCHK(hipMemset(B.resid_hist, 0, 4 * (size_t)ne * sizeof(double)));
+  B.ws_hist = dalloc<unsigned long long>(2 * (size_t)ne, own);
+  HIPCHK(hipMemset(B.ws_hist, 0, 2 * (size_t)ne * sizeof(unsigned long long)));
   B.ncp_tol = b->p.ncp_tol;
   B.iters = dalloc<int>(ne, own);
   B.refac = dalloc<int>(ne, own);
@@ -1338,6 +1340,37 @@ flash_status flash_residual_history(flash_batch* b, double* max_out, int64_t* ov
     if (newton_out) *newton_out = newton;
     if (env_steps_out) *env_steps_out = steps;
     if (reset) HIPCHK(hipMemset(dp, 0, h.size() * sizeof(double)));
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_ws_history(flash_batch* b, int64_t* started_out, int64_t* restarted_out, int32_t reset) {
+  if (!b) return fail(FLASH_ERR_INVALID_ARG, "null batch");
+  if (!b->groups.empty()) {
+    int64_t st = 0, rs = 0;
+    const flash_status s = each_group(b, [&](int, flash_batch* c) {
+      int64_t a = 0, r = 0;
+      const flash_status s2 = flash_ws_history(c, &a, &r, reset);
+      st += a; rs += r;
+      return s2;
+    });
+    if (started_out) *started_out = st;
+    if (restarted_out) *restarted_out = rs;
+    return s;
+  }
+  try {
+    HIPCHK(hipStreamSynchronize(b->stream));
+    const int ne = b->n_envs;
+    unsigned long long* dp = b->fp64 ? b->bd.ws_hist : b->bf.ws_hist;
+    std::vector<unsigned long long> h(2 * (size_t)ne);
+    HIPCHK(hipMemcpy(h.data(), dp, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    int64_t st = 0, rs = 0;
+    for (int e = 0; e < ne; ++e) { st += (int64_t)h[2 * e]; rs += (int64_t)h[2 * e + 1]; }
+    if (started_out) *started_out = st;
+    if (restarted_out) *restarted_out = rs;
+    if (reset) HIPCHK(hipMemset(dp, 0, h.size() * sizeof(unsigned long long)));
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());
   }

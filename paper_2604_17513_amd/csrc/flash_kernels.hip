@@ -1208,7 +1208,7 @@ __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, i
   const unsigned long long t_start = (own_cost && B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
   const int c = B.ccount[e];
   if (c == 0) {
-    if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~1;
+    if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~5;
     return;
   }
   const int cap = B.cap;
@@ -1827,8 +1827,9 @@ restart:
     if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
     if (own_cost && B.cost) B.cost[e] += wall_clock64() - t_start;
     if (first_lg && B.ws_state) {
-      int w = B.ws_state[e] & ~1;
+      int w = B.ws_state[e] & ~5;
       if (learned && !learned_failed) w |= 1;
+      if (learned_failed) w |= 4;
       if (learned_failed && (w & 0xff00) < (kWsMaxFail << 8)) w += 1 << 8;
       if ((w & 0xff00) >= (kWsMaxFail << 8)) w |= 2;   // previous-iterate start only from now on
       B.ws_state[e] = w;

@@ -36,7 +36,7 @@ EXPORTED = [
     "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
-    "flash_ws_record",
+    "flash_ws_record", "flash_ws_history",
     "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
     "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
     "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_grad_noalloc", "flash_mlp_train", "flash_mlp_eval",
@@ -126,6 +126,7 @@ def lib():
         F32, I64 = C.POINTER(C.c_float), C.c_int64
         L.flash_ws_load.argtypes = [P, C.POINTER(C.c_uint16), C.c_size_t, F32]
         L.flash_ws_record.argtypes = [P, I32]
+        L.flash_ws_history.argtypes = [P, C.POINTER(I64), C.POINTER(I64), I32]
         L.flash_ws_collect.argtypes = [P, P, P, I64, C.POINTER(I64)]
         L.flash_mlp_create.argtypes = [I64, C.c_uint64, P, C.POINTER(P)]
         L.flash_mlp_destroy.argtypes = [P]
@@ -396,6 +397,12 @@ class Batch:
         w = np.ascontiguousarray(weights_bf16, dtype=np.uint16)
         nm = np.ascontiguousarray(norm, dtype=np.float32)
         _check(lib().flash_ws_load(self._h, w.ctypes.data_as(C.POINTER(C.c_uint16)), w.size, _fptr(nm)))
+
+    def ws_history(self, reset: bool = True):
+        """(env-steps started from the prediction, env-steps restarted from the plain start) since the last reset."""
+        a, r = C.c_int64(), C.c_int64()
+        _check(lib().flash_ws_history(self._h, C.byref(a), C.byref(r), 1 if reset else 0))
+        return a.value, r.value
 
     def ws_record(self, on: bool = True):
         _check(lib().flash_ws_record(self._h, 1 if on else 0))
