@@ -712,3 +712,135 @@ def rollout(oe: OracleEnv, x, v, obstacles, params, n_steps: int, tol: float = 1
         out.append(res)
         x, v, obstacles = res.x, res.v, res.obstacles
     return out
+
+
+# =============================================================================
+# Fixed-budget lightweight mode (Alg. 1 with the inertia-only contact metric, Eq. 10)
+# =============================================================================
+#
+# Alg. 1 updates the multipliers once per local-global iteration with the
+# lightweight Schur complement Z~ = J M^-1 J^T + E (Eq. 10) in place of the
+# exact Z = J A^-1 J^T + E (Eq. 7), and recomputes the positions with the
+# exact global solve (Eq. 9); the scene configuration bounds the non-smooth
+# Newton iterations ("iterations") and stops them at a tolerance, and the
+# parameter table sets 5 local-global and 10 linear-solver iterations.  This
+# mode runs, for each of K local-global iterations, up to N such updates:
+#   g = b + h^2 H^T lambda,  q_g = A^-1 g                    (global solve)
+#   Phi, K, E at (q_g, lambda)                                (Eq. 5)
+#   stop if r(Phi) <= tol
+#   delta = -(K W~ + E)^-1 Phi,  W~ = h^2 H M^-1 H^T          (Eq. 8 with Eq. 10)
+#   lambda <- clip(lambda + delta)
+# and then q^k = A^-1 (b + h^2 H^T lambda) (Eq. 9).  N = 1 is Alg. 1 as
+# printed.  With the positions q_g consistent with lambda, Alg. 1's increment
+# (1/h^2) Z~^-1 (h - J A^-1 g) equals -(K W~ + E)^-1 Phi in these units
+# (lambda in newtons, Phi in metres); Phi is evaluated exactly at q_g rather
+# than through its linearisation.  No line search: the algorithm has none.
+# The proximal scale is the residual scale s = h^2 / m_v, which is the
+# diagonal of W~ for a vertex with one contact.  W~ couples only contacts on
+# the same vertex.  The result depends on the budget and is not the converged
+# step unless the iteration converges within it.
+
+def contact_blocks(Y, lam, d0, dob, s, mu):
+    """Phi (c,3) and the generalized-Jacobian blocks of each contact at contact-frame displacement
+    Y (c,3) and multipliers lam (c,3): K_j = dPhi_j/dY_j, E_j = dPhi_j/dlambda_j (3x3 each), with
+    the min-map normal and Alart-Curnier tangential parts at proximal scale s (c,)."""
+    c = Y.shape[0]
+    phi = np.zeros((c, 3))
+    Kb = np.zeros((c, 3, 3))
+    Eb = np.zeros((c, 3, 3))
+    for j in range(c):
+        cn = d0[j] + Y[j, 0]
+        ut = Y[j, 1:] - dob[j]
+        sj = s[j]
+        if cn <= sj * lam[j, 0]:              # normal active: Phi_n = C_n
+            phi[j, 0] = cn
+            Kb[j, 0, 0] = 1.0
+        else:                                 # inactive: Phi_n = s lambda_n
+            phi[j, 0] = sj * lam[j, 0]
+            Eb[j, 0, 0] = sj
+        y = lam[j, 1:] - ut / sj
+        rho = mu * max(lam[j, 0], 0.0)
+        ny = float(np.linalg.norm(y))
+        if rho <= 0.0:                        # no friction force available: Phi_t = s lambda_t
+            phi[j, 1:] = sj * lam[j, 1:]
+            Eb[j, 1:, 1:] = sj * np.eye(2)
+        elif ny <= rho:                       # stick: Phi_t = u_t
+            phi[j, 1:] = ut
+            Kb[j, 1:, 1:] = np.eye(2)
+        else:                                 # slip
+            yh = y / ny
+            kap = rho / ny
+            P = np.eye(2) - np.outer(yh, yh)
+            phi[j, 1:] = sj * (lam[j, 1:] - rho * yh)
+            Kb[j, 1:, 1:] = kap * P
+            Eb[j, 1:, 1:] = sj * (np.eye(2) - kap * P)
+            Eb[j, 1:, 0] = -sj * mu * yh
+    return phi, Kb, Eb
+
+
+def inertia_metric(oe: OracleEnv, contacts: Contacts, h: float) -> np.ndarray:
+    """W~ = h^2 H M^-1 H^T in contact frames (3c x 3c): (h^2 / m_v) F_j^T F_k for contacts j, k on the
+    same vertex v, zero otherwise (Eq. 10's inertia-only metric)."""
+    c = contacts.count
+    Wt = np.zeros((3 * c, 3 * c))
+    for j in range(c):
+        for k in range(c):
+            if contacts.vertex[j] == contacts.vertex[k]:
+                vj = contacts.vertex[j]
+                Wt[3 * j:3 * j + 3, 3 * k:3 * k + 3] = h * h / oe.mass[vj] * (contacts.frame[j].T @ contacts.frame[k])
+    return Wt
+
+
+def _contact_force_field(oe: OracleEnv, contacts: Contacts, lam):
+    """H^T lambda as per-vertex world forces (n, 3)."""
+    f = np.zeros((oe.n, 3))
+    if contacts.count:
+        np.add.at(f, contacts.vertex, np.einsum("jia,ja->ji", contacts.frame, lam))
+    return f
+
+
+def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: int, tol: float = 0.0,
+                     lam_warm=None) -> StepResult:
+    """One time step in the fixed-budget lightweight mode described above (K = params.lg_iterations,
+    N = newton_iterations).  info['newton'] counts the multiplier updates, info['lam_history'] holds
+    the multipliers after each update."""
+    h = float(params.h)
+    x = np.asarray(x, dtype=np.float64)
+    v = np.asarray(v, dtype=np.float64)
+    contacts = detect(x, v, obstacles, params)
+    qt = predicted_state(x, v, h, params.gravity)
+    q = qt.copy()
+    c = contacts.count
+    lam = np.zeros((c, 3)) if lam_warm is None else np.array(lam_warm, dtype=np.float64).reshape(c, 3)
+    s = h * h / oe.mass[contacts.vertex] if c else np.zeros(0)
+    Fr = contacts.frame
+    dob = np.einsum("jia,ji->ja", Fr, contacts.dobs)[:, 1:] if c else np.zeros((0, 2))
+    Wt = inertia_metric(oe, contacts, h)
+    info = {"newton": 0, "lam_history": [], "csp_residuals": []}
+    for k in range(int(params.lg_iterations)):
+        p = project(oe, q)
+        b = assemble_rhs(oe, qt, p, h)
+        if c:
+            for it in range(int(newton_iterations)):
+                qg = oe.solve(b + h * h * _contact_force_field(oe, contacts, lam))
+                Y = np.einsum("jia,ji->ja", Fr, qg[contacts.vertex] - x[contacts.vertex])
+                phi, Kb, Eb = contact_blocks(Y, lam, contacts.d0, dob, s, oe.mu)
+                r = residual_of(phi)
+                if r <= tol:
+                    break
+                Z = np.zeros((3 * c, 3 * c))
+                for j in range(c):
+                    Z[3 * j:3 * j + 3, :] = Kb[j] @ Wt[3 * j:3 * j + 3, :]
+                    Z[3 * j:3 * j + 3, 3 * j:3 * j + 3] += Eb[j]
+                delta = np.linalg.solve(Z, -phi.reshape(-1)).reshape(c, 3)
+                lam = np.clip(lam + delta, -params.max_force, params.max_force)
+                info["newton"] += 1
+                info["lam_history"].append(lam.copy())
+            info["csp_residuals"].append(r)
+        q = oe.solve(b + h * h * _contact_force_field(oe, contacts, lam))
+    xn = q
+    vn = (q - x) / h
+    impulse = h * np.einsum("jia,ja->ji", Fr, lam) if c else np.zeros((0, 3))
+    r = contact_residual(oe, x, q, contacts, lam, h)
+    new_obs = [advance_obstacle(ob, h) for ob in obstacles]
+    return StepResult(xn, vn, contacts, lam, impulse, r, new_obs, info)
