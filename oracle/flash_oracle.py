@@ -322,11 +322,22 @@ def tangent_frame(n: np.ndarray):
 
 @dataclass
 class Contacts:
+    """Constraint rows of a step, in (vertex, obstacle) order.
+
+    Obstacle contacts: frame columns n, t1, t2, gap d0, obstacle displacement dobs.
+    Attachment rows (bilateral, supplementary Eq. 13), obstacle index MAX_OBSTACLES + gripper:
+    frame I, d = target - x stored as d0 = -d[0] and dobs = d, so that the contact-frame
+    quantities become Phi = Y - d with every row active and sticking (no cone)."""
     vertex: np.ndarray      # (c,) int
     obstacle: np.ndarray    # (c,) int
     frame: np.ndarray       # (c, 3, 3) columns n, t1, t2
     d0: np.ndarray          # (c,)
     dobs: np.ndarray        # (c, 3) obstacle displacement over the step
+    attach: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=bool))
+
+    def __post_init__(self):
+        if self.attach.shape[0] != self.vertex.shape[0]:
+            self.attach = np.zeros(self.vertex.shape[0], dtype=bool)
 
     @property
     def count(self) -> int:
@@ -339,12 +350,52 @@ def predicted_state(x, v, h, gravity):
     return (x + h * v) + (h * h) * g[None, :]
 
 
-def detect(x, v, obstacles, params) -> Contacts:
-    """Vertex-obstacle contacts, listed in (vertex, obstacle) order.
+MAX_OBSTACLES = 4
+
+
+def grasp_update(x, grippers, held):
+    """Attachment sets at the start of a step (supplementary, bilateral constraint for cloth
+    control): a gripper whose grasp is off holds nothing; a grasping gripper that holds no vertex
+    takes every vertex within its radius of its center ((dx^2 + dy^2) + dz^2 <= r^2, FP64), with
+    the offset o = x - c, except vertices already held by another gripper (lower index first).
+    held: list (per gripper) of dicts vertex -> offset, or None."""
+    held = [dict(hg) for hg in held] if held else [dict() for _ in grippers]
+    while len(held) < len(grippers):
+        held.append({})
+    for g, gr in enumerate(grippers):
+        if not gr.grasp:
+            held[g] = {}
+    for g, gr in enumerate(grippers):
+        if gr.grasp and not held[g]:
+            taken = set().union(*[set(hg) for hg in held]) if held else set()
+            c = np.asarray(gr.center, dtype=np.float64)
+            r = float(gr.radius)
+            d = x - c[None, :]
+            d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+            held[g] = {int(i): d[i].copy() for i in np.nonzero(d2 <= r * r)[0] if int(i) not in taken}
+    return held[:len(grippers)]
+
+
+def gripper_displacement(gr, h: float) -> np.ndarray:
+    return np.zeros(3) if gr.move_steps == 0 else h * np.asarray(gr.lin_vel, dtype=np.float64)
+
+
+def advance_gripper(gr, h: float):
+    gr = gr.copy()
+    gr.center = gr.center + gripper_displacement(gr, h)
+    if gr.move_steps > 0:
+        gr.move_steps -= 1
+    return gr
+
+
+def detect(x, v, obstacles, params, grippers=None, held=None) -> Contacts:
+    """Vertex-obstacle contacts and attachment rows, listed in (vertex, obstacle) order.
 
     A pair is a contact iff the predicate holds at x or at the predicted
     position x~, with the obstacle at its end-of-step pose.  Normal, tangents
-    and gap d0 are taken at x.
+    and gap d0 are taken at x.  A vertex held by gripper g adds an attachment
+    row (obstacle index MAX_OBSTACLES + g) with target c_g(t+h) + o (the
+    gripper's end-of-step pose plus the offset taken at capture).
     """
     h = params.h
     margin = params.contact_margin
@@ -373,13 +424,36 @@ def detect(x, v, obstacles, params) -> Contacts:
     verts = np.asarray(verts, dtype=np.int64)
     obsi = np.asarray(obsi, dtype=np.int64)
     if c == 0:
-        return Contacts(verts, obsi, np.zeros((0, 3, 3)), np.zeros(0), np.zeros((0, 3)))
-    nn = np.stack([normals[o][vv] for vv, o in zip(verts, obsi)])
-    t1, t2 = tangent_frame(nn)
-    frame = np.stack([nn, t1, t2], axis=2)
-    d0 = np.array([d0s[o][vv] for vv, o in zip(verts, obsi)])
-    dob = np.stack([dobs[o] for o in obsi])
-    return Contacts(verts, obsi, frame, d0, dob)
+        con = Contacts(verts, obsi, np.zeros((0, 3, 3)), np.zeros(0), np.zeros((0, 3)))
+    else:
+        nn = np.stack([normals[o][vv] for vv, o in zip(verts, obsi)])
+        t1, t2 = tangent_frame(nn)
+        frame = np.stack([nn, t1, t2], axis=2)
+        d0 = np.array([d0s[o][vv] for vv, o in zip(verts, obsi)])
+        dob = np.stack([dobs[o] for o in obsi])
+        con = Contacts(verts, obsi, frame, d0, dob)
+    if not grippers or not held or not any(held):
+        return con
+    # attachment rows, merged into the (vertex, obstacle) order
+    rows = []
+    for g, gr in enumerate(grippers):
+        cn = np.asarray(gr.center, dtype=np.float64) + gripper_displacement(gr, h)
+        for vtx, off in held[g].items():
+            d = (cn + off) - x[vtx]
+            rows.append((vtx, MAX_OBSTACLES + g, d))
+    keys = [(int(a), int(b), "c", j) for j, (a, b) in enumerate(zip(con.vertex, con.obstacle))]
+    keys += [(vtx, o, "a", k) for k, (vtx, o, _) in enumerate(rows)]
+    keys.sort(key=lambda t: (t[0], t[1]))
+    V, Ob, Fr, D0, Dob, At = [], [], [], [], [], []
+    for vtx, o, kind, k in keys:
+        V.append(vtx); Ob.append(o)
+        if kind == "c":
+            Fr.append(con.frame[k]); D0.append(con.d0[k]); Dob.append(con.dobs[k]); At.append(False)
+        else:
+            d = rows[k][2]
+            Fr.append(np.eye(3)); D0.append(-d[0]); Dob.append(d.copy()); At.append(True)
+    return Contacts(np.asarray(V, dtype=np.int64), np.asarray(Ob, dtype=np.int64), np.stack(Fr),
+                    np.asarray(D0), np.stack(Dob), np.asarray(At, dtype=bool))
 
 
 # =============================================================================
@@ -441,6 +515,10 @@ class CSP:
     s: np.ndarray        # (c,) h^2 / m_v
     mu: float
     max_force: float
+    attach: np.ndarray = None   # (c,) bool: bilateral rows (Phi = Y - d, always active and sticking)
+
+    def att(self) -> np.ndarray:
+        return self.attach if self.attach is not None else np.zeros(self.d0.shape[0], dtype=bool)
 
 
 def build_csp(oe: OracleEnv, x, qb, contacts: Contacts, h: float, max_force: float):
@@ -462,7 +540,7 @@ def build_csp(oe: OracleEnv, x, qb, contacts: Contacts, h: float, max_force: flo
     y0 = np.einsum("jia,ji->ja", Fr, disp).reshape(-1)
     dob = np.einsum("jia,ji->ja", Fr, contacts.dobs)[:, 1:]
     s = h * h / oe.mass[contacts.vertex]
-    return CSP(y0, W, contacts.d0.copy(), dob, s, oe.mu, max_force), Gcols, inv
+    return CSP(y0, W, contacts.d0.copy(), dob, s, oe.mu, max_force, contacts.attach.copy()), Gcols, inv
 
 
 def ncp_function(csp: CSP, lam: np.ndarray, s: Optional[np.ndarray] = None):
@@ -487,9 +565,14 @@ def ncp_function(csp: CSP, lam: np.ndarray, s: Optional[np.ndarray] = None):
     ny = np.linalg.norm(y, axis=1)
     proj = y.copy()
     out = ny > rho
+    att = csp.att()
+    out &= ~att
     with np.errstate(invalid="ignore", divide="ignore"):
         proj[out] = (rho[out] / ny[out])[:, None] * y[out]
     phi[:, 1:] = s[:, None] * (lam[:, 1:] - proj)
+    # bilateral rows: Phi = Y - d (the attached vertex at its target)
+    phi[att, 0] = Cn[att]
+    phi[att, 1:] = ut[att]
     return phi, Cn, ut, y, rho, ny
 
 
@@ -513,9 +596,13 @@ def generalized_jacobian(csp: CSP, lam: np.ndarray, s: Optional[np.ndarray] = No
         s = csp.s
     phi, Cn, ut, y, rho, ny = ncp_function(csp, lam, s)
     W = csp.W
+    att = csp.att()
     Jm = np.zeros((3 * c, 3 * c))
     for j in range(c):
         rn = 3 * j
+        if att[j]:                            # bilateral: rows of W, E = 0
+            Jm[rn:rn + 3, :] = W[rn:rn + 3, :]
+            continue
         if Cn[j] <= s[j] * lam[j, 0]:
             Jm[rn, :] = W[rn, :]
         else:
@@ -598,10 +685,18 @@ def _pgs(csp: CSP, lam, tol, max_sweeps, info):
     W = csp.W
     lam = lam.copy()
     Y = csp.y0 + W @ lam.reshape(-1)
+    att = csp.att()
     for sweep in range(max_sweeps):
         for j in range(c):
             i = 3 * j
             Wjj = W[i:i + 3, i:i + 3]
+            if att[j]:
+                # bilateral row: lambda_j <- lambda_j - W_jj^-1 (Y_j - d_j), unbounded
+                r = np.array([csp.d0[j] + Y[i], Y[i + 1] - csp.dob[j, 0], Y[i + 2] - csp.dob[j, 1]])
+                dl = -np.linalg.solve(Wjj, r)
+                lam[j] += dl
+                Y += W[:, i:i + 3] @ dl
+                continue
             # normal: lambda_n <- max(0, lambda_n - C_n / W_nn)
             Cn = csp.d0[j] + Y[i]
             ln = max(0.0, lam[j, 0] - Cn / Wjj[0, 0])
@@ -640,6 +735,8 @@ class StepResult:
     residual: float
     obstacles: list
     info: dict = field(default_factory=dict)
+    grippers: list = field(default_factory=list)
+    held: list = field(default_factory=list)
 
 
 def contact_residual(oe: OracleEnv, x, q, contacts: Contacts, lam, h: float) -> float:
@@ -660,18 +757,25 @@ def contact_residual(oe: OracleEnv, x, q, contacts: Contacts, lam, h: float) -> 
     rho = oe.mu * np.maximum(lam[:, 0], 0.0)
     ny = np.linalg.norm(y, axis=1)
     proj = y.copy()
-    out = ny > rho
+    att = contacts.attach
+    out = (ny > rho) & ~att
     proj[out] = (rho[out] / ny[out])[:, None] * y[out]
     phi[:, 1:] = s[:, None] * (lam[:, 1:] - proj)
+    phi[att, 0] = Cn[att]
+    phi[att, 1:] = ut[att]
     return residual_of(phi)
 
 
-def step(oe: OracleEnv, x, v, obstacles, params, tol: float = 1e-12, lam_warm=None) -> StepResult:
-    """One time step of one environment (Alg. 1 body, every CSP solved to `tol`)."""
+def step(oe: OracleEnv, x, v, obstacles, params, tol: float = 1e-12, lam_warm=None, grippers=None,
+         held=None) -> StepResult:
+    """One time step of one environment (Alg. 1 body, every CSP solved to `tol`).  grippers / held:
+    kinematic grippers and the attachment sets they held after the previous step (see grasp_update)."""
     h = float(params.h)
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
-    contacts = detect(x, v, obstacles, params)
+    grippers = list(grippers) if grippers else []
+    held = grasp_update(x, grippers, held) if grippers else []
+    contacts = detect(x, v, obstacles, params, grippers, held)
     qt = predicted_state(x, v, h, params.gravity)
     q = qt.copy()
     c = contacts.count
@@ -701,16 +805,18 @@ def step(oe: OracleEnv, x, v, obstacles, params, tol: float = 1e-12, lam_warm=No
     impulse = h * np.einsum("jia,ja->ji", contacts.frame, lam) if c else np.zeros((0, 3))
     r = contact_residual(oe, x, q, contacts, lam, h)
     new_obs = [advance_obstacle(ob, h) for ob in obstacles]
-    return StepResult(xn, vn, contacts, lam, impulse, r, new_obs, info)
+    new_grip = [advance_gripper(gr, h) for gr in grippers]
+    return StepResult(xn, vn, contacts, lam, impulse, r, new_obs, info, new_grip, held)
 
 
-def rollout(oe: OracleEnv, x, v, obstacles, params, n_steps: int, tol: float = 1e-12):
+def rollout(oe: OracleEnv, x, v, obstacles, params, n_steps: int, tol: float = 1e-12, grippers=None):
     """n_steps consecutive steps; returns the list of StepResults."""
     out = []
+    held = None
     for _ in range(n_steps):
-        res = step(oe, x, v, obstacles, params, tol=tol)
+        res = step(oe, x, v, obstacles, params, tol=tol, grippers=grippers, held=held)
         out.append(res)
-        x, v, obstacles = res.x, res.v, res.obstacles
+        x, v, obstacles, grippers, held = res.x, res.v, res.obstacles, res.grippers, res.held
     return out
 
 
@@ -740,10 +846,11 @@ def rollout(oe: OracleEnv, x, v, obstacles, params, n_steps: int, tol: float = 1
 # the same vertex.  The result depends on the budget and is not the converged
 # step unless the iteration converges within it.
 
-def contact_blocks(Y, lam, d0, dob, s, mu):
+def contact_blocks(Y, lam, d0, dob, s, mu, attach=None):
     """Phi (c,3) and the generalized-Jacobian blocks of each contact at contact-frame displacement
     Y (c,3) and multipliers lam (c,3): K_j = dPhi_j/dY_j, E_j = dPhi_j/dlambda_j (3x3 each), with
-    the min-map normal and Alart-Curnier tangential parts at proximal scale s (c,)."""
+    the min-map normal and Alart-Curnier tangential parts at proximal scale s (c,); bilateral rows
+    (attach) have Phi = Y - d, K = I, E = 0."""
     c = Y.shape[0]
     phi = np.zeros((c, 3))
     Kb = np.zeros((c, 3, 3))
@@ -752,6 +859,11 @@ def contact_blocks(Y, lam, d0, dob, s, mu):
         cn = d0[j] + Y[j, 0]
         ut = Y[j, 1:] - dob[j]
         sj = s[j]
+        if attach is not None and attach[j]:
+            phi[j, 0] = cn
+            phi[j, 1:] = ut
+            Kb[j] = np.eye(3)
+            continue
         if cn <= sj * lam[j, 0]:              # normal active: Phi_n = C_n
             phi[j, 0] = cn
             Kb[j, 0, 0] = 1.0
@@ -800,14 +912,16 @@ def _contact_force_field(oe: OracleEnv, contacts: Contacts, lam):
 
 
 def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: int, tol: float = 0.0,
-                     lam_warm=None) -> StepResult:
+                     lam_warm=None, grippers=None, held=None) -> StepResult:
     """One time step in the fixed-budget lightweight mode described above (K = params.lg_iterations,
     N = newton_iterations).  info['newton'] counts the multiplier updates, info['lam_history'] holds
     the multipliers after each update."""
     h = float(params.h)
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
-    contacts = detect(x, v, obstacles, params)
+    grippers = list(grippers) if grippers else []
+    held = grasp_update(x, grippers, held) if grippers else []
+    contacts = detect(x, v, obstacles, params, grippers, held)
     qt = predicted_state(x, v, h, params.gravity)
     q = qt.copy()
     c = contacts.count
@@ -824,7 +938,7 @@ def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: 
             for it in range(int(newton_iterations)):
                 qg = oe.solve(b + h * h * _contact_force_field(oe, contacts, lam))
                 Y = np.einsum("jia,ji->ja", Fr, qg[contacts.vertex] - x[contacts.vertex])
-                phi, Kb, Eb = contact_blocks(Y, lam, contacts.d0, dob, s, oe.mu)
+                phi, Kb, Eb = contact_blocks(Y, lam, contacts.d0, dob, s, oe.mu, contacts.attach)
                 r = residual_of(phi)
                 if r <= tol:
                     break
@@ -843,4 +957,5 @@ def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: 
     impulse = h * np.einsum("jia,ja->ji", Fr, lam) if c else np.zeros((0, 3))
     r = contact_residual(oe, x, q, contacts, lam, h)
     new_obs = [advance_obstacle(ob, h) for ob in obstacles]
-    return StepResult(xn, vn, contacts, lam, impulse, r, new_obs, info)
+    new_grip = [advance_gripper(gr, h) for gr in grippers]
+    return StepResult(xn, vn, contacts, lam, impulse, r, new_obs, info, new_grip, held)

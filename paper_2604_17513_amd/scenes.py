@@ -74,6 +74,29 @@ class Obstacle:
 
 
 @dataclass
+class Gripper:
+    """Kinematic gripper (end effector) for bilateral attachment.
+
+    center is the pose at the start of the next step; it translates by h*lin_vel per step for
+    move_steps steps (negative: forever), then holds.  While `grasp` is on and the gripper holds
+    no vertex, the vertices within `radius` of its center are attached to it; turning `grasp`
+    off releases them.
+    """
+    center: np.ndarray
+    radius: float
+    grasp: bool = True
+    lin_vel: np.ndarray = field(default_factory=lambda: np.zeros(3))
+    move_steps: int = -1
+
+    def copy(self) -> "Gripper":
+        return Gripper(np.array(self.center, float), float(self.radius), bool(self.grasp),
+                       np.array(self.lin_vel, float), int(self.move_steps))
+
+
+MAX_GRIPPERS = 2
+
+
+@dataclass
 class Params:
     h: float = 1.0 / 60.0
     gravity: tuple = (0.0, -9.81, 0.0)
@@ -93,6 +116,7 @@ class Scene:
     params: Params
     name: str = ""
     meta: dict = field(default_factory=dict)
+    grippers: List[List[Gripper]] = field(default_factory=list)   # per env (may be empty)
 
     @property
     def n_envs(self) -> int:
