@@ -395,7 +395,10 @@ def detect(x, v, obstacles, params, grippers=None, held=None) -> Contacts:
     position x~, with the obstacle at its end-of-step pose.  Normal, tangents
     and gap d0 are taken at x.  A vertex held by gripper g adds an attachment
     row (obstacle index MAX_OBSTACLES + g) with target c_g(t+h) + o (the
-    gripper's end-of-step pose plus the offset taken at capture).
+    gripper's end-of-step pose plus the offset taken at capture), and no
+    obstacle rows: its position is prescribed by the attachment (a reading;
+    an obstacle row beside three equality rows on one vertex is redundant
+    when the target is clear of the obstacle and contradicts it otherwise).
     """
     h = params.h
     margin = params.contact_margin
@@ -414,8 +417,12 @@ def detect(x, v, obstacles, params, grippers=None, held=None) -> Contacts:
         d0s.append(d0)
         normals.append(nrm)
         dobs.append(dob)
+    # a vertex held by a gripper has its position prescribed by the attachment: no obstacle rows
+    held_v = set().union(*[set(hg) for hg in held]) if (grippers and held) else set()
     verts, obsi = [], []
     for vtx in range(n):
+        if vtx in held_v:
+            continue
         for o in range(len(obstacles)):
             if hits[o][vtx]:
                 verts.append(vtx)

@@ -123,3 +123,19 @@ def test_momentum_balance_with_attachments_and_ground(seed):
         assert r.residual <= 1e-10
         assert r.contacts.attach.sum() == 1 and (~r.contacts.attach).sum() > 0
         x, v, held, gr, obs = r.x, r.v, r.held, r.grippers, r.obstacles
+
+
+def test_held_vertex_takes_no_obstacle_rows():
+    """A corner held just above the ground lies within the contact margin but gets only its
+    attachment rows; its neighbours keep their ground contacts."""
+    sc = scenes.cloth_drop(n=6, side=0.1, height=0.001, seed=0)
+    p = sc.params
+    x = sc.x0[0] - np.array([0.0, 0.05, 0.0])
+    grip = scenes.Gripper(x[0].copy(), 1e-3)
+    held = O.grasp_update(x, [grip], None)
+    con = O.detect(x, np.zeros_like(x), [scenes.ground()], p, [grip], held)
+    rows0 = [(int(o), bool(a)) for vv, o, a in zip(con.vertex, con.obstacle, con.attach) if vv == 0]
+    assert rows0 == [(O.MAX_OBSTACLES, True)]
+    assert (con.vertex == 1).sum() == 1 and not con.attach[con.vertex == 1][0]
+    free = O.detect(x, np.zeros_like(x), [scenes.ground()], p)
+    assert free.count == con.count       # the ground row of vertex 0 became its attachment row
