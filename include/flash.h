@@ -56,7 +56,7 @@ enum { FLASH_TET = 0, FLASH_TRI = 1 };
 enum { FLASH_PLANE = 0, FLASH_BOX = 1, FLASH_CAPSULE = 2 };
 enum { FLASH_FP32 = 0, FLASH_FP64 = 1 };
 enum { FLASH_WS_ZERO = 0, FLASH_WS_PREV = 1, FLASH_WS_LEARNED = 2 };
-enum { FLASH_MAX_OBSTACLES = 4 };
+enum { FLASH_MAX_OBSTACLES = 4, FLASH_MAX_GRIPPERS = 2 };
 
 /* One environment: one deformable body.
  * Element maps and weights follow the as-rigid-as-possible reading of Eq. 3:
@@ -94,6 +94,26 @@ typedef struct {
   double size[3];
   double lin_vel[3];
 } flash_obstacle;
+
+/* Kinematic gripper for bilateral attachment (supplementary, bilateral constraint
+ * for cloth control: x_i - p_grip(t) = 0 for the grasped vertices, which join the
+ * set when the gripper is activated within a proximity threshold and leave it on
+ * release).  center: pose at the start of the next step; it translates by
+ * h * lin_vel during each of the next move_steps steps (negative: forever), then
+ * holds.  While grasp != 0 and the gripper holds no vertex, a step's detection
+ * attaches every vertex within `radius` of the center (FP64 squared distance,
+ * <= r^2) that no other gripper holds, lower gripper index first, and keeps its
+ * offset o = x - center; each held vertex then carries three equality rows
+ * q_i = center(t+h) + o (always active, no friction cone, unbounded multipliers)
+ * in the same contact solve, and no obstacle rows (its position is prescribed).
+ * grasp = 0 releases the set. */
+typedef struct {
+  double center[3];
+  double lin_vel[3];
+  double radius;                  /* capture threshold, m */
+  int32_t move_steps;
+  int32_t grasp;                  /* 1: grasp (capture when holding nothing), 0: release */
+} flash_gripper;
 
 typedef struct {
   double h;                       /* time step, s */
@@ -137,11 +157,27 @@ typedef struct {
                                      env, so that no env waits for the slowest env of the batch
                                      between phases; bitwise the same results.  Steps that record
                                      warm-start training pairs use the per-phase launches. */
+  int32_t contact_metric;         /* FLASH_METRIC_EXACT (0, default): every contact subproblem is solved
+                                     to inner_tol by semismooth Newton with the exact contact-space
+                                     operator (the fully implicit metric Z of Eq. 7).
+                                     FLASH_METRIC_LIGHTWEIGHT (1): the paper's fixed-budget mode (Alg. 1
+                                     with the inertia-only metric Z~ = J M^-1 J^T + E of Eq. 10): each
+                                     local-global iteration makes at most max_inner_iterations
+                                     multiplier updates (K W~ + E) delta = -Phi with W~ = h^2 H M^-1 H^T,
+                                     Phi at the exact positions, proximal scale h^2 / m_v, no line
+                                     search, stopping early at inner_tol; the step then ends wherever
+                                     that budget leaves it (flash_residual reports it, and
+                                     FLASH_ERR_NOT_CONVERGED when above ncp_tol).  The learned
+                                     prediction is not used in this mode. */
 } flash_params;
 
-/* One contact of the last step.  impulse = h F lambda in the world frame (N s);
- * lambda holds the contact-frame multipliers (n, t1, t2) in newtons.
- * mode: 0 separate (lambda = 0), 1 stick, 2 slip. */
+enum { FLASH_METRIC_EXACT = 0, FLASH_METRIC_LIGHTWEIGHT = 1 };
+
+/* One constraint row of the last step.  impulse = h F lambda in the world frame
+ * (N s); lambda holds the contact-frame multipliers (n, t1, t2) in newtons.
+ * mode: 0 separate (lambda = 0), 1 stick, 2 slip, 3 attachment (obstacle =
+ * FLASH_MAX_OBSTACLES + gripper index; frame = world axes, gap = the x
+ * component of x - target, lambda = world-frame force). */
 typedef struct {
   int32_t env, vertex, obstacle, mode;
   double normal[3];
@@ -219,6 +255,16 @@ flash_status flash_get_state_device(flash_batch *b, int32_t env, void *x_dev, vo
 flash_status flash_set_obstacles(flash_batch *b, int32_t env, const flash_obstacle *o, int32_t n);
 flash_status flash_get_obstacles(flash_batch *b, int32_t env, flash_obstacle *o, int32_t capacity,
                                  int32_t *n_out);
+
+/* Replaces the grippers of one env (env >= 0, n <= FLASH_MAX_GRIPPERS) or of
+ * every env (env = -1: g holds n_envs * n entries, env-major), as move and
+ * grasp commands for the next step (see flash_gripper).  Vertices already held
+ * stay held while their gripper keeps grasping; grippers beyond n release.
+ * Attachment rows count against max_contacts_per_env.  Copied; synchronises
+ * the batch's stream.  Errors: FLASH_ERR_INVALID_ARG for a null batch, env
+ * outside [-1, n_envs), n outside [0, FLASH_MAX_GRIPPERS], a null g with n > 0,
+ * a negative radius or a non-finite center. */
+flash_status flash_set_grippers(flash_batch *b, int32_t env, const flash_gripper *g, int32_t n);
 
 /* Enqueues n_steps steps of every env (Alg. 1 loop body): contact detection at
  * the obstacles' end-of-step poses, prediction, K local-global iterations each

@@ -136,9 +136,15 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
   __shared__ int sh_scan[kBlock / 64];
   __shared__ double sh_c[kMaxObs][3];
   __shared__ double sh_dob[kMaxObs][3];
+  __shared__ double sh_gc[kMaxGrip][3];    // gripper center at the start of the step (capture)
+  __shared__ double sh_gcn[kMaxGrip][3];   // and at its end (attachment targets)
+  __shared__ int sh_gcap[kMaxGrip];        // 1: grasping and holding nothing: captures this step
+  __shared__ int sh_gon[kMaxGrip];         // grasp on
+  __shared__ int sh_gheld[kMaxGrip];
   const int e = blockIdx.x;
   const int v0 = B.voff[e], v1 = B.voff[e + 1];
   const int nob = B.nobs[e];
+  const int ng = B.ngrip ? B.ngrip[e] : 0;
   const double h = B.h, hh = B.h * B.h;
   const int cap = B.cap;
   if (threadIdx.x < nob) {
@@ -148,6 +154,20 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
       double dob = moving ? h * B.obs_vel[3 * o + k] : 0.0;
       sh_dob[threadIdx.x][k] = dob;
       sh_c[threadIdx.x][k] = B.obs_c[3 * o + k] + dob;
+    }
+  }
+  if (threadIdx.x < kMaxGrip) {
+    const int g = threadIdx.x, q = e * kMaxGrip + g;
+    const bool on = g < ng && B.grip_grasp[q] != 0;
+    sh_gon[g] = on ? 1 : 0;
+    sh_gcap[g] = (on && B.grip_held[q] == 0) ? 1 : 0;
+    sh_gheld[g] = 0;
+    if (g < ng) {
+      const bool moving = B.grip_move[q] != 0;
+      for (int k = 0; k < 3; ++k) {
+        sh_gc[g][k] = B.grip_c[3 * q + k];
+        sh_gcn[g][k] = B.grip_c[3 * q + k] + (moving ? h * B.grip_vel[3 * q + k] : 0.0);
+      }
     }
   }
   if (threadIdx.x == 0) {
@@ -180,13 +200,68 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
                    obstacle_pred(kind, sh_c[o], R, sz, xt, B.margin);
         if (hit) mask |= 1u << o;
       }
+      if (ng > 0) {
+        // attachment sets: release when the grasp is off; a grasping gripper that holds nothing
+        // takes the free vertices within its radius (lowest gripper first), with their offsets
+        int ag = B.att_g[i];
+        if (ag >= 0 && !sh_gon[ag]) ag = -1;
+        for (int g = 0; g < ng && ag < 0; ++g) {
+          if (!sh_gcap[g]) continue;
+          const double d0 = xd[0] - sh_gc[g][0], d1 = xd[1] - sh_gc[g][1], d2 = xd[2] - sh_gc[g][2];
+          const double r = B.grip_r[e * kMaxGrip + g];
+          if ((d0 * d0 + d1 * d1) + d2 * d2 <= r * r) {
+            ag = g;
+            B.att_off[3 * (size_t)i] = d0;
+            B.att_off[3 * (size_t)i + 1] = d1;
+            B.att_off[3 * (size_t)i + 2] = d2;
+          }
+        }
+        B.att_g[i] = ag;
+        if (ag >= 0) {
+          // a held vertex's position is prescribed by its attachment: no obstacle rows
+          mask = 1u << (kMaxObs + ag);
+          atomicAdd(&sh_gheld[ag], 1);
+        }
+      }
     }
     int total;
     int off = block_excl_scan(__popc(mask), sh_scan, &total);
     if (mask) {
       int slot = count + off;
-      for (int o = 0; o < nob; ++o) {
+      for (int o = 0; o < kCacheSlots; ++o) {
         if (!(mask & (1u << o))) continue;
+        if (slot < cap && o >= kMaxObs) {
+          // attachment row of gripper g: frame I, target = end-of-step center + offset, stored as
+          // d0 = -(target - x)_0 and dob = (target - x)_{1,2} so that Phi = Y - (target - x)
+          const int g = o - kMaxObs;
+          const int j = e * cap + slot;
+          double d[3];
+          for (int k = 0; k < 3; ++k) d[k] = (sh_gcn[g][k] + B.att_off[3 * (size_t)i + k]) - xd[k];
+          B.cvert[j] = i - v0;
+          B.cobs[j] = o;
+          T* F = B.cframe + 9 * (size_t)j;
+          for (int k = 0; k < 9; ++k) F[k] = (k % 4 == 0) ? T(1) : T(0);
+          if (sizeof(T) == 4 && B.cframe64) {
+            double* F64 = B.cframe64 + 9 * (size_t)j;
+            for (int k = 0; k < 9; ++k) F64[k] = (k % 4 == 0) ? 1.0 : 0.0;
+          }
+          B.cd0[j] = (T)(-d[0]);
+          B.cd0d[j] = -d[0];
+          B.cdob[2 * j] = (T)d[1];
+          B.cdob[2 * j + 1] = (T)d[2];
+          B.cs[j] = (T)(hh / (double)B.mass[i]);
+          const int ci = i * kCacheSlots + o;
+          int fresh = 1;
+          double l[3] = {0.0, 0.0, 0.0};
+          if (B.warm_start != 0 && B.cache_stamp[ci] == cur - 1) {
+            for (int k = 0; k < 3; ++k) l[k] = (double)B.cache_f[3 * ci + k];
+            fresh = 0;
+          }
+          for (int k = 0; k < 3; ++k) B.clam[3 * j + k] = l[k];
+          B.cnew[j] = fresh;
+          ++slot;
+          continue;
+        }
         if (slot < cap) {
           int oo = e * kMaxObs + o;
           const double* R = B.obs_R + 9 * oo;
@@ -210,7 +285,7 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
           B.cdob[2 * j + 1] = (T)((t2[0] * dob[0] + t2[1] * dob[1]) + t2[2] * dob[2]);
           B.cs[j] = (T)(hh / (double)B.mass[i]);
           // warm start from the previous step's world-frame force at this (vertex, obstacle)
-          const int ci = i * kMaxObs + o;
+          const int ci = i * kCacheSlots + o;
           T l0 = 0, l1 = 0, l2 = 0;
           int fresh = 1;
           if (B.warm_start != 0 && B.cache_stamp[ci] == cur - 1) {
@@ -237,6 +312,8 @@ __global__ void __launch_bounds__(kBlock) k_detect(DevBatch<T> B, const T* mu_en
     }
     count += total;
   }
+  __syncthreads();
+  if (threadIdx.x < ng) B.grip_held[e * kMaxGrip + threadIdx.x] = sh_gheld[threadIdx.x];
   if (threadIdx.x == 0) {
     B.ccount[e] = count < cap ? count : cap;
     B.iters[e] = 0;
@@ -283,19 +360,20 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     double s = h * h / (double)B.mass[vi];
     double ln = B.clam[3 * j], l1 = B.clam[3 * j + 1], l2 = B.clam[3 * j + 2];
     double cn = B.cd0d[j] + Y[0];
-    double pn = fmin(cn, s * ln);
+    const bool att = B.cobs[j] >= kMaxObs;      // attachment: Phi = Y - d, no cone
+    double pn = att ? cn : fmin(cn, s * ln);
     double ut1 = Y[1] - (double)B.cdob[2 * j], ut2 = Y[2] - (double)B.cdob[2 * j + 1];
     double y1 = l1 - ut1 / s, y2 = l2 - ut2 / s;
     double rho = mu * fmax(ln, 0.0);
     double ny = sqrt(y1 * y1 + y2 * y2);
     double p1 = y1, p2 = y2;
-    if (ny > rho) { double f = ny > 0.0 ? rho / ny : 0.0; p1 = f * y1; p2 = f * y2; }
+    if (!att && ny > rho) { double f = ny > 0.0 ? rho / ny : 0.0; p1 = f * y1; p2 = f * y2; }
     double t1 = s * (l1 - p1), t2 = s * (l2 - p2);
     double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
     if (!(rj == rj)) rj = INFINITY;
     r = fmax(r, rj);
     // cache the world force for the next step's warm start
-    const int ci = vi * kMaxObs + B.cobs[j];
+    const int ci = vi * kCacheSlots + B.cobs[j];
     T f0 = B.cforce[3 * j], f1 = B.cforce[3 * j + 1], f2 = B.cforce[3 * j + 2];
     B.cache_f[3 * ci] = f0; B.cache_f[3 * ci + 1] = f1; B.cache_f[3 * ci + 2] = f2;
     B.cache_stamp[ci] = cur;
@@ -323,7 +401,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
   }
   if (bad) atomicOr(&B.flags[e], 1);
   __syncthreads();
-  // obstacle track: pose at the start of the next step
+  // obstacle and gripper tracks: poses at the start of the next step
   const int nob = B.nobs[e];
   if (threadIdx.x < nob) {
     int o = e * kMaxObs + threadIdx.x;
@@ -331,6 +409,15 @@ __global__ void __launch_bounds__(kBlock) k_finalize(DevBatch<T> B, const T* mu_
     if (mv != 0) {
       for (int k = 0; k < 3; ++k) B.obs_c[3 * o + k] = B.obs_c[3 * o + k] + h * B.obs_vel[3 * o + k];
       if (mv > 0) B.obs_move[o] = mv - 1;
+    }
+  }
+  const int ng = B.ngrip ? B.ngrip[e] : 0;
+  if (threadIdx.x >= 64 && threadIdx.x < 64 + ng) {
+    const int q = e * kMaxGrip + threadIdx.x - 64;
+    const int mv = B.grip_move[q];
+    if (mv != 0) {
+      for (int k = 0; k < 3; ++k) B.grip_c[3 * q + k] = B.grip_c[3 * q + k] + h * B.grip_vel[3 * q + k];
+      if (mv > 0) B.grip_move[q] = mv - 1;
     }
   }
 }

@@ -13,6 +13,8 @@
 namespace flash {
 
 constexpr int kMaxObs = 4;
+constexpr int kMaxGrip = 2;                       // grippers (bilateral attachment) per env
+constexpr int kCacheSlots = kMaxObs + kMaxGrip;   // constraint rows per vertex: warm-start cache entries
 constexpr int kBlock = 256;
 constexpr int kBK = 16;         // panel width of the blocked factorisations in the contact solve
 constexpr int kWsMaxFail = 3;   // learned-start failures after which an env keeps the plain start
@@ -39,6 +41,7 @@ struct DevBatch {
   double max_force;
   int warm_start;             // FLASH_WS_*
   int reuse;                  // reuse capacitance factorisations across Newton iterations
+  int lite;                   // 1: fixed-budget lightweight contact update (inertia-only metric)
 
   const int* voff;            // [n_envs+1]
   const int* toff;            // [n_envs+1]
@@ -78,10 +81,21 @@ struct DevBatch {
   const double* obs_size;     // [*3]
   const double* obs_vel;      // [*3]
 
+  // grippers [n_envs * kMaxGrip] and the vertices they hold (bilateral attachment)
+  int* ngrip;                 // [n_envs]
+  int* grip_grasp;            // grasp on (1) / off (0)
+  int* grip_move;             // steps left to move (negative: forever)
+  int* grip_held;             // vertices held after the last detection
+  double* grip_c;             // [*3] center at the start of the next step
+  const double* grip_vel;     // [*3]
+  const double* grip_r;       // capture radius
+  int* att_g;                 // [NV] gripper holding the vertex, -1: none
+  double* att_off;            // [3 per vertex] offset from the gripper center taken at capture
+
   // contacts [n_envs * cap]
   int* ccount;                // [n_envs]
   int* cvert;                 // local vertex index
-  int* cobs;
+  int* cobs;                  // obstacle index; kMaxObs + g for the attachment row of gripper g
   T* cframe;                  // [9 per contact] columns n, t1, t2: frame[3*a + k] = column a, comp k
   double* cframe64;           // the same frames in FP64 (FP32 batches with an FP64 contact solve; else
                               // nullptr, or cframe itself in FP64 batches)
@@ -107,7 +121,7 @@ struct DevBatch {
   int* nbase;                 // [n_envs]
   int* lust;                  // [4 per env] stored capacitance factorisation: valid, rows, base version x2
 
-  // warm-start cache [NV * kMaxObs]
+  // warm-start cache [NV * kCacheSlots]
   T* cache_f;                 // [3 per entry] world force
   int* cache_stamp;
   int* stamp;                 // [1] step counter (device side)

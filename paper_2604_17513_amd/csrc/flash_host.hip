@@ -522,6 +522,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.max_force = b->p.max_force;
   B.warm_start = b->p.warm_start;
   B.reuse = 1;   // reuse of a capacitance factorisation while the contact classes hold
+  B.lite = b->p.contact_metric == FLASH_METRIC_LIGHTWEIGHT ? 1 : 0;
   const int NV = b->NV, NT = b->NT;
   const size_t cap = (size_t)B.cap;
 
@@ -667,6 +668,22 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.obs_R = dalloc<double>(9 * no, own);
   B.obs_size = dalloc<double>(3 * no, own);
   B.obs_vel = dalloc<double>(3 * no, own);
+  // grippers and attachment sets (none until flash_set_grippers)
+  const size_t ngs = (size_t)ne * kMaxGrip;
+  B.ngrip = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.ngrip, 0, ne * sizeof(int)));
+  B.grip_grasp = dalloc<int>(ngs, own);
+  B.grip_move = dalloc<int>(ngs, own);
+  B.grip_held = dalloc<int>(ngs, own);
+  HIPCHK(hipMemset(B.grip_grasp, 0, ngs * sizeof(int)));
+  HIPCHK(hipMemset(B.grip_move, 0, ngs * sizeof(int)));
+  HIPCHK(hipMemset(B.grip_held, 0, ngs * sizeof(int)));
+  B.grip_c = dalloc<double>(3 * ngs, own);
+  B.grip_vel = dalloc<double>(3 * ngs, own);
+  B.grip_r = dalloc<double>(ngs, own);
+  B.att_g = dalloc<int>(NV, own);
+  HIPCHK(hipMemset(B.att_g, 0xFF, (size_t)NV * sizeof(int)));
+  B.att_off = dalloc<double>(3 * (size_t)NV, own);
   // contacts
   B.ccount = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.ccount, 0, ne * sizeof(int)));
@@ -698,9 +715,9 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   HIPCHK(hipMemset(B.lust, 0, 4 * ne * sizeof(int)));
   B.nbase = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.nbase, 0, ne * sizeof(int)));
-  B.cache_f = dalloc<T>(3 * (size_t)NV * kMaxObs, own);
-  B.cache_stamp = dalloc<int>((size_t)NV * kMaxObs, own);
-  HIPCHK(hipMemset(B.cache_stamp, 0xFF, (size_t)NV * kMaxObs * sizeof(int)));
+  B.cache_f = dalloc<T>(3 * (size_t)NV * kCacheSlots, own);
+  B.cache_stamp = dalloc<int>((size_t)NV * kCacheSlots, own);
+  HIPCHK(hipMemset(B.cache_stamp, 0xFF, (size_t)NV * kCacheSlots * sizeof(int)));
   B.stamp = dalloc<int>(1, own);
   {
     int one = 1;
@@ -763,7 +780,8 @@ void set_state_t(flash_batch* b, int env, const double* x, const double* v) {
       HIPCHK(hipStreamSynchronize(b->stream));
     }
   }
-  HIPCHK(hipMemsetAsync(B.cache_stamp + (size_t)vo * kMaxObs, 0xFF, (size_t)n * kMaxObs * sizeof(int), b->stream));
+  HIPCHK(hipMemsetAsync(B.cache_stamp + (size_t)vo * kCacheSlots, 0xFF, (size_t)n * kCacheSlots * sizeof(int),
+                        b->stream));
   HIPCHK(hipMemsetAsync(B.ws_state + e0, 0, (size_t)(e1 - e0) * sizeof(int), b->stream));
   HIPCHK(hipStreamSynchronize(b->stream));
 }
@@ -827,7 +845,8 @@ int contacts_t(flash_batch* b, int env, flash_contact* out, int capacity, int* n
       }
       r.gap = d0[j];
       const double ln = r.lambda[0], lt = std::sqrt(r.lambda[1] * r.lambda[1] + r.lambda[2] * r.lambda[2]);
-      r.mode = ln <= 0 ? 0 : (lt < b->mu[e] * ln * (1.0 - 1e-6) ? 1 : 2);
+      if (co[j] >= kMaxObs) r.mode = 3;   // attachment row (bilateral)
+      else r.mode = ln <= 0 ? 0 : (lt < b->mu[e] * ln * (1.0 - 1e-6) ? 1 : 2);
     }
   }
   return 0;
@@ -889,6 +908,38 @@ void set_obstacles_t(flash_batch* b, int env, const flash_obstacle* o, int n) {
 }
 
 template <class T>
+void set_grippers_t(flash_batch* b, int env, const flash_gripper* gp, int n) {
+  DevBatch<T>& B = dev<T>(b);
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const int e0 = env < 0 ? 0 : env, e1 = env < 0 ? b->n_envs : env + 1;
+  const int ne = e1 - e0;
+  const size_t q0 = (size_t)e0 * kMaxGrip, nq = (size_t)ne * kMaxGrip;
+  std::vector<int> grasp(nq, 0), mv(nq, 0), held(nq, 0), cnt(ne, n);
+  std::vector<double> c(3 * nq, 0.0), vel(3 * nq, 0.0), r(nq, 0.0);
+  HIPCHK(hipMemcpy(held.data(), B.grip_held + q0, nq * sizeof(int), hipMemcpyDeviceToHost));
+  for (int e = 0; e < ne; ++e)
+    for (int g = 0; g < n; ++g) {
+      const flash_gripper& G = gp[(size_t)e * n + g];
+      const size_t q = (size_t)e * kMaxGrip + g;
+      grasp[q] = G.grasp ? 1 : 0;
+      mv[q] = G.move_steps;
+      r[q] = G.radius;
+      for (int k = 0; k < 3; ++k) { c[3 * q + k] = G.center[k]; vel[3 * q + k] = G.lin_vel[k]; }
+    }
+  // grippers beyond n hold nothing: their vertices are released at the next step
+  for (int e = 0; e < ne; ++e)
+    for (int g = n; g < kMaxGrip; ++g) held[(size_t)e * kMaxGrip + g] = 0;
+  HIPCHK(hipMemcpy(B.ngrip + e0, cnt.data(), ne * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.grip_grasp + q0, grasp.data(), nq * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.grip_move + q0, mv.data(), nq * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.grip_held + q0, held.data(), nq * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(B.grip_c + 3 * q0, c.data(), 3 * nq * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(const_cast<double*>(B.grip_vel) + 3 * q0, vel.data(), 3 * nq * sizeof(double),
+                   hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(const_cast<double*>(B.grip_r) + q0, r.data(), nq * sizeof(double), hipMemcpyHostToDevice));
+}
+
+template <class T>
 void get_obstacles_t(flash_batch* b, int env, flash_obstacle* o, int n) {
   DevBatch<T>& B = dev<T>(b);
   HIPCHK(hipStreamSynchronize(b->stream));
@@ -926,6 +977,8 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     return fail(FLASH_ERR_INVALID_ARG, "invalid solver parameters");
   if (p->precision != FLASH_FP32 && p->precision != FLASH_FP64)
     return fail(FLASH_ERR_INVALID_ARG, "precision must be FLASH_FP32 or FLASH_FP64");
+  if (p->contact_metric != FLASH_METRIC_EXACT && p->contact_metric != FLASH_METRIC_LIGHTWEIGHT)
+    return fail(FLASH_ERR_INVALID_ARG, "contact_metric must be FLASH_METRIC_EXACT or FLASH_METRIC_LIGHTWEIGHT");
   {
     // one workgroup holds an env's contact data in LDS: the capacity must fit one CU's LDS
     const int cap = csp_capacity(p->max_contacts_per_env);
@@ -1160,6 +1213,23 @@ flash_status flash_set_obstacles(flash_batch* b, int32_t env, const flash_obstac
     });
   }
   GUARD(if (b->fp64) set_obstacles_t<double>(b, env, o, n); else set_obstacles_t<float>(b, env, o, n));
+  return FLASH_OK;
+}
+
+flash_status flash_set_grippers(flash_batch* b, int32_t env, const flash_gripper* g, int32_t n) {
+  if (!b || bad_env(b, env) || n < 0 || n > FLASH_MAX_GRIPPERS || (n > 0 && !g))
+    return fail(FLASH_ERR_INVALID_ARG, "invalid batch, env or gripper count");
+  const int ne = env < 0 ? b->n_envs : 1;
+  for (int q = 0; q < ne * n; ++q)
+    if (!(g[q].radius >= 0) || !std::isfinite(g[q].center[0] + g[q].center[1] + g[q].center[2]))
+      return fail(FLASH_ERR_INVALID_ARG, "bad gripper radius or center");
+  if (!b->groups.empty()) {
+    if (env >= 0) { const int gi = group_of(b, env); return flash_set_grippers(b->groups[gi], env - b->gofs[gi], g, n); }
+    return each_group(b, [&](int gi, flash_batch* c) {
+      return flash_set_grippers(c, -1, g ? g + (size_t)b->gofs[gi] * n : nullptr, n);
+    });
+  }
+  GUARD(if (b->fp64) set_grippers_t<double>(b, env, g, n); else set_grippers_t<float>(b, env, g, n));
   return FLASH_OK;
 }
 

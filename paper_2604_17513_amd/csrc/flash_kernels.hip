@@ -1200,11 +1200,232 @@ __device__ __forceinline__ void contact_KE(int cls, T sp, T mu, T kap, T y0, T y
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fixed-budget lightweight contact update (Alg. 1 with the inertia-only metric of Eq. 10).
+// Per local-global iteration, up to max_newton updates lambda <- lambda + delta with
+// (K W~ + E) delta = -Phi, W~ = h^2 H M^-1 H^T (blocks (h^2 / m_v) F_j^T F_k between contacts of
+// one vertex), Phi and (K, E) at the exact contact displacement Y = y_free + W lambda, proximal
+// scale s = h^2 / m_v, no line search; stops early at inner_tol.  For a vertex with one contact
+// W~ = s I and the system is [s 0 0; -s mu y^ (slip only), s I], solved in closed form; vertices
+// touching several obstacles solve their 3m x 3m block by Gaussian elimination.
+// ---------------------------------------------------------------------------
+
+// Phi and the generalized-Jacobian blocks of one contact (proximal scale sp): K = dPhi/dY,
+// E = dPhi/dlambda.  Returns the slip direction in yh (zero unless slipping).
+template <class CT>
+__device__ __forceinline__ void lite_contact(CT sp, CT mu, CT d0, CT dob1, CT dob2, const CT* Yj, const double* lj,
+                                             bool att, CT phi[3], CT K[3][3], CT E[3][3]) {
+  const CT l0 = (CT)lj[0], l1 = (CT)lj[1], l2 = (CT)lj[2];
+  const CT cn = d0 + Yj[0];
+  const CT ut1 = Yj[1] - dob1, ut2 = Yj[2] - dob2;
+  if (att) {   // attachment row: Phi = Y - d, K = I, E = 0
+    phi[0] = cn; phi[1] = ut1; phi[2] = ut2;
+    contact_KE(3, sp, mu, CT(0), CT(0), CT(0), K, E);
+    return;
+  }
+  int cls = (cn <= sp * l0) ? 1 : 0;
+  phi[0] = fmin(cn, sp * l0);
+  const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
+  const CT rho = mu * fmax(l0, CT(0));
+  const CT ny = sqrt(y1 * y1 + y2 * y2);
+  CT kap = 0, yh0 = 0, yh1 = 0, p1 = 0, p2 = 0;
+  if (rho > CT(0)) {
+    if (ny <= rho) { cls |= 2; p1 = y1; p2 = y2; }
+    else { cls |= 4; kap = rho / ny; yh0 = y1 / ny; yh1 = y2 / ny; p1 = rho * yh0; p2 = rho * yh1; }
+  }
+  phi[1] = sp * (l1 - p1);
+  phi[2] = sp * (l2 - p2);
+  contact_KE(cls, sp, mu, kap, yh0, yh1, K, E);
+}
+
+// delta for the m contacts (m >= 2) of one vertex starting at contact j
+template <class CT>
+__device__ __noinline__ void lite_group_solve(int m, CT sp, CT mu, const CT* Fr, const CT* d0, const CT* dob,
+                                              const CT* Y, const double* lam, const int* cobs, CT* dl) {
+  double Z[3 * kCacheSlots][3 * kCacheSlots + 1];
+  CT Kq[kCacheSlots][3][3], Eq[kCacheSlots][3][3], ph[kCacheSlots][3];
+  for (int q = 0; q < m; ++q)
+    lite_contact(sp, mu, d0[q], dob[2 * q], dob[2 * q + 1], Y + 3 * q, lam + 3 * q, cobs[q] >= kMaxObs, ph[q], Kq[q],
+                 Eq[q]);
+  const int n = 3 * m;
+  for (int q = 0; q < m; ++q)
+    for (int a = 0; a < 3; ++a) {
+      const int row = 3 * q + a;
+      for (int r = 0; r < m; ++r)
+        for (int b = 0; b < 3; ++b) {
+          // (K_q W~_qr)[a][b] with W~_qr = sp F_q^T F_r
+          double acc = 0.0;
+          for (int cc = 0; cc < 3; ++cc) {
+            double g = 0.0;
+            for (int k = 0; k < 3; ++k) g += (double)Fr[9 * q + 3 * cc + k] * (double)Fr[9 * r + 3 * b + k];
+            acc += (double)Kq[q][a][cc] * (double)sp * g;
+          }
+          if (q == r) acc += (double)Eq[q][a][b];
+          Z[row][3 * r + b] = acc;
+        }
+      Z[row][n] = -(double)ph[q][a];
+    }
+  for (int k = 0; k < n; ++k) {
+    int pv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (fabs(Z[i][k]) > fabs(Z[pv][k])) pv = i;
+    if (pv != k)
+      for (int t = k; t <= n; ++t) { const double tmp = Z[k][t]; Z[k][t] = Z[pv][t]; Z[pv][t] = tmp; }
+    const double piv = Z[k][k];
+    for (int i = k + 1; i < n; ++i) {
+      const double f = piv != 0.0 ? Z[i][k] / piv : 0.0;
+      for (int t = k; t <= n; ++t) Z[i][t] -= f * Z[k][t];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double acc = Z[k][n];
+    for (int t = k + 1; t < n; ++t) acc -= Z[k][t] * (double)dl[t];
+    dl[k] = Z[k][k] != 0.0 ? (CT)(acc / Z[k][k]) : CT(0);
+  }
+}
+
+template <class T, class CT>
+__device__ __forceinline__ void csp_env_lite(const DevBatch<T>& B, const T* mu_env, int first_lg, int e,
+                                             unsigned char* smem_raw, bool own_cost) {
+  const unsigned long long t_start = (own_cost && B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
+  const int c = B.ccount[e];
+  if (c == 0) {
+    if (first_lg && B.ws_state && threadIdx.x == 0) B.ws_state[e] &= ~5;
+    return;
+  }
+  const int cap = B.cap;
+  double* lam = reinterpret_cast<double*>(smem_raw);
+  CT* Y = reinterpret_cast<CT*>(lam + 3 * cap);
+  CT* fw = Y + 3 * cap;
+  CT* dl = fw + 3 * cap;
+  CT* d0s = dl + 3 * cap;
+  CT* dobs = d0s + cap;
+  __shared__ double sh_red[kBlock / 64];
+  const size_t cb = (size_t)e * cap;
+  const CT* Gc = static_cast<const CT*>(B.Gc) + cb * cap;
+  const int v0 = B.voff[e];
+  const CT hh = (CT)(B.h * B.h);
+  const CT mu = mu_env[e];
+  const double dmaxf = B.max_force;
+  const CT* Fr;
+  if constexpr (std::is_same<CT, T>::value) Fr = B.cframe + 9 * cb;
+  else Fr = B.cframe64 + 9 * cb;
+  CT* yfg = static_cast<CT*>(B.cyf) + 3 * cb;
+  const int* cv = B.cvert + cb;
+  const int* cobs = B.cobs + cb;
+  const int tid = threadIdx.x;
+  for (int j = tid; j < c; j += kBlock) {
+    const CT* F = Fr + 9 * j;
+    const int vi = v0 + cv[j];
+    const CT zw0 = B.z[vi], zw1 = B.z[B.NV + vi], zw2 = B.z[2 * B.NV + vi];
+    for (int a = 0; a < 3; ++a) {
+      yfg[3 * j + a] = F[3 * a] * zw0 + F[3 * a + 1] * zw1 + F[3 * a + 2] * zw2;
+      lam[3 * j + a] = B.clam[3 * (cb + j) + a];
+    }
+    d0s[j] = B.cd0[cb + j];
+    dobs[2 * j] = B.cdob[2 * (cb + j)];
+    dobs[2 * j + 1] = B.cdob[2 * (cb + j) + 1];
+  }
+  __syncthreads();
+  // Y = y_free + W lambda with W = h^2 F^T Gbar[contacts] F (Gc symmetric: coalesced column reads)
+  auto update_Y = [&]() {
+    for (int j = tid; j < c; j += kBlock) {
+      const CT* F = Fr + 9 * j;
+      const CT l0 = (CT)lam[3 * j], l1 = (CT)lam[3 * j + 1], l2 = (CT)lam[3 * j + 2];
+      for (int k = 0; k < 3; ++k) fw[3 * j + k] = F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2;
+    }
+    __syncthreads();
+    for (int j = tid; j < c; j += kBlock) {
+      CT g0 = 0, g1 = 0, g2 = 0;
+      batched_terms<16>(0, c, [&](int k) { return Gc[(size_t)k * c + j]; }, [&](int k, CT g) {
+        g0 += g * fw[3 * k]; g1 += g * fw[3 * k + 1]; g2 += g * fw[3 * k + 2];
+      });
+      const CT* F = Fr + 9 * j;
+      for (int a = 0; a < 3; ++a)
+        Y[3 * j + a] = yfg[3 * j + a] + hh * (F[3 * a] * g0 + F[3 * a + 1] * g1 + F[3 * a + 2] * g2);
+    }
+    __syncthreads();
+  };
+  update_Y();
+  const int maxit = B.max_newton;
+  int it = 0;
+  double r = 0.0;
+  for (;; ++it) {
+    // residual at the residual scale s = h^2 / m_v (FP64), the same scale as the update's
+    double rloc = 0.0;
+    for (int j = tid; j < c; j += kBlock) {
+      const double s = (double)B.cs[cb + j];
+      const double ld0 = lam[3 * j], ld1 = lam[3 * j + 1], ld2 = lam[3 * j + 2];
+      const double cnd = B.cd0d[cb + j] + (double)Y[3 * j];
+      const double ut1 = (double)Y[3 * j + 1] - (double)dobs[2 * j], ut2 = (double)Y[3 * j + 2] - (double)dobs[2 * j + 1];
+      const bool att = cobs[j] >= kMaxObs;
+      const double pn = att ? cnd : fmin(cnd, s * ld0);
+      const double z1 = ld1 - ut1 / s, z2 = ld2 - ut2 / s;
+      const double nz = sqrt(z1 * z1 + z2 * z2);
+      const double rh = (double)mu * fmax(ld0, 0.0);
+      double q1 = z1, q2 = z2;
+      if (!att && nz > rh) { const double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
+      const double t1 = s * (ld1 - q1), t2 = s * (ld2 - q2);
+      double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
+      if (!(rj == rj)) rj = INFINITY;
+      rloc = fmax(rloc, rj);
+    }
+    r = block_max(rloc, sh_red);
+    if (r <= B.tol || it >= maxit) break;
+    // one update per vertex group (contacts are listed by vertex, so a group is contiguous)
+    for (int j = tid; j < c; j += kBlock) {
+      if (j > 0 && cv[j - 1] == cv[j]) continue;
+      int m = 1;
+      while (j + m < c && cv[j + m] == cv[j] && m < kCacheSlots) ++m;
+      const CT sp = (CT)B.cs[cb + j];
+      if (m == 1) {
+        CT ph[3], K[3][3], E[3][3];
+        lite_contact(sp, mu, d0s[j], dobs[2 * j], dobs[2 * j + 1], Y + 3 * j, lam + 3 * j, cobs[j] >= kMaxObs, ph, K,
+                     E);
+        // Z = sp K + E = [sp 0 0; E_tn sp I]
+        const CT dn = -ph[0] / sp;
+        dl[3 * j] = dn;
+        dl[3 * j + 1] = (-ph[1] - E[1][0] * dn) / sp;
+        dl[3 * j + 2] = (-ph[2] - E[2][0] * dn) / sp;
+      } else {
+        lite_group_solve<CT>(m, sp, mu, Fr + 9 * j, d0s + j, dobs + 2 * j, Y + 3 * j, lam + 3 * j, cobs + j,
+                             dl + 3 * j);
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < 3 * c; q += kBlock) lam[q] = fmin(fmax(lam[q] + (double)dl[q], -dmaxf), dmaxf);
+    __syncthreads();
+    update_Y();
+  }
+  for (int j = tid; j < c; j += kBlock) {
+    const CT* F = Fr + 9 * j;
+    const CT l0 = (CT)lam[3 * j], l1 = (CT)lam[3 * j + 1], l2 = (CT)lam[3 * j + 2];
+    for (int a = 0; a < 3; ++a) B.clam[3 * (cb + j) + a] = lam[3 * j + a];
+    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
+  }
+  if (tid == 0) {
+    B.iters[e] += it;
+    if (B.phase) {
+      unsigned long long* cnt = B.phase + (size_t)B.n_envs * 8 + 8 * e;
+      cnt[3] += (r > B.tol) ? 1 : 0;
+      cnt[6] += it;
+      cnt[7] += 1;
+    }
+    if (r > B.tol) B.flags[e] |= 2; else B.flags[e] &= ~2;
+    if (own_cost && B.cost) B.cost[e] += wall_clock64() - t_start;
+    if (first_lg && B.ws_state) B.ws_state[e] &= ~5;
+  }
+}
+
 // The contact subproblem of env e by the whole workgroup; smem_raw: csp_smem_bytes<CT>
 // of LDS.  own_cost: add the solve's wall-clock time to the env's scheduling cost.
-template <class T, class CT>
+template <class T, class CT, bool LITE = false>
 __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, int first_lg, int e, unsigned char* smem_raw,
                         bool own_cost) {
+  if constexpr (LITE) {
+    csp_env_lite<T, CT>(B, mu_env, first_lg, e, smem_raw, own_cost);
+    return;
+  }
   const unsigned long long t_start = (own_cost && B.cost && threadIdx.x == 0) ? wall_clock64() : 0ull;
   const int c = B.ccount[e];
   if (c == 0) {
@@ -1325,7 +1546,8 @@ __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, i
       for (int j = tid; j < c; j += kBlock) {
         if (B.cnew[cb + j]) {
           const CT cn = B.cd0[cb + j] + S.Y[3 * j];
-          S.lam[3 * j] = cn < CT(0) ? (double)(-cn / S.sp[j]) : 0.0;
+          const bool att = B.cobs[cb + j] >= kMaxObs;   // attachment rows start from zero
+          S.lam[3 * j] = (cn < CT(0) && !att) ? (double)(-cn / S.sp[j]) : 0.0;
           S.lam[3 * j + 1] = 0;
           S.lam[3 * j + 2] = 0;
           any = 1;
@@ -1357,12 +1579,14 @@ __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, i
           const CT l0 = (CT)L[3 * j], l1 = (CT)L[3 * j + 1], l2 = (CT)L[3 * j + 2];
           const CT cn = B.cd0[cb + j] + Yv[3 * j];
           const CT ut1 = Yv[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = Yv[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-          const CT phn = fmin(cn, sp * l0);
+          const bool att = B.cobs[cb + j] >= kMaxObs;
+          const CT phn = att ? cn : fmin(cn, sp * l0);
           const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
           const CT rho = mu * fmax(l0, CT(0));
           const CT ny = sqrt(y1 * y1 + y2 * y2);
           CT p1 = 0, p2 = 0;
-          if (rho > CT(0)) {
+          if (att) { p1 = y1; p2 = y2; }
+          else if (rho > CT(0)) {
             if (ny <= rho) { p1 = y1; p2 = y2; }
             else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
           }
@@ -1403,6 +1627,11 @@ __device__ __forceinline__ void csp_env(const DevBatch<T>& B, const T* mu_env, i
   double r = 0.0;
   mark(0);
   int it0 = 0;
+  // stall recovery: after kStallRun consecutive failed line searches the solve starts once more
+  // from the zero start (Jacobi estimates of the normal multipliers) with a fresh iteration budget
+  constexpr int kStallRun = 8;
+  int ls_run = 0;
+  bool zero_restarted = false;
 restart:
   for (;; ++it) {
     // ---- Phi (inner scale), classification, residual (residual scale, FP64) ----
@@ -1413,13 +1642,16 @@ restart:
       const CT l0 = (CT)ld0, l1 = (CT)ld1, l2 = (CT)ld2;
       const CT cn = B.cd0[cb + j] + S.Y[3 * j];
       const CT ut1 = S.Y[3 * j + 1] - B.cdob[2 * (cb + j)], ut2 = S.Y[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-      const CT phn = fmin(cn, sp * l0);
+      // attachment rows (bilateral): Phi = Y - d, always active and sticking, no cone
+      const bool att = B.cobs[cb + j] >= kMaxObs;
+      const CT phn = att ? cn : fmin(cn, sp * l0);
       const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
       const CT rho = mu * fmax(l0, CT(0));
       const CT ny = sqrt(y1 * y1 + y2 * y2);
-      int cls = (cn <= sp * l0) ? 1 : 0;
+      int cls = (att || cn <= sp * l0) ? 1 : 0;
       CT p1 = y1, p2 = y2, kap = 0, yh0 = 0, yh1 = 0;
-      if (rho > CT(0)) {
+      if (att) cls |= 2;
+      else if (rho > CT(0)) {
         if (ny <= rho) cls |= 2;
         else {
           cls |= 4;
@@ -1434,12 +1666,12 @@ restart:
       // residual scale
       const double s = (double)B.cs[cb + j];
       const double cnd = B.cd0d[cb + j] + (double)S.Y[3 * j];
-      const double pn = fmin(cnd, s * ld0);
+      const double pn = att ? cnd : fmin(cnd, s * ld0);
       const double z1 = ld1 - (double)ut1 / s, z2 = ld2 - (double)ut2 / s;
       const double nz = sqrt(z1 * z1 + z2 * z2);
       const double rh = (double)mu * fmax(ld0, 0.0);
       double q1 = z1, q2 = z2;
-      if (nz > rh) { double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
+      if (!att && nz > rh) { double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
       const double t1 = s * (ld1 - q1), t2 = s * (ld2 - q2);
       double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
       if (!(rj == rj)) rj = INFINITY;
@@ -1755,12 +1987,14 @@ restart:
         const CT cn = B.cd0[cb + j] + S.Y[3 * j] + alpha * S.Wd[3 * j];
         const CT ut1 = S.Y[3 * j + 1] + alpha * S.Wd[3 * j + 1] - B.cdob[2 * (cb + j)];
         const CT ut2 = S.Y[3 * j + 2] + alpha * S.Wd[3 * j + 2] - B.cdob[2 * (cb + j) + 1];
-        const CT phn = fmin(cn, sp * l0);
+        const bool att = B.cobs[cb + j] >= kMaxObs;
+        const CT phn = att ? cn : fmin(cn, sp * l0);
         const CT y1 = l1 - ut1 / sp, y2 = l2 - ut2 / sp;
         const CT rho = mu * fmax(l0, CT(0));
         const CT ny = sqrt(y1 * y1 + y2 * y2);
         CT p1 = 0, p2 = 0;
-        if (rho > CT(0)) {
+        if (att) { p1 = y1; p2 = y2; }
+        else if (rho > CT(0)) {
           if (ny <= rho) { p1 = y1; p2 = y2; }
           else { p1 = rho * y1 / ny; p2 = rho * y2 / ny; }
         }
@@ -1789,6 +2023,25 @@ restart:
       for (int j = tid; j < c; j += kBlock)
         for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
       __syncthreads();
+    }
+    ls_run = ok ? 0 : ls_run + 1;
+    if (ls_run >= kStallRun && !zero_restarted) {
+      zero_restarted = true;
+      ls_run = 0;
+      for (int j = tid; j < c; j += kBlock) {
+        const CT cn = B.cd0[cb + j] + yfg[3 * j];
+        const bool att = B.cobs[cb + j] >= kMaxObs;
+        S.lam[3 * j] = (cn < CT(0) && !att) ? (double)(-cn / S.sp[j]) : 0.0;
+        S.lam[3 * j + 1] = 0;
+        S.lam[3 * j + 2] = 0;
+      }
+      __syncthreads();
+      apply_W(S.lam, S.Y);
+      for (int j = tid; j < c; j += kBlock)
+        for (int a = 0; a < 3; ++a) S.Y[3 * j + a] += yfg[3 * j + a];
+      if (tid == 0) lust[0] = 0;
+      __syncthreads();
+      it0 = it + 1;
     }
   }
   mark(7);
@@ -1837,12 +2090,12 @@ restart:
   }
 }
 
-template <class T, class CT>
+template <class T, class CT, bool LITE>
 __global__ void __launch_bounds__(kBlock) k_csp(DevBatch<T> B, const T* mu_env, int first_lg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // workgroups take envs in the order of the last step's solve times, longest first
   const int e = B.order ? B.order[blockIdx.x] : blockIdx.x;
-  csp_env<T, CT>(B, mu_env, first_lg, e, smem_raw, true);
+  csp_env<T, CT, LITE>(B, mu_env, first_lg, e, smem_raw, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -1859,7 +2112,7 @@ constexpr size_t fused_gemv_lds() {
   return 3 * kChunk * sizeof(T) + kChunk * sizeof(int) + (size_t)(kBlock / 64 - 1) * 3 * 64 * VW * sizeof(T);
 }
 
-template <class T, class CT, int VW, int UNROLL>
+template <class T, class CT, int VW, int UNROLL, bool LITE>
 __global__ void __launch_bounds__(kBlock) k_lg_fused(DevBatch<T> B, const T* mu_env) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   constexpr int TILE = 64 * VW;
@@ -1887,7 +2140,7 @@ __global__ void __launch_bounds__(kBlock) k_lg_fused(DevBatch<T> B, const T* mu_
     __syncthreads();
     for (int c0 = 0; c0 < v1 - v0; c0 += TILE) gemv_tile<T, false, VW, UNROLL>(B, e, c0, s_vec, s_row, s_red);
     __syncthreads();
-    csp_env<T, CT>(B, mu_env, k == 0 ? 1 : 0, e, smem_raw, false);
+    csp_env<T, CT, LITE>(B, mu_env, k == 0 ? 1 : 0, e, smem_raw, false);
     __syncthreads();
     for (int c0 = 0; c0 < v1 - v0; c0 += TILE) gemv_tile<T, true, VW, UNROLL>(B, e, c0, s_vec, s_row, s_red);
     __syncthreads();
@@ -1912,12 +2165,15 @@ size_t fused_smem_bytes(const DevBatch<T>& B) {
 template <class T>
 void launch_lg_fused(const DevBatch<T>& B, const T* mu_env, hipStream_t s) {
   constexpr int VW = fused_vw<T>();
+  const dim3 g(B.n_envs), blk(kBlock);
   if (B.csp64) {
     const size_t sm = fused_smem_bytes<T, double>(B);
-    hipLaunchKernelGGL((k_lg_fused<T, double, VW, kFusedUnroll>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env);
+    if (B.lite) hipLaunchKernelGGL((k_lg_fused<T, double, VW, kFusedUnroll, true>), g, blk, sm, s, B, mu_env);
+    else hipLaunchKernelGGL((k_lg_fused<T, double, VW, kFusedUnroll, false>), g, blk, sm, s, B, mu_env);
   } else {
     const size_t sm = fused_smem_bytes<T, T>(B);
-    hipLaunchKernelGGL((k_lg_fused<T, T, VW, kFusedUnroll>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env);
+    if (B.lite) hipLaunchKernelGGL((k_lg_fused<T, T, VW, kFusedUnroll, true>), g, blk, sm, s, B, mu_env);
+    else hipLaunchKernelGGL((k_lg_fused<T, T, VW, kFusedUnroll, false>), g, blk, sm, s, B, mu_env);
   }
 }
 
@@ -2008,21 +2264,27 @@ void launch_order(const DevBatch<T>& B, hipStream_t s) {
 
 template <class T>
 void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s) {
+  const dim3 g(B.n_envs), blk(kBlock);
   if (B.csp64) {
     size_t sm = csp_smem_bytes<double>(B.cap, B.rlds);
-    hipLaunchKernelGGL((k_csp<T, double>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+    if (B.lite) hipLaunchKernelGGL((k_csp<T, double, true>), g, blk, sm, s, B, mu_env, first_lg);
+    else hipLaunchKernelGGL((k_csp<T, double, false>), g, blk, sm, s, B, mu_env, first_lg);
   } else {
     size_t sm = csp_smem_bytes<T>(B.cap, B.rlds);
-    hipLaunchKernelGGL((k_csp<T, T>), dim3(B.n_envs), dim3(kBlock), sm, s, B, mu_env, first_lg);
+    if (B.lite) hipLaunchKernelGGL((k_csp<T, T, true>), g, blk, sm, s, B, mu_env, first_lg);
+    else hipLaunchKernelGGL((k_csp<T, T, false>), g, blk, sm, s, B, mu_env, first_lg);
   }
 }
 
 template <class T>
 hipError_t prepare_csp(size_t* static_lds) {
   constexpr int VW = fused_vw<T>();
-  const void* kernels[4] = {(const void*)k_csp<T, double>, (const void*)k_csp<T, T>,
-                            (const void*)k_lg_fused<T, double, VW, kFusedUnroll>,
-                            (const void*)k_lg_fused<T, T, VW, kFusedUnroll>};
+  const void* kernels[8] = {(const void*)k_csp<T, double, false>, (const void*)k_csp<T, T, false>,
+                            (const void*)k_lg_fused<T, double, VW, kFusedUnroll, false>,
+                            (const void*)k_lg_fused<T, T, VW, kFusedUnroll, false>,
+                            (const void*)k_csp<T, double, true>, (const void*)k_csp<T, T, true>,
+                            (const void*)k_lg_fused<T, double, VW, kFusedUnroll, true>,
+                            (const void*)k_lg_fused<T, T, VW, kFusedUnroll, true>};
   size_t most = 0;
   for (const void* k : kernels) {
     hipFuncAttributes fa;

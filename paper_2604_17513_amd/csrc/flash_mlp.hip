@@ -400,7 +400,8 @@ __global__ void k_ws_features(DevBatch<T> B, const T* mu_env, float* feat, int* 
   if (slot >= (long)B.n_envs * B.cap) return;
   const int e = (int)(slot / B.cap), jj = (int)(slot - (long)e * B.cap);
   float* f = feat + slot * kFeat;
-  if (jj >= B.ccount[e]) {
+  // empty slots and attachment rows (bilateral, no prediction) get no features
+  if (jj >= B.ccount[e] || B.cobs[slot] >= kMaxObs) {
     for (int k = 0; k < kFeat; ++k) f[k] = 0.f;
     if (need) need[slot] = 0;
     return;
@@ -455,7 +456,7 @@ __global__ void k_ws_labels(DevBatch<T> B, const float* feat, float* lab) {
   if (slot >= (long)B.n_envs * B.cap) return;
   const int e = (int)(slot / B.cap), jj = (int)(slot - (long)e * B.cap);
   float* y = lab + slot * 3;
-  if (jj >= B.ccount[e]) { y[0] = y[1] = y[2] = 0.f; return; }
+  if (jj >= B.ccount[e] || B.cobs[slot] >= kMaxObs) { y[0] = y[1] = y[2] = 0.f; return; }
   const double dc = B.margin > 0 ? B.margin : 1e-3;
   const int vi = B.voff[e] + B.cvert[slot];
   const double s = B.h * B.h / (double)B.mass[vi];
@@ -470,6 +471,10 @@ __global__ void k_ws_candidates(DevBatch<T> B, const T* mu_env, const float* fea
   if (slot >= (long)B.n_envs * B.cap) return;
   const int e = (int)(slot / B.cap), jj = (int)(slot - (long)e * B.cap);
   if (jj >= B.ccount[e]) return;
+  if (B.cobs[slot] >= kMaxObs) {   // attachment rows keep the plain start
+    for (int k = 0; k < 3; ++k) lam_ml[3 * slot + k] = B.clam[3 * slot + k];
+    return;
+  }
   const double dc = B.margin > 0 ? B.margin : 1e-3;
   const int vi = B.voff[e] + B.cvert[slot];
   const double s = B.h * B.h / (double)B.mass[vi];

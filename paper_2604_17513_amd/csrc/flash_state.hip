@@ -44,10 +44,10 @@ void launch_state_in(const DevBatch<T>& B, int vo, int n, int e0, int e1, const 
     copy3(B.x + vo, B.NV, static_cast<const double*>(x), lds, n, s);
     if (v) copy3(B.v + vo, B.NV, static_cast<const double*>(v), lds, n, s);
   }
-  const int entries = n * kMaxObs, ne = e1 - e0;
+  const int entries = n * kCacheSlots, ne = e1 - e0;
   const int m = entries > ne ? entries : ne;
   if (m > 0)
-    hipLaunchKernelGGL(k_forget, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, B.cache_stamp + (long)vo * kMaxObs,
+    hipLaunchKernelGGL(k_forget, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, B.cache_stamp + (long)vo * kCacheSlots,
                        entries, B.ws_state + e0, ne);
 }
 

@@ -28,12 +28,14 @@ FLASH_ERR_NONFINITE = 6
 FLASH_ERR_UNSUPPORTED = 7
 FLASH_FP32, FLASH_FP64 = 0, 1
 FLASH_WS_ZERO, FLASH_WS_PREV, FLASH_WS_LEARNED = 0, 1, 2
+FLASH_METRIC_EXACT, FLASH_METRIC_LIGHTWEIGHT = 0, 1
 MAX_OBSTACLES = 4
+MAX_GRIPPERS = 2
 
 EXPORTED = [
     "flash_create_batch", "flash_destroy_batch", "flash_set_state", "flash_get_state",
     "flash_set_state_device", "flash_get_state_device",
-    "flash_set_obstacles", "flash_get_obstacles", "flash_step", "flash_synchronize",
+    "flash_set_obstacles", "flash_get_obstacles", "flash_set_grippers", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
     "flash_ws_record", "flash_ws_history",
@@ -58,13 +60,18 @@ class flash_obstacle(C.Structure):
                 ("rot", C.c_double * 9), ("size", C.c_double * 3), ("lin_vel", C.c_double * 3)]
 
 
+class flash_gripper(C.Structure):
+    _fields_ = [("center", C.c_double * 3), ("lin_vel", C.c_double * 3), ("radius", C.c_double),
+                ("move_steps", C.c_int32), ("grasp", C.c_int32)]
+
+
 class flash_params(C.Structure):
     _fields_ = [("h", C.c_double), ("gravity", C.c_double * 3), ("lg_iterations", C.c_int32),
                 ("max_inner_iterations", C.c_int32), ("ncp_tol", C.c_double), ("contact_margin", C.c_double),
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
                 ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32),
-                ("stream_groups", C.c_int32), ("fused_lg", C.c_int32)]
+                ("stream_groups", C.c_int32), ("fused_lg", C.c_int32), ("contact_metric", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -110,6 +117,7 @@ def lib():
         L.flash_get_state_device.argtypes = [P, I32, P, P, I32]
         L.flash_set_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32]
         L.flash_get_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32, C.POINTER(I32)]
+        L.flash_set_grippers.argtypes = [P, I32, C.POINTER(flash_gripper), I32]
         L.flash_step.argtypes = [P, I32]
         L.flash_synchronize.argtypes = [P]
         L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
@@ -164,7 +172,7 @@ def _dptr(a: np.ndarray):
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                   fixed_schedule: bool = False, contact_fp32: bool = False,
-                  stream_groups: int = 0, fused_lg: bool = False) -> flash_params:
+                  stream_groups: int = 0, fused_lg: bool = False, contact_metric: int = 0) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -183,6 +191,18 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.contact_fp32 = 1 if contact_fp32 else 0
     s.stream_groups = int(stream_groups)
     s.fused_lg = 1 if fused_lg else 0
+    s.contact_metric = int(contact_metric)
+    return s
+
+
+def gripper_struct(g: scenes.Gripper) -> flash_gripper:
+    s = flash_gripper()
+    for k in range(3):
+        s.center[k] = g.center[k]
+        s.lin_vel[k] = g.lin_vel[k]
+    s.radius = g.radius
+    s.move_steps = g.move_steps
+    s.grasp = 1 if g.grasp else 0
     return s
 
 
@@ -206,7 +226,8 @@ class Batch:
     def __init__(self, envs: Sequence[scenes.EnvDesc], params: scenes.Params, precision: int = FLASH_FP32,
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
                  stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
-                 contact_fp32: bool = False, stream_groups: int = 0, fused_lg: bool = False):
+                 contact_fp32: bool = False, stream_groups: int = 0, fused_lg: bool = False,
+                 contact_metric: int = 0):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -226,7 +247,7 @@ class Batch:
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
-                                contact_fp32, stream_groups, fused_lg)
+                                contact_fp32, stream_groups, fused_lg, contact_metric)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -292,6 +313,22 @@ class Batch:
             for q, o in enumerate(obstacles):
                 arr[q] = obstacle_struct(o)
         _check(lib().flash_set_obstacles(self._h, env, arr, n))
+
+    def set_grippers(self, grippers, env: int = -1):
+        """grippers: per-env lists of scenes.Gripper (env = -1, equal lengths) or one env's list."""
+        if env < 0:
+            n = len(grippers[0])
+            arr = (flash_gripper * max(self.n_envs * n, 1))()
+            for e, lst in enumerate(grippers):
+                assert len(lst) == n
+                for q, g in enumerate(lst):
+                    arr[e * n + q] = gripper_struct(g)
+        else:
+            n = len(grippers)
+            arr = (flash_gripper * max(n, 1))()
+            for q, g in enumerate(grippers):
+                arr[q] = gripper_struct(g)
+        _check(lib().flash_set_grippers(self._h, env, arr, n))
 
     def get_obstacles(self, env: int):
         arr = (flash_obstacle * MAX_OBSTACLES)()
@@ -509,11 +546,11 @@ def mlp_grad_noalloc(params_dev, x_dev, target_dev, n: int, grad_dev, loss_dev=N
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0,
-               fused_lg: bool = False) -> Batch:
+               fused_lg: bool = False, contact_metric: int = 0) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
               fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups,
-              fused_lg=fused_lg)
+              fused_lg=fused_lg, contact_metric=contact_metric)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:
@@ -521,4 +558,11 @@ def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = 
     else:
         for e, lst in enumerate(sc.obstacles):
             b.set_obstacles(lst, env=e)
+    if sc.grippers:
+        n_g = {len(g) for g in sc.grippers}
+        if len(n_g) == 1:
+            b.set_grippers(sc.grippers)
+        else:
+            for e, lst in enumerate(sc.grippers):
+                b.set_grippers(lst, env=e)
     return b

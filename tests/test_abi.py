@@ -101,7 +101,7 @@ def test_struct_layouts_match_header_field_order():
     # the ctypes mirrors follow the header's field order; sizes are those of the C structs on LP64
     assert C.sizeof(F.flash_obstacle) == 8 + 8 * (3 + 9 + 3 + 3)
     assert C.sizeof(F.flash_env_desc) == 16 + 16 + 8 * 6
-    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8
+    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8 + 8
     assert C.sizeof(F.flash_contact) == 16 + 8 * (3 + 3 + 1 + 3 + 3)
     assert C.sizeof(F.flash_env_stats) == 24 + 8
 
@@ -114,7 +114,8 @@ def test_struct_layouts_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no host C compiler")
-    structs = [F.flash_env_desc, F.flash_obstacle, F.flash_params, F.flash_contact, F.flash_env_stats]
+    structs = [F.flash_env_desc, F.flash_obstacle, F.flash_params, F.flash_contact, F.flash_env_stats,
+               F.flash_gripper]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "flash.h"', "int main(void) {"]
     expect = []
     for S in structs:
