@@ -393,6 +393,26 @@ flash_status flash_ws_load(flash_batch *b, const uint16_t *weights_bf16, size_t 
  * Synchronises. */
 flash_status flash_ws_history(flash_batch *b, int64_t *started_out, int64_t *restarted_out, int32_t reset);
 
+/* Checkpoint and resume.  A checkpoint holds, per env, everything the next
+ * step reads besides the constant model and the network weights: positions
+ * and velocities (Eq. 1's q_h, v_h, in the batch's precision, bit for bit),
+ * obstacle tracks (pose, velocity, steps left to move), grippers and the
+ * vertices they hold with their capture offsets (supplementary bilateral
+ * constraint, Eq. 13), the warm-start cache of previous-step multipliers and
+ * the learned-start state.  A batch created from the same envs, parameters
+ * and capacity, with any stream grouping, that loads it and steps gives the
+ * same bits as the batch that saved it.
+ *   flash_checkpoint_size: bytes needed (host).
+ *   flash_save_checkpoint: writes into buf (host, caller-owned, capacity
+ *     bytes); FLASH_ERR_CAPACITY with *n_bytes = the size needed when buf is
+ *     NULL or too small.  Synchronises.
+ *   flash_load_checkpoint: n_bytes must equal flash_checkpoint_size; a blob of
+ *     another shape, precision or vertex split is rejected with
+ *     FLASH_ERR_INVALID_ARG before anything is written.  Synchronises. */
+flash_status flash_checkpoint_size(flash_batch *b, size_t *n_bytes);
+flash_status flash_save_checkpoint(flash_batch *b, void *buf, size_t capacity, size_t *n_bytes);
+flash_status flash_load_checkpoint(flash_batch *b, const void *buf, size_t n_bytes);
+
 /* Training-pair recording.  on != 0: each step also evaluates the features
  * of its contacts at the step start (a captured graph is re-captured).
  * flash_ws_collect, called after a flash_step of one step, appends one row per

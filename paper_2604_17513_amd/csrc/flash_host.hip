@@ -957,6 +957,126 @@ void get_obstacles_t(flash_batch* b, int env, flash_obstacle* o, int n) {
 
 bool bad_env(flash_batch* b, int env) { return env < -1 || env >= b->n_envs; }
 
+// ----------------------------------------------------------------------------
+// Checkpoint: everything the next step reads besides the constant model and
+// the network weights, per env, so that a batch created from the same envs
+// and parameters resumes bitwise whatever its stream grouping.  Warm-start
+// cache entries are stored as a valid bit and rebased on load onto the
+// loading batch's step counter.
+// ----------------------------------------------------------------------------
+constexpr char kCkptMagic[8] = {'F', 'L', 'A', 'S', 'H', 'C', 'K', '1'};
+struct CkptHeader {
+  char magic[8];
+  int32_t n_envs, elem, max_obs, max_grip, slots, reserved;
+  int64_t nv_total;
+};
+
+template <class T>
+size_t env_ckpt_bytes(int nv) {
+  return sizeof(int32_t)                                            // vertex count
+         + 6 * (size_t)nv * sizeof(T)                                 // x, v
+         + sizeof(int32_t) + kMaxObs * (2 * sizeof(int32_t) + 18 * sizeof(double))
+         + sizeof(int32_t) + kMaxGrip * (3 * sizeof(int32_t) + 7 * sizeof(double))
+         + (size_t)nv * (sizeof(int32_t) + 3 * sizeof(double))       // holding gripper, offset
+         + (size_t)nv * kCacheSlots * (3 * sizeof(T) + 1)            // cache force, valid
+         + sizeof(int32_t);                                          // learned-start state
+}
+
+struct Cursor {
+  unsigned char* w = nullptr;
+  const unsigned char* r = nullptr;
+  template <class X>
+  void put(const X* src, size_t n) { std::memcpy(w, src, n * sizeof(X)); w += n * sizeof(X); }
+  template <class X>
+  void get(X* dst, size_t n) { std::memcpy(dst, r, n * sizeof(X)); r += n * sizeof(X); }
+};
+
+template <class X>
+void d2h(X* dst, const X* src, size_t n) { if (n) HIPCHK(hipMemcpy(dst, src, n * sizeof(X), hipMemcpyDeviceToHost)); }
+template <class X>
+void h2d(X* dst, const X* src, size_t n) { if (n) HIPCHK(hipMemcpy(dst, src, n * sizeof(X), hipMemcpyHostToDevice)); }
+
+// b is a leaf batch (no groups), e its local env index
+template <class T>
+void save_env_t(flash_batch* b, int e, Cursor& c) {
+  DevBatch<T>& B = dev<T>(b);
+  const int vo = b->voff[e], nv = b->voff[e + 1] - vo;
+  const int32_t nv32 = nv;
+  c.put(&nv32, 1);
+  std::vector<T> t((size_t)nv * kCacheSlots * 3);
+  for (int k = 0; k < 3; ++k) { d2h(t.data(), B.x + (size_t)k * b->NV + vo, nv); c.put(t.data(), nv); }
+  for (int k = 0; k < 3; ++k) { d2h(t.data(), B.v + (size_t)k * b->NV + vo, nv); c.put(t.data(), nv); }
+  const size_t so = (size_t)e * kMaxObs, sg = (size_t)e * kMaxGrip;
+  int32_t i4[3 * kMaxGrip + 2 * kMaxObs];
+  double d8[18 * kMaxObs + 7 * kMaxGrip];
+  d2h(i4, B.nobs + e, 1); c.put(i4, 1);
+  d2h(i4, B.obs_kind + so, kMaxObs); d2h(i4 + kMaxObs, B.obs_move + so, kMaxObs); c.put(i4, 2 * kMaxObs);
+  d2h(d8, B.obs_c + 3 * so, 3 * kMaxObs); d2h(d8 + 3 * kMaxObs, B.obs_R + 9 * so, 9 * kMaxObs);
+  d2h(d8 + 12 * kMaxObs, B.obs_size + 3 * so, 3 * kMaxObs); d2h(d8 + 15 * kMaxObs, B.obs_vel + 3 * so, 3 * kMaxObs);
+  c.put(d8, 18 * kMaxObs);
+  d2h(i4, B.ngrip + e, 1); c.put(i4, 1);
+  d2h(i4, B.grip_grasp + sg, kMaxGrip); d2h(i4 + kMaxGrip, B.grip_move + sg, kMaxGrip);
+  d2h(i4 + 2 * kMaxGrip, B.grip_held + sg, kMaxGrip); c.put(i4, 3 * kMaxGrip);
+  d2h(d8, B.grip_c + 3 * sg, 3 * kMaxGrip); d2h(d8 + 3 * kMaxGrip, B.grip_vel + 3 * sg, 3 * kMaxGrip);
+  d2h(d8 + 6 * kMaxGrip, B.grip_r + sg, kMaxGrip); c.put(d8, 7 * kMaxGrip);
+  std::vector<int32_t> ag(nv);
+  std::vector<double> off(3 * (size_t)nv);
+  d2h(ag.data(), B.att_g + vo, nv); c.put(ag.data(), nv);
+  d2h(off.data(), B.att_off + 3 * (size_t)vo, 3 * (size_t)nv); c.put(off.data(), 3 * (size_t)nv);
+  const size_t ne = (size_t)nv * kCacheSlots;
+  d2h(t.data(), B.cache_f + 3 * (size_t)vo * kCacheSlots, 3 * ne); c.put(t.data(), 3 * ne);
+  std::vector<int32_t> st(ne);
+  int32_t cur = 0;
+  d2h(st.data(), B.cache_stamp + (size_t)vo * kCacheSlots, ne);
+  d2h(&cur, B.stamp, 1);
+  std::vector<unsigned char> valid(ne);
+  for (size_t i = 0; i < ne; ++i) valid[i] = st[i] == cur - 1 ? 1 : 0;
+  c.put(valid.data(), ne);
+  d2h(i4, B.ws_state + e, 1); c.put(i4, 1);
+}
+
+template <class T>
+void load_env_t(flash_batch* b, int e, Cursor& c) {
+  DevBatch<T>& B = dev<T>(b);
+  const int vo = b->voff[e], nv = b->voff[e + 1] - vo;
+  int32_t nv32 = 0;
+  c.get(&nv32, 1);   // checked against nv before any load
+  std::vector<T> t((size_t)nv * kCacheSlots * 3);
+  for (int k = 0; k < 3; ++k) { c.get(t.data(), nv); h2d(B.x + (size_t)k * b->NV + vo, t.data(), nv); }
+  for (int k = 0; k < 3; ++k) { c.get(t.data(), nv); h2d(B.v + (size_t)k * b->NV + vo, t.data(), nv); }
+  const size_t so = (size_t)e * kMaxObs, sg = (size_t)e * kMaxGrip;
+  int32_t i4[3 * kMaxGrip + 2 * kMaxObs];
+  double d8[18 * kMaxObs + 7 * kMaxGrip];
+  c.get(i4, 1); h2d(B.nobs + e, i4, 1); b->nobs[e] = i4[0];
+  c.get(i4, 2 * kMaxObs); h2d(B.obs_kind + so, i4, kMaxObs); h2d(B.obs_move + so, i4 + kMaxObs, kMaxObs);
+  c.get(d8, 18 * kMaxObs);
+  h2d(B.obs_c + 3 * so, d8, 3 * kMaxObs); h2d(const_cast<double*>(B.obs_R) + 9 * so, d8 + 3 * kMaxObs, 9 * kMaxObs);
+  h2d(const_cast<double*>(B.obs_size) + 3 * so, d8 + 12 * kMaxObs, 3 * kMaxObs);
+  h2d(const_cast<double*>(B.obs_vel) + 3 * so, d8 + 15 * kMaxObs, 3 * kMaxObs);
+  c.get(i4, 1); h2d(B.ngrip + e, i4, 1);
+  c.get(i4, 3 * kMaxGrip);
+  h2d(B.grip_grasp + sg, i4, kMaxGrip); h2d(B.grip_move + sg, i4 + kMaxGrip, kMaxGrip);
+  h2d(B.grip_held + sg, i4 + 2 * kMaxGrip, kMaxGrip);
+  c.get(d8, 7 * kMaxGrip);
+  h2d(B.grip_c + 3 * sg, d8, 3 * kMaxGrip); h2d(const_cast<double*>(B.grip_vel) + 3 * sg, d8 + 3 * kMaxGrip, 3 * kMaxGrip);
+  h2d(const_cast<double*>(B.grip_r) + sg, d8 + 6 * kMaxGrip, kMaxGrip);
+  std::vector<int32_t> ag(nv);
+  std::vector<double> off(3 * (size_t)nv);
+  c.get(ag.data(), nv); h2d(B.att_g + vo, ag.data(), nv);
+  c.get(off.data(), 3 * (size_t)nv); h2d(B.att_off + 3 * (size_t)vo, off.data(), 3 * (size_t)nv);
+  const size_t ne = (size_t)nv * kCacheSlots;
+  c.get(t.data(), 3 * ne); h2d(B.cache_f + 3 * (size_t)vo * kCacheSlots, t.data(), 3 * ne);
+  std::vector<unsigned char> valid(ne);
+  c.get(valid.data(), ne);
+  int32_t cur = 0;
+  d2h(&cur, B.stamp, 1);
+  std::vector<int32_t> st(ne);
+  for (size_t i = 0; i < ne; ++i) st[i] = valid[i] ? cur - 1 : -1;
+  h2d(B.cache_stamp + (size_t)vo * kCacheSlots, st.data(), ne);
+  c.get(i4, 1); h2d(B.ws_state + e, i4, 1);
+}
+
+
 }  // namespace
 
 // ============================================================================
@@ -1441,6 +1561,81 @@ flash_status flash_ws_history(flash_batch* b, int64_t* started_out, int64_t* res
     if (started_out) *started_out = st;
     if (restarted_out) *restarted_out = rs;
     if (reset) HIPCHK(hipMemset(dp, 0, h.size() * sizeof(unsigned long long)));
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_checkpoint_size(flash_batch* b, size_t* n_bytes) {
+  if (!b || !n_bytes) return fail(FLASH_ERR_INVALID_ARG, "null argument");
+  size_t n = sizeof(CkptHeader);
+  for (int e = 0; e < b->n_envs; ++e) {
+    const int nv = b->voff[e + 1] - b->voff[e];
+    n += b->fp64 ? env_ckpt_bytes<double>(nv) : env_ckpt_bytes<float>(nv);
+  }
+  *n_bytes = n;
+  return FLASH_OK;
+}
+
+flash_status flash_save_checkpoint(flash_batch* b, void* buf, size_t capacity, size_t* n_bytes) {
+  size_t need = 0;
+  const flash_status s0 = flash_checkpoint_size(b, &need);
+  if (s0 != FLASH_OK) return s0;
+  if (n_bytes) *n_bytes = need;
+  if (!buf || capacity < need) return fail(FLASH_ERR_CAPACITY, "checkpoint buffer too small");
+  try {
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, sizeof(h.magic));
+    h.n_envs = b->n_envs; h.elem = b->fp64 ? 8 : 4; h.max_obs = kMaxObs; h.max_grip = kMaxGrip;
+    h.slots = kCacheSlots; h.nv_total = b->voff[b->n_envs];
+    Cursor c;
+    c.w = static_cast<unsigned char*>(buf);
+    c.put(&h, 1);
+    for (int e = 0; e < b->n_envs; ++e) {
+      flash_batch* leaf = b;
+      int le = e;
+      if (!b->groups.empty()) { const int g = group_of(b, e); leaf = b->groups[g]; le = e - b->gofs[g]; }
+      HIPCHK(hipStreamSynchronize(leaf->stream));
+      if (leaf->fp64) save_env_t<double>(leaf, le, c); else save_env_t<float>(leaf, le, c);
+    }
+  } catch (const FlashError& ex) {
+    return fail(ex.st, ex.what());
+  }
+  return FLASH_OK;
+}
+
+flash_status flash_load_checkpoint(flash_batch* b, const void* buf, size_t n_bytes) {
+  size_t need = 0;
+  const flash_status s0 = flash_checkpoint_size(b, &need);
+  if (s0 != FLASH_OK) return s0;
+  if (!buf || n_bytes != need) return fail(FLASH_ERR_INVALID_ARG, "checkpoint size does not match this batch");
+  CkptHeader h{};
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, sizeof(h.magic)) != 0 || h.n_envs != b->n_envs ||
+      h.elem != (b->fp64 ? 8 : 4) || h.max_obs != kMaxObs || h.max_grip != kMaxGrip || h.slots != kCacheSlots ||
+      h.nv_total != b->voff[b->n_envs])
+    return fail(FLASH_ERR_INVALID_ARG, "checkpoint does not belong to a batch of this shape and precision");
+  // every env's vertex count before anything is written
+  const unsigned char* rec = static_cast<const unsigned char*>(buf) + sizeof(CkptHeader);
+  for (int e = 0; e < b->n_envs; ++e) {
+    const int nv = b->voff[e + 1] - b->voff[e];
+    int32_t nv32 = 0;
+    std::memcpy(&nv32, rec, sizeof(nv32));
+    if (nv32 != nv) return fail(FLASH_ERR_INVALID_ARG, "checkpoint vertex count differs at env " + std::to_string(e));
+    rec += b->fp64 ? env_ckpt_bytes<double>(nv) : env_ckpt_bytes<float>(nv);
+  }
+  try {
+    Cursor c;
+    c.r = static_cast<const unsigned char*>(buf) + sizeof(CkptHeader);
+    for (int e = 0; e < b->n_envs; ++e) {
+      flash_batch* leaf = b;
+      int le = e;
+      if (!b->groups.empty()) { const int g = group_of(b, e); leaf = b->groups[g]; le = e - b->gofs[g]; }
+      HIPCHK(hipStreamSynchronize(leaf->stream));
+      if (leaf->fp64) load_env_t<double>(leaf, le, c); else load_env_t<float>(leaf, le, c);
+      HIPCHK(hipDeviceSynchronize());
+    }
   } catch (const FlashError& ex) {
     return fail(ex.st, ex.what());
   }

@@ -38,7 +38,8 @@ EXPORTED = [
     "flash_set_obstacles", "flash_get_obstacles", "flash_set_grippers", "flash_step", "flash_synchronize",
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
-    "flash_ws_record", "flash_ws_history",
+    "flash_ws_record", "flash_ws_history", "flash_checkpoint_size", "flash_save_checkpoint",
+    "flash_load_checkpoint",
     "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
     "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
     "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_grad_noalloc", "flash_mlp_train", "flash_mlp_eval",
@@ -119,6 +120,9 @@ def lib():
         L.flash_get_obstacles.argtypes = [P, I32, C.POINTER(flash_obstacle), I32, C.POINTER(I32)]
         L.flash_set_grippers.argtypes = [P, I32, C.POINTER(flash_gripper), I32]
         L.flash_step.argtypes = [P, I32]
+        L.flash_checkpoint_size.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.flash_save_checkpoint.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.flash_load_checkpoint.argtypes = [P, P, C.c_size_t]
         L.flash_synchronize.argtypes = [P]
         L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
         L.flash_residual.argtypes = [P, D, D, C.POINTER(I32)]
@@ -440,6 +444,18 @@ class Batch:
         a, r = C.c_int64(), C.c_int64()
         _check(lib().flash_ws_history(self._h, C.byref(a), C.byref(r), 1 if reset else 0))
         return a.value, r.value
+
+    def save_checkpoint(self) -> bytes:
+        """Everything the next step reads besides the model and the network weights, as bytes."""
+        n = C.c_size_t()
+        _check(lib().flash_checkpoint_size(self._h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().flash_save_checkpoint(self._h, C.cast(buf, C.c_void_p), n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load_checkpoint(self, blob: bytes):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        _check(lib().flash_load_checkpoint(self._h, C.cast(buf, C.c_void_p), len(blob)))
 
     def ws_record(self, on: bool = True):
         _check(lib().flash_ws_record(self._h, 1 if on else 0))

@@ -7,6 +7,9 @@ host; every kernel still runs to completion).
   steps above the tolerance and is reported as not converged;
 * a get/set state round trip is bitwise, and resuming after it (which drops the multiplier
   history) agrees with the uninterrupted run within the solve tolerance;
+* a checkpoint (state, obstacle and gripper tracks, held vertices, multiplier cache, learned-start
+  state) resumes bitwise in a fresh batch with another stream grouping, and a blob of another
+  shape is rejected before anything is written;
 * invalid env indices and too small output capacities are rejected with their status;
 * 128 envs run the squeeze's whole 500-step horizon in the batched configuration with every
   env-step at the tolerance.
@@ -97,6 +100,55 @@ def test_state_round_trip_and_resume():
     assert err <= 1e-5 * max(np.abs(xa).max(), L)
     per, mx, its, st = b.residual()
     assert mx <= sc.params.ncp_tol
+
+
+@pytest.mark.parametrize("case", ["squeeze_fp32", "dragged_sheet_fp64"])
+def test_checkpoint_resume_is_bitwise(case):
+    """Save after 15 steps, run 10 more; a fresh batch (other stream grouping) that loads the
+    checkpoint runs the same 10 steps to the same bits: positions, velocities, multipliers and
+    the moving obstacles' and grippers' tracks."""
+    F = _F()
+    if case == "squeeze_fp32":
+        sc = scenes.squeeze_blocks(3, seed=36, hexes=5)
+        kw_a, kw_b = dict(stream_groups=1), dict(stream_groups=3, use_graph=True)
+    else:
+        sc = scenes.cloth_drop(n=8, side=0.2, height=0.001, seed=5)
+        sc.x0[0] = sc.x0[0] - np.array([0.0, 0.05, 0.0])
+        sc.obstacles[0] = [scenes.ground()]
+        sc.grippers = [[scenes.Gripper(sc.x0[0][0].copy(), 1e-3, True, np.array([0.05, 0.04, 0.01]), 30)]]
+        kw_a, kw_b = dict(precision=F.FLASH_FP64), dict(precision=F.FLASH_FP64, fused_lg=True)
+    a = F.from_scene(sc, **kw_a)
+    a.step(15)
+    blob = a.save_checkpoint()
+    a.step(10)
+    xa, va = a.get_state()
+    ca = a.contacts()
+    b = F.from_scene(sc, **kw_b)
+    b.load_checkpoint(blob)
+    b.step(10)
+    xb, vb = b.get_state()
+    cb = b.contacts()
+    _say(f"{case}: checkpoint {len(blob)} bytes, contacts {len(ca['vertex'])}, "
+         f"max |dx| {np.abs(xa - xb).max():.1e}")
+    assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+    assert np.array_equal(ca["lambda"], cb["lambda"]) and np.array_equal(ca["obstacle"], cb["obstacle"])
+    for e in range(len(sc.envs)):
+        oa, ob = a.get_obstacles(e), b.get_obstacles(e)
+        assert all(np.array_equal(p.center, q.center) for p, q in zip(oa, ob))
+    # a state-only resume loses the multiplier history (and the held set): not the same run
+    c = F.from_scene(sc, **kw_b)
+    c.load_checkpoint(blob)
+    xs, vs = c.get_state()
+    c.set_state(xs, vs)
+    c.step(10)
+    _say(f"{case}: state-only resume differs by {np.abs(c.get_state()[0] - xa).max():.1e} m")
+    # a blob of another shape is rejected and leaves the batch as it was
+    other = F.from_scene(scenes.squeeze_blocks(1, seed=36, hexes=4))
+    with pytest.raises(F.FlashError):
+        b.load_checkpoint(other.save_checkpoint())
+    with pytest.raises(F.FlashError):
+        b.load_checkpoint(blob[:-1])
+    assert np.array_equal(b.get_state()[0], xb)
 
 
 def test_invalid_env_and_capacity_are_rejected():
