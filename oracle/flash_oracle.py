@@ -897,17 +897,26 @@ def contact_blocks(Y, lam, d0, dob, s, mu, attach=None):
     return phi, Kb, Eb
 
 
-def inertia_metric(oe: OracleEnv, contacts: Contacts, h: float) -> np.ndarray:
-    """W~ = h^2 H M^-1 H^T in contact frames (3c x 3c): (h^2 / m_v) F_j^T F_k for contacts j, k on the
-    same vertex v, zero otherwise (Eq. 10's inertia-only metric)."""
+def inertia_metric(oe: OracleEnv, contacts: Contacts, h: float):
+    """W~ = h^2 H M^-1 H^T in contact frames (3c x 3c, scipy sparse): (h^2 / m_v) F_j^T F_k for
+    contacts j, k on the same vertex v, zero otherwise (Eq. 10's inertia-only metric; M is diagonal,
+    so only contacts of one vertex couple)."""
     c = contacts.count
-    Wt = np.zeros((3 * c, 3 * c))
+    rows, cols, vals = [], [], []
+    by_vertex = {}
     for j in range(c):
-        for k in range(c):
-            if contacts.vertex[j] == contacts.vertex[k]:
-                vj = contacts.vertex[j]
-                Wt[3 * j:3 * j + 3, 3 * k:3 * k + 3] = h * h / oe.mass[vj] * (contacts.frame[j].T @ contacts.frame[k])
-    return Wt
+        by_vertex.setdefault(int(contacts.vertex[j]), []).append(j)
+    ii, jj = np.meshgrid(np.arange(3), np.arange(3), indexing="ij")
+    for vtx, idx in by_vertex.items():
+        for j in idx:
+            for k in idx:
+                blk = h * h / oe.mass[vtx] * (contacts.frame[j].T @ contacts.frame[k])
+                rows.append(3 * j + ii.ravel())
+                cols.append(3 * k + jj.ravel())
+                vals.append(blk.ravel())
+    if not rows:
+        return sp.csr_matrix((3 * c, 3 * c))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(3 * c, 3 * c))
 
 
 def _contact_force_field(oe: OracleEnv, contacts: Contacts, lam):
@@ -937,6 +946,15 @@ def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: 
     Fr = contacts.frame
     dob = np.einsum("jia,ji->ja", Fr, contacts.dobs)[:, 1:] if c else np.zeros((0, 2))
     Wt = inertia_metric(oe, contacts, h)
+    # Z~ = K W~ + E couples only the contacts of one vertex (W~ does): the vertex groups and their
+    # W~ blocks, fixed over the step
+    groups = {}
+    for j in range(c):
+        groups.setdefault(int(contacts.vertex[j]), []).append(j)
+    blocks = []
+    for idx in groups.values():
+        rows = np.array([3 * j + a for j in idx for a in range(3)])
+        blocks.append((np.array(idx), Wt[rows][:, rows].toarray()))
     info = {"newton": 0, "lam_history": [], "csp_residuals": []}
     for k in range(int(params.lg_iterations)):
         p = project(oe, q)
@@ -949,11 +967,12 @@ def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: 
                 r = residual_of(phi)
                 if r <= tol:
                     break
-                Z = np.zeros((3 * c, 3 * c))
-                for j in range(c):
-                    Z[3 * j:3 * j + 3, :] = Kb[j] @ Wt[3 * j:3 * j + 3, :]
-                    Z[3 * j:3 * j + 3, 3 * j:3 * j + 3] += Eb[j]
-                delta = np.linalg.solve(Z, -phi.reshape(-1)).reshape(c, 3)
+                # Z~ delta = -Phi, one vertex block at a time
+                delta = np.zeros((c, 3))
+                for idx, Wb in blocks:
+                    m = len(idx)
+                    Zb = sla.block_diag(*Kb[idx]) @ Wb + sla.block_diag(*Eb[idx])
+                    delta[idx] = np.linalg.solve(Zb, -phi[idx].reshape(3 * m)).reshape(m, 3)
                 lam = np.clip(lam + delta, -params.max_force, params.max_force)
                 info["newton"] += 1
                 info["lam_history"].append(lam.copy())

@@ -59,7 +59,7 @@ def test_inertia_metric_blocks():
     oe = O.precompute(sc.envs[0], p.h)
     box = scenes.box((0.05 + 0.0015 + 0.02, 0.01, 0.0), (0.02, 0.05, 0.05))
     con = O.detect(sc.x0[0], sc.v0[0], [scenes.ground(), box], p)
-    Wt = O.inertia_metric(oe, con, p.h)
+    Wt = O.inertia_metric(oe, con, p.h).toarray()
     assert np.allclose(Wt, Wt.T)
     multi = 0
     for j in range(con.count):
