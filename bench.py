@@ -33,6 +33,13 @@ Arms, each on a fresh batch over the same steps:
                    the same tolerance: Newton iterations and env-steps/s.
   uneven_batched   a second workload: 4096 envs of the uneven mixed recipe
                    (cloth sheets and tet blocks, moving obstacles), 3 groups.
+  contact_metric   the exact contact-space metric Z = h^2 J A^-1 H^T + E (Eq. 7)
+                   against the inertia-only Z~ (Eq. 10), on the dropped cube
+                   (FP64, 1 env, 120 steps) and on the squeeze workload from the
+                   state at the start of the timed window: updates per local-
+                   global iteration, ms/step and the residual reached, with Z~
+                   both run to the tolerance and held to the paper's budget of
+                   10 updates per local-global iteration.
 
 After each arm's timed window one more step of sampled envs is checked against
 the FP64 oracle from the GPU's own state (oracle_error: max absolute and
@@ -76,7 +83,8 @@ METRIC = "env-steps/sec at NCP residual 1e-6: plain vs batched+learned warm-star
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 K_FUSED_BIT = 1 << 9          # kernel class of k_lg_fused in flash_kernel_name order
-ALL_ARMS = ("plain", "batched", "batched_learned", "batched_groups", "cold_starts", "uneven_batched")
+ALL_ARMS = ("plain", "batched", "batched_learned", "batched_groups", "cold_starts", "uneven_batched",
+            "contact_metric")
 
 
 def log(*a):
@@ -380,6 +388,54 @@ def run_arm(F, sc, args, *, warm_start, ws=None, use_graph=False, groups=0, fuse
     return res, extra, jobs
 
 
+def _timed_metric_run(F, sc, prec, metric, cap, steps, blob=None, warm=0):
+    """One solver variant from a state (a checkpoint, or `warm` steps from the scene's start):
+    steps timed with device synchronisation on both sides."""
+    sc.params.max_inner_iterations = cap
+    b = F.from_scene(sc, precision=prec, contact_metric=metric, fused_lg=True)
+    if blob is not None:
+        b.load_checkpoint(blob)
+    elif warm:
+        b.step(warm)
+    b.synchronize()
+    b.residual_history(reset=True)
+    t = time.perf_counter()
+    b.step(steps)
+    b.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    mx, over, newton, st = b.residual_history(reset=True, full=True)
+    b.close()
+    return {"ms_per_step": round(1e3 * dt, 3), "env_steps_per_s": round(len(sc.envs) / dt, 1),
+            "updates_per_lg_iteration": round(newton / max(st, 1) / sc.params.lg_iterations, 3),
+            "max_residual_m": float(f"{mx:.3e}"), "env_steps_above_tol": int(over), "env_steps": int(st),
+            "steps_timed": steps}
+
+
+def metric_compare(F, scenes, args):
+    """Exact metric against the inertia-only metric (to the tolerance, and at a budget of 10)."""
+    out = {}
+    variants = (("exact", 0, 50), ("lightweight_to_tol", 1, 20000), ("lightweight_budget_10", 1, 10))
+    c1 = {}
+    for name, metric, cap in variants:
+        c1[name] = _timed_metric_run(F, scenes.drop_cube(seed=0), F.FLASH_FP64, metric, cap, 120)
+    out["C1_drop_cube_fp64"] = c1
+    sc = scenes.squeeze_blocks(args.envs, seed=0)
+    b = F.from_scene(sc, fused_lg=True)
+    b.step(args.warmup)
+    blob = b.save_checkpoint()
+    b.close()
+    c2 = {}
+    for name, metric, cap in variants:
+        n = 2 if name == "lightweight_to_tol" else args.steps
+        c2[name] = _timed_metric_run(F, scenes.squeeze_blocks(args.envs, seed=0), F.FLASH_FP32, metric, cap, n,
+                                     blob=blob)
+    out[f"C2_squeeze_blocks_{args.envs}_fp32_from_step_{args.warmup}"] = c2
+    out["note"] = ("every variant solves each local-global iteration's contact problem to the same inner "
+                   "tolerance (exact and lightweight_to_tol) or stops at 10 updates (lightweight_budget_10); "
+                   "updates are semismooth Newton iterations for the exact metric, block updates for Z~")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -533,6 +589,12 @@ def main():
         arms["uneven_batched"] = res
         checks["uneven_batched"] = jobs
         log(f"uneven batched arm: {res['ms_per_step']} ms/step")
+
+    if "contact_metric" in arms_on:
+        arms["contact_metric"] = metric_compare(F, scenes, args)
+        c2 = [v for k, v in arms["contact_metric"].items() if k.startswith("C2")][0]
+        log("contact metric: " + ", ".join(f"{k} {v['updates_per_lg_iteration']} updates, {v['ms_per_step']} ms"
+                                           for k, v in c2.items()))
 
     cpu = None
     # ---- host legs (spawned processes: the GPU state of this process is not inherited)

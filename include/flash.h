@@ -131,7 +131,9 @@ typedef struct {
                                      LDS of a CU: at most 330 when the contact solve runs in
                                      FP64 (FP64 batches; FP32 batches unless contact_fp32),
                                      814 with contact_fp32 = 1; larger values return
-                                     FLASH_ERR_INVALID_ARG from flash_create_batch */
+                                     FLASH_ERR_INVALID_ARG from flash_create_batch, except with
+                                     the lightweight metric, which then solves from global memory
+                                     (global_contact_solve) up to 65536 */
   double inner_tol;               /* stopping tolerance of every contact solve, metres
                                      (0: 0.25 * ncp_tol in FP32, 1e-12 in FP64) */
   int32_t contact_fp32;           /* FP32 batches: 0 (default) runs the per-env contact-space
@@ -169,6 +171,16 @@ typedef struct {
                                      that budget leaves it (flash_residual reports it, and
                                      FLASH_ERR_NOT_CONVERGED when above ncp_tol).  The learned
                                      prediction is not used in this mode. */
+  int32_t global_contact_solve;   /* lightweight metric only.  0 (default): the contact update runs
+                                     in LDS, one workgroup per env, while max_contacts_per_env fits
+                                     one CU's LDS, and from global memory beyond that.  1: always from
+                                     global memory: the contact displacement follows lambda through
+                                     the position update of Alg. 1 (u = Gbar (b + h^2 H^T lambda)) at
+                                     every update instead of through a contact-space operator, so
+                                     no per-env storage grows with the square of the contact count
+                                     and max_contacts_per_env may reach 65536.  Same iteration; the
+                                     two routes round differently.  With the exact metric it must
+                                     be 0. */
 } flash_params;
 
 enum { FLASH_METRIC_EXACT = 0, FLASH_METRIC_LIGHTWEIGHT = 1 };

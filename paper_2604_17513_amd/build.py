@@ -16,6 +16,7 @@ SOURCES = {
     "flash_kernels.hip": [],
     "flash_host.hip": [],
     "flash_state.hip": [],
+    "flash_lite.hip": [],
     "flash_mlp.hip": [],
     "flash_mlp_host.hip": [],
 }

@@ -42,6 +42,9 @@ struct DevBatch {
   int warm_start;             // FLASH_WS_*
   int reuse;                  // reuse capacitance factorisations across Newton iterations
   int lite;                   // 1: fixed-budget lightweight contact update (inertia-only metric)
+  int lite_global;            // 1: the lightweight update runs from global memory (k_lite_update)
+  int* lite_done;             // [n_envs] the env's lightweight iteration stopped in this local-global
+                              // iteration (tolerance or budget); its position updates are skipped
 
   const int* voff;            // [n_envs+1]
   const int* toff;            // [n_envs+1]

@@ -392,6 +392,27 @@ struct flash_batch {
         if (infer) launch_ws_infer<T>(B, mu_d, mlp, stream);
       });
     }
+    if (B.lite_global) {
+      // lightweight update from global memory: per local-global iteration the free displacement
+      // z = Gbar b, then alternately u = z + h^2 Gbar H^T lambda (envs still iterating) and one
+      // update of every vertex group; the last residual evaluation only decides
+      launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, -1, 0, stream); });
+      const int N = B.max_newton;
+      for (int k = 0; k < p.lg_iterations; ++k) {
+        launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
+        launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });
+        launch(K_APPLY, [&] { launch_apply<T>(B, sched, stream); });
+        launch(K_CORRECT, [&] { launch_correct<T>(B, sched, stream); });
+        for (int it = 0; it <= N; ++it) {
+          launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, it, k == 0 ? 1 : 0, stream); });
+          if (it < N) launch(K_CORRECT, [&] { launch_correct<T>(B, sched, stream, B.lite_done); });
+        }
+        if (k == 0 && ws_record) launch(K_MLP, [&] { launch_ws_labels<T>(B, mlp.feat, ws_lab, stream); });
+      }
+      launch(K_FINALIZE, [&] { launch_finalize<T>(B, mu_d, stream); });
+      HIPCHK(hipGetLastError());
+      return;
+    }
     launch(K_GATHER, [&] { launch_gather<T>(B, stream); });
     if (p.fused_lg && !ws_record) {
       // the whole local-global loop in one launch, one workgroup per env
@@ -502,6 +523,19 @@ struct flash_batch {
 
 namespace {
 
+// LDS one workgroup needs to hold an env's contact data at this capacity (contact solve in LDS)
+size_t csp_lds_need(const flash_params& p) {
+  const int cap = csp_capacity(p.max_contacts_per_env);
+  const int rlds = csp_lds_rows(csp_rows(cap));
+  const bool ct64 = p.precision == FLASH_FP64 || !p.contact_fp32;
+  return (ct64 ? csp_smem_bytes<double>(cap, rlds) : csp_smem_bytes<float>(cap, rlds)) + kCspStaticLds;
+}
+
+// the lightweight metric's update runs from global memory (on request, or beyond one CU's LDS)
+bool lite_in_global_memory(const flash_params& p) {
+  return p.contact_metric == FLASH_METRIC_LIGHTWEIGHT && (p.global_contact_solve == 1 || csp_lds_need(p) > kLdsBytes);
+}
+
 template <class T>
 void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env_desc* envs) {
   auto& own = b->owned;
@@ -523,6 +557,7 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   B.warm_start = b->p.warm_start;
   B.reuse = 1;   // reuse of a capacitance factorisation while the contact classes hold
   B.lite = b->p.contact_metric == FLASH_METRIC_LIGHTWEIGHT ? 1 : 0;
+  B.lite_global = lite_in_global_memory(b->p) ? 1 : 0;
   const int NV = b->NV, NT = b->NT;
   const size_t cap = (size_t)B.cap;
 
@@ -701,15 +736,19 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   if constexpr (sizeof(T) == 8) B.cframe64 = reinterpret_cast<double*>(B.cframe);
   else B.cframe64 = B.csp64 ? dalloc<double>(9 * ne * cap, own) : nullptr;
   const size_t cts = B.csp64 ? sizeof(double) : sizeof(T);
-  B.Gc = dalloc<unsigned char>(ne * cap * cap * cts, own);
-  B.Ginv = dalloc<unsigned char>(ne * cap * cap * cts, own);
+  // contact-space matrices of the solves in LDS (none for the global-memory lightweight update)
+  const size_t csq = B.lite_global ? 1 : ne * cap * cap * cts;
+  B.Gc = dalloc<unsigned char>(csq, own);
+  B.Ginv = dalloc<unsigned char>(csq, own);
   {
     const size_t rm = (size_t)B.rmax;
-    B.Cm = dalloc<unsigned char>(ne * (rm * rm + 16 * rm) * cts + 4 * ne * rm * sizeof(int), own);
-    B.lupan = dalloc<unsigned char>(ne * rm * (kBK + 2) * cts, own);
+    B.Cm = dalloc<unsigned char>(B.lite_global ? 1 : ne * (rm * rm + 16 * rm) * cts + 4 * ne * rm * sizeof(int), own);
+    B.lupan = dalloc<unsigned char>(B.lite_global ? 1 : ne * rm * (kBK + 2) * cts, own);
   }
-  B.base = dalloc<int>(ne * cap, own);
-  B.scr = dalloc<unsigned char>(ne * cap * 16 * cts, own);
+  B.base = dalloc<int>(B.lite_global ? 1 : ne * cap, own);
+  B.scr = dalloc<unsigned char>(B.lite_global ? 1 : ne * cap * 16 * cts, own);
+  B.lite_done = dalloc<int>(ne, own);
+  HIPCHK(hipMemset(B.lite_done, 0, ne * sizeof(int)));
   B.cyf = dalloc<unsigned char>(3 * ne * cap * cts, own);
   B.lust = dalloc<int>(4 * ne, own);
   HIPCHK(hipMemset(B.lust, 0, 4 * ne * sizeof(int)));
@@ -1092,24 +1131,26 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
                                 void* hip_stream, flash_batch** out) {
   if (!envs || !p || !out || n_envs <= 0) return fail(FLASH_ERR_INVALID_ARG, "null argument or n_envs <= 0");
   *out = nullptr;
+  const bool lite = p->contact_metric == FLASH_METRIC_LIGHTWEIGHT;
   if (!(p->h > 0) || p->lg_iterations <= 0 || !(p->ncp_tol > 0) || !(p->contact_margin >= 0) ||
-      !(p->inner_tol >= 0) || p->max_contacts_per_env < 0 || p->max_contacts_per_env > 4096)
+      !(p->inner_tol >= 0) || p->max_contacts_per_env < 0 || p->max_contacts_per_env > (lite ? 65536 : 4096))
     return fail(FLASH_ERR_INVALID_ARG, "invalid solver parameters");
   if (p->precision != FLASH_FP32 && p->precision != FLASH_FP64)
     return fail(FLASH_ERR_INVALID_ARG, "precision must be FLASH_FP32 or FLASH_FP64");
   if (p->contact_metric != FLASH_METRIC_EXACT && p->contact_metric != FLASH_METRIC_LIGHTWEIGHT)
     return fail(FLASH_ERR_INVALID_ARG, "contact_metric must be FLASH_METRIC_EXACT or FLASH_METRIC_LIGHTWEIGHT");
-  {
+  if (p->global_contact_solve != 0 && p->global_contact_solve != 1)
+    return fail(FLASH_ERR_INVALID_ARG, "global_contact_solve must be 0 or 1");
+  if (p->global_contact_solve == 1 && !lite)
+    return fail(FLASH_ERR_INVALID_ARG, "global_contact_solve = 1 needs the lightweight contact metric");
+  if (!lite) {
     // one workgroup holds an env's contact data in LDS: the capacity must fit one CU's LDS
-    const int cap = csp_capacity(p->max_contacts_per_env);
-    const int rlds = csp_lds_rows(csp_rows(cap));
-    const bool ct64 = p->precision == FLASH_FP64 || !p->contact_fp32;
-    const size_t need =
-        (ct64 ? csp_smem_bytes<double>(cap, rlds) : csp_smem_bytes<float>(cap, rlds)) + kCspStaticLds;
+    // (the lightweight metric falls back to its global-memory update instead)
+    const size_t need = csp_lds_need(*p);
     if (need > kLdsBytes)
-      return fail(FLASH_ERR_INVALID_ARG, "max_contacts_per_env " + std::to_string(cap) + " needs " +
-                                             std::to_string(need) + " bytes of LDS per contact solve; a CU has " +
-                                             std::to_string(kLdsBytes));
+      return fail(FLASH_ERR_INVALID_ARG, "max_contacts_per_env " + std::to_string(csp_capacity(p->max_contacts_per_env)) +
+                                             " needs " + std::to_string(need) +
+                                             " bytes of LDS per contact solve; a CU has " + std::to_string(kLdsBytes));
   }
   for (int e = 0; e < n_envs; ++e) {
     const flash_env_desc& d = envs[e];

@@ -30,7 +30,13 @@ template <class T> constexpr int gemv_tile(int vw) { return 64 * (int)((8 << vw)
 
 template <class T> void launch_apply(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
 template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s);
-template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
+// skip (optional): envs with skip[e] != 0 keep their u
+template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s,
+                                       const int* skip = nullptr);
+// lightweight update in global memory: it = -1 prepares the warm start's forces, it >= 0 is
+// the (it + 1)-th residual evaluation of the local-global iteration (an update unless done)
+template <class T> void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int it, int first_lg,
+                                           hipStream_t s);
 // The whole local-global loop of a step, one workgroup per env (bitwise equal to the
 // kernel-per-phase sequence project, assemble, apply, csp, correct repeated K times).
 template <class T> void launch_lg_fused(const DevBatch<T>& B, const T* mu_env, hipStream_t s);

@@ -72,7 +72,8 @@ class flash_params(C.Structure):
                 ("max_force", C.c_double), ("precision", C.c_int32), ("warm_start", C.c_int32),
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
                 ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32),
-                ("stream_groups", C.c_int32), ("fused_lg", C.c_int32), ("contact_metric", C.c_int32)]
+                ("stream_groups", C.c_int32), ("fused_lg", C.c_int32), ("contact_metric", C.c_int32),
+                ("global_contact_solve", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -176,7 +177,8 @@ def _dptr(a: np.ndarray):
 def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                   fixed_schedule: bool = False, contact_fp32: bool = False,
-                  stream_groups: int = 0, fused_lg: bool = False, contact_metric: int = 0) -> flash_params:
+                  stream_groups: int = 0, fused_lg: bool = False, contact_metric: int = 0,
+                  global_contact_solve: int = 0) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -196,6 +198,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.stream_groups = int(stream_groups)
     s.fused_lg = 1 if fused_lg else 0
     s.contact_metric = int(contact_metric)
+    s.global_contact_solve = int(global_contact_solve)
     return s
 
 
@@ -231,7 +234,7 @@ class Batch:
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
                  stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
                  contact_fp32: bool = False, stream_groups: int = 0, fused_lg: bool = False,
-                 contact_metric: int = 0):
+                 contact_metric: int = 0, global_contact_solve: int = 0):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
@@ -251,7 +254,7 @@ class Batch:
             d.density, d.thickness, d.young = e.density, e.thickness, e.young
             d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
-                                contact_fp32, stream_groups, fused_lg, contact_metric)
+                                contact_fp32, stream_groups, fused_lg, contact_metric, global_contact_solve)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -562,11 +565,11 @@ def mlp_grad_noalloc(params_dev, x_dev, target_dev, n: int, grad_dev, loss_dev=N
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0,
-               fused_lg: bool = False, contact_metric: int = 0) -> Batch:
+               fused_lg: bool = False, contact_metric: int = 0, global_contact_solve: int = 0) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
               fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups,
-              fused_lg=fused_lg, contact_metric=contact_metric)
+              fused_lg=fused_lg, contact_metric=contact_metric, global_contact_solve=global_contact_solve)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:

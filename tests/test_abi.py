@@ -95,6 +95,22 @@ def test_contact_capacity_beyond_lds_is_rejected_without_device():
         assert st != F.FLASH_ERR_INVALID_ARG, L.flash_last_error()
         if st == F.FLASH_OK:
             L.flash_destroy_batch(h)
+    # the lightweight metric takes capacities beyond LDS (its update then runs from global memory),
+    # up to 65536; the exact metric cannot ask for the global-memory update
+    p = F.flash_params()
+    p.h, p.lg_iterations, p.ncp_tol, p.contact_margin = 1.0 / 60, 2, 1e-6, 2e-3
+    h = C.c_void_p()
+    for metric, glob, cap, ok in ((F.FLASH_METRIC_LIGHTWEIGHT, 0, 4000, True),
+                                  (F.FLASH_METRIC_LIGHTWEIGHT, 1, 65536, True),
+                                  (F.FLASH_METRIC_LIGHTWEIGHT, 0, 65537, False),
+                                  (F.FLASH_METRIC_EXACT, 1, 100, False),
+                                  (F.FLASH_METRIC_LIGHTWEIGHT, 2, 100, False),
+                                  (F.FLASH_METRIC_EXACT, 0, 4000, False)):
+        p.contact_metric, p.global_contact_solve, p.max_contacts_per_env = metric, glob, cap
+        st = L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h))
+        assert (st != F.FLASH_ERR_INVALID_ARG) == ok, (metric, glob, cap, L.flash_last_error())
+        if st == F.FLASH_OK:
+            L.flash_destroy_batch(h)
 
 
 def test_struct_layouts_match_header_field_order():

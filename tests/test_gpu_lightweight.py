@@ -142,3 +142,111 @@ def test_lightweight_fused_equals_per_phase_and_converges_to_exact():
          f"updates {its[0]} (exact mode {ex.residual()[2][0]} Newton iterations)")
     assert mx <= 1e-11
     assert np.abs(xl - xe).max() <= 1e-9
+
+
+# ---- the lightweight update from global memory (capacities beyond one CU's LDS) -------------------
+
+def _sheet_on_ground(n, seed, grippers=0):
+    sc = scenes.cloth_drop(n=n, side=0.5, height=0.001, seed=seed, lg_iterations=5)
+    sc.x0[0] = sc.x0[0] - np.array([0.0, 0.05, 0.0])           # lying 1 mm above the ground
+    sc.obstacles[0] = [scenes.ground()]
+    sc.params.max_inner_iterations = 10
+    x0 = sc.x0[0]
+    if grippers:
+        a = int(np.argmin(x0[:, 0] + x0[:, 2]))
+        c = int(np.argmax(x0[:, 0] - x0[:, 2]))
+        sc.grippers = [[scenes.Gripper(x0[a].copy(), 1e-3, True, np.array([0.03, 0.06, 0.03]), -1),
+                        scenes.Gripper(x0[c].copy(), 1e-3, True, np.array([-0.03, 0.06, 0.03]), -1)]]
+    return sc
+
+
+@pytest.mark.parametrize("budget", [1, 10])
+def test_global_update_fp64_drop_cube_matches_oracle(budget):
+    """The drop cube's lightweight steps with the update forced into global memory match the
+    oracle as the in-LDS update does (warm starts rebuilt from the previous GPU step)."""
+    F = _F()
+    sc = scenes.drop_cube(seed=0, lg_iterations=5)
+    sc.params.max_inner_iterations = budget
+    oe = O.precompute(sc.envs[0], sc.params.h)
+    b = F.from_scene(sc, precision=F.FLASH_FP64, max_contacts=128, inner_tol=1e-300,
+                     contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, global_contact_solve=1)
+    for s in range(30):
+        if s in (0, 11, 12, 13, 20, 29):
+            _check(b, sc, {0: oe}, [0], budget, 1e-9, warm=s > 0, label=f"global budget {budget} step {s}")
+        else:
+            b.step(1)
+    assert b.stats()[0]["inner_iterations"] <= 5 * budget
+
+
+def test_global_update_equals_lds_update_and_graph():
+    """Same iteration in LDS and from global memory (FP64 squeeze block, tolerance exit on): the
+    two routes differ by rounding only; the global route captured in a graph gives its eager bits."""
+    F = _F()
+    sc = scenes.squeeze_blocks(2, seed=5, hexes=5, lg_iterations=6)
+    sc.params.max_inner_iterations = 10
+    kw = dict(precision=F.FLASH_FP64, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT)
+    a = F.from_scene(sc, **kw)
+    g = F.from_scene(sc, global_contact_solve=1, **kw)
+    gg = F.from_scene(sc, global_contact_solve=1, use_graph=True, **kw)
+    for bb in (a, g, gg):
+        bb.step(12)
+    xa, xg, xgg = a.get_state()[0], g.get_state()[0], gg.get_state()[0]
+    _say(f"global vs LDS route after 12 steps: max |dx| {np.abs(xa - xg).max():.2e} m; updates "
+         f"{a.stats()[0]['inner_iterations']} / {g.stats()[0]['inner_iterations']}")
+    assert np.abs(xa - xg).max() <= 1e-10
+    assert np.array_equal(xg, xgg)
+    assert np.array_equal(g.contacts()["lambda"], gg.contacts()["lambda"])
+
+
+def test_sheet_on_ground_beyond_lds_fp32_matches_oracle():
+    """A 48 x 48 sheet lying on the ground: 2304 contacts, beyond what one CU's LDS holds, so the
+    FP32 batch updates from global memory.  Steps from reset states (zero start on both sides) match
+    the oracle's lightweight step with the paper's budget (5 x 10) within 1e-5 relative."""
+    F = _F()
+    sc = _sheet_on_ground(48, seed=2)
+    oe = O.precompute(sc.envs[0], sc.params.h)
+    b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, max_contacts=2400, inner_tol=1e-300,
+                     use_graph=True)
+    for s in range(6):
+        if s in (0, 4):
+            x, v = b.get_state()
+            b.set_state(x, v)
+            _check(b, sc, {0: oe}, [0], 10, 1e-5, warm=False, label=f"sheet 48^2 fp32 step {s}")
+        else:
+            b.step(1)
+    st = b.stats()[0]
+    assert st["contacts"] == 2304 and not (st["flags"] & 4)
+
+
+def test_two_grippers_lift_sheet_corners_beyond_lds_fp64():
+    """Two grippers take the corners of the 48 x 48 sheet on the ground and lift them (bilateral
+    attachment rows beside 2302 ground rows): FP64 steps from reset multiplier histories match the
+    oracle's lightweight step with the same grippers and held sets."""
+    F = _F()
+    sc = _sheet_on_ground(48, seed=3, grippers=2)
+    p = sc.params
+    oe = O.precompute(sc.envs[0], p.h)
+    b = F.from_scene(sc, precision=F.FLASH_FP64, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, max_contacts=2400,
+                     inner_tol=1e-300)
+    gr = list(sc.grippers[0])
+    held = None
+    L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+    for s in range(8):
+        if s in (0, 6):
+            x, v = b.get_state()
+            b.set_state(x, v)
+            obs = b.get_obstacles(0)
+            b.step(1)
+            x1, _ = b.get_state()
+            ref = O.step_lightweight(oe, x, v, obs, p, newton_iterations=10, tol=0.0, grippers=gr, held=held)
+            gc = b.contacts(0)
+            same = list(zip(gc["vertex"], gc["obstacle"])) == list(zip(ref.contacts.vertex, ref.contacts.obstacle))
+            err = float(np.abs(x1 - ref.x).max())
+            _say(f"two grippers step {s}: rows {ref.contacts.count} (attachments {int(ref.contacts.attach.sum())}) "
+                 f"max|dq| {err:.3e} oracle residual {ref.residual:.2e}")
+            assert same and int((gc["mode"] == 3).sum()) == 2
+            assert err <= 1e-9 * max(np.abs(ref.x).max(), L)
+            held = ref.held
+        else:
+            b.step(1)
+        gr = [O.advance_gripper(g, p.h) for g in gr]
