@@ -52,8 +52,40 @@ struct HostEnv {
   std::vector<int> hidx;      // 4 per bending hinge (edge x0 x1, opposite x2 x3)
   std::vector<double> halpha; // 4 per hinge
   std::vector<double> hw;     // per hinge
-  std::vector<double> Ginv;   // n*n symmetric
+  std::vector<double> Ginv;   // n*n symmetric (empty when twin >= 0)
+  int twin = -1;              // an earlier env of the batch with the same mesh and material, whose
+                              // explicit inverse this env shares
 };
+
+// The system matrix depends on the mesh, the material and h only (not on mu): envs equal in these
+// share one inverse.  FNV-1a over the defining values; same_model confirms a key match.
+uint64_t model_key(const flash_env_desc& d) {
+  uint64_t hsh = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* c = static_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) { hsh ^= c[i]; hsh *= 1099511628211ull; }
+  };
+  const int k = d.elem == FLASH_TET ? 4 : 3;
+  mix(&d.elem, sizeof(d.elem));
+  mix(&d.n_vertices, sizeof(d.n_vertices));
+  mix(&d.n_elements, sizeof(d.n_elements));
+  mix(d.rest_x, 3 * (size_t)d.n_vertices * sizeof(double));
+  mix(d.elements, (size_t)k * d.n_elements * sizeof(int32_t));
+  const double sc[5] = {d.density, d.elem == FLASH_TRI ? d.thickness : 0.0, d.young, d.poisson,
+                        d.elem == FLASH_TRI ? d.bending : 0.0};
+  mix(sc, sizeof(sc));
+  return hsh;
+}
+
+bool same_model(const flash_env_desc& a, const flash_env_desc& b) {
+  if (a.elem != b.elem || a.n_vertices != b.n_vertices || a.n_elements != b.n_elements) return false;
+  const int k = a.elem == FLASH_TET ? 4 : 3;
+  if (std::memcmp(a.rest_x, b.rest_x, 3 * (size_t)a.n_vertices * sizeof(double)) != 0) return false;
+  if (std::memcmp(a.elements, b.elements, (size_t)k * a.n_elements * sizeof(int32_t)) != 0) return false;
+  if (a.density != b.density || a.young != b.young || a.poisson != b.poisson) return false;
+  if (a.elem == FLASH_TRI && (a.thickness != b.thickness || a.bending != b.bending)) return false;
+  return true;
+}
 
 void tet_data(const flash_env_desc& d, HostEnv& H) {
   const int n = d.n_vertices, m = d.n_elements;
@@ -328,6 +360,7 @@ struct flash_batch {
   int2* gemv_items[3] = {nullptr, nullptr, nullptr};
   int gemv_n_items[3] = {0, 0, 0};
   GemvSchedule sched{};
+  SplitSchedule split{};      // row-split products (global-memory lightweight route only)
   bool tuned = false;
   double cand_ms[6] = {0, 0, 0, 0, 0, 0};
   // learned warm start: network weights, per-slot inference buffers, training-pair recording
@@ -401,11 +434,11 @@ struct flash_batch {
       for (int k = 0; k < p.lg_iterations; ++k) {
         launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
         launch(K_ASSEMBLE, [&] { launch_assemble<T>(B, stream); });
-        launch(K_APPLY, [&] { launch_apply<T>(B, sched, stream); });
-        launch(K_CORRECT, [&] { launch_correct<T>(B, sched, stream); });
+        launch(K_APPLY, [&] { launch_split_apply<T>(B, split, stream); });
+        launch(K_CORRECT, [&] { launch_split_correct<T>(B, split, nullptr, stream); });
         for (int it = 0; it <= N; ++it) {
           launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, it, k == 0 ? 1 : 0, stream); });
-          if (it < N) launch(K_CORRECT, [&] { launch_correct<T>(B, sched, stream, B.lite_done); });
+          if (it < N) launch(K_CORRECT, [&] { launch_split_correct<T>(B, split, B.lite_done, stream); });
         }
         if (k == 0 && ws_record) launch(K_MLP, [&] { launch_ws_labels<T>(B, mlp.feat, ws_lab, stream); });
       }
@@ -627,10 +660,11 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   for (int e = 0; e < ne; ++e) {
     const int n = H[e].n;
     const int ld = (n + 31) / 32 * 32;   // 128-byte aligned rows
-    goff[e] = gtot;
     gld[e] = ld;
-    gtot += (int64_t)n * ld;
     max_ld = std::max(max_ld, ld);
+    if (H[e].twin >= 0) { goff[e] = goff[H[e].twin]; continue; }
+    goff[e] = gtot;
+    gtot += (int64_t)n * ld;
   }
   b->max_ld = max_ld;
   // work lists of the explicit-inverse products: every existing column tile, largest envs first
@@ -650,10 +684,59 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
     }
     b->sched = b->schedule(1, 4);   // 16 bytes per lane, 4 rows in flight: the untuned default
   }
+  if (B.lite_global) {
+    // row-split work list of the global-memory lightweight route: every block (column tile, split
+    // of at most kSplitRows rows) of every env; an env's splits cover the most rows either product
+    // reads (its vertices, or its contact capacity).  Workgroups are dealt to the 8 XCDs round-robin,
+    // so the list runs over groups of 8 consecutive blocks and gives every env the group's 8 blocks
+    // in a row: block b always lands on XCD b mod 8, and all envs read it close together in time
+    // (envs sharing an inverse then share that XCD's L2 lines).  Slots of blocks an env lacks are
+    // padded with empty items (env -1).  The item order never changes the bits.
+    const int tile = split_tile<T>();
+    std::vector<int64_t> poff(ne);
+    std::vector<int> nsplit(ne);
+    int64_t ptot = 0;
+    for (int e = 0; e < ne; ++e) {
+      const int n = H[e].n;
+      const int rows = std::max(n, std::min(B.cap, kCacheSlots * n));
+      nsplit[e] = (rows + kSplitRows - 1) / kSplitRows;
+      poff[e] = ptot;
+      ptot += (int64_t)nsplit[e] * 3 * n;
+    }
+    std::vector<int> order(ne);
+    for (int e = 0; e < ne; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return H[a].n > H[c].n; });
+    constexpr int kXcds = 8;
+    int max_n = 0, max_split = 0;
+    for (int e = 0; e < ne; ++e) { max_n = std::max(max_n, H[e].n); max_split = std::max(max_split, nsplit[e]); }
+    const int nblk = (max_n + tile - 1) / tile * max_split;
+    std::vector<int4> items;
+    for (int bg = 0; bg < nblk; bg += kXcds)
+      for (int e : order) {
+        bool any = false;
+        int4 grp[kXcds];
+        for (int j = 0; j < kXcds; ++j) {
+          const int blk = bg + j, t0 = blk / max_split * tile, sp = blk % max_split;
+          const bool has = blk < nblk && t0 < H[e].n && sp < nsplit[e];
+          grp[j] = has ? make_int4(e, t0, sp, 0) : make_int4(-1, 0, 0, 0);
+          any = any || has;
+        }
+        if (any) items.insert(items.end(), grp, grp + kXcds);
+      }
+    int4* d_items = dalloc<int4>(items.size(), own);
+    HIPCHK(hipMemcpy(d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    int64_t* d_poff = dalloc<int64_t>(ne, own);
+    HIPCHK(hipMemcpy(d_poff, poff.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice));
+    b->split.items = d_items;
+    b->split.n_items = (int)items.size();
+    b->split.partial = dalloc<T>((size_t)ptot, own);
+    b->split.poff = d_poff;
+  }
   T* G = dalloc<T>((size_t)gtot, own);
   {
     std::vector<T> blk;
     for (int e = 0; e < ne; ++e) {
+      if (H[e].twin >= 0) continue;
       const int n = H[e].n, ld = gld[e];
       blk.assign((size_t)n * ld, T(0));
       for (int i = 0; i < n; ++i)
@@ -1209,9 +1292,17 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     b->NT = b->toff[n_envs];
     std::vector<HostEnv> H(n_envs);
     const int nth = std::max(1u, std::thread::hardware_concurrency());
+    // envs with the same mesh and material share one explicit inverse (host and device)
+    std::map<uint64_t, std::vector<int>> seen;
     for (int e = 0; e < n_envs; ++e) {
       if (envs[e].elem == FLASH_TET) tet_data(envs[e], H[e]); else tri_data(envs[e], H[e]);
-      system_inverse(envs[e], H[e], p->h, nth);
+      const uint64_t key = model_key(envs[e]);
+      for (int f : seen[key])
+        if (same_model(envs[e], envs[f])) { H[e].twin = f; break; }
+      if (H[e].twin < 0) {
+        system_inverse(envs[e], H[e], p->h, nth);
+        seen[key].push_back(e);
+      }
     }
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS limit of the contact-solve kernels

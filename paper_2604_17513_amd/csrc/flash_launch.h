@@ -28,6 +28,22 @@ struct GemvSchedule {
 };
 template <class T> constexpr int gemv_tile(int vw) { return 64 * (int)((8 << vw) / sizeof(T)); }
 
+// Row-split explicit-inverse products of the global-memory lightweight route: each workgroup sums
+// at most kSplitRows rows for one column tile of 64 x 16 bytes into a partial, and a merge pass adds
+// an env's partials in split order.  The split depends only on the env's own sizes, so an env gives
+// the same bits alone or in any batch.
+constexpr int kSplitRows = 512;
+template <class T> constexpr int split_tile() { return 64 * (int)(16 / sizeof(T)); }
+struct SplitSchedule {
+  const int4* items;       // (env, first column, split, 0) per workgroup
+  int n_items;
+  void* partial;           // T [sum over envs of splits x 3 x n]
+  const int64_t* poff;     // [n_envs] element offset of each env's partials
+};
+template <class T> void launch_split_apply(const DevBatch<T>& B, const SplitSchedule& S, hipStream_t s);
+template <class T> void launch_split_correct(const DevBatch<T>& B, const SplitSchedule& S, const int* skip,
+                                             hipStream_t s);
+
 template <class T> void launch_apply(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s);
 template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int first_lg, hipStream_t s);
 // skip (optional): envs with skip[e] != 0 keep their u

@@ -148,7 +148,140 @@ __global__ void __launch_bounds__(kBlock) k_lite_update(DevBatch<T> B, const T* 
   }
 }
 
+// Partial sums of one row split of env e's explicit-inverse product for one column tile.
+// ROWS = false: rows 0..n-1 with the right-hand side b (z = Gbar b); ROWS = true: the contact
+// rows with their world forces (u = z + h^2 Gbar H^T lambda).  Gbar is symmetric, so rows are
+// read along their length (16-byte vectors, non-temporal: each row is read once per product).
+template <class T, bool ROWS>
+__global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4* items, const int* skip,
+                                                       T* partial, const int64_t* poff) {
+  constexpr int VW = (int)(16 / sizeof(T));
+  constexpr int TILE = 64 * VW;
+  constexpr int UNROLL = 4;
+  constexpr int WS = kBlock / 64;
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  __shared__ T s_vec[3 * kSplitRows];
+  __shared__ int s_row[kSplitRows];
+  __shared__ T s_red[(WS - 1) * 3 * TILE];
+  const int4 item = items[blockIdx.x];
+  const int e = item.x, tile0 = item.y, split = item.z;
+  if (e < 0 || (skip && skip[e])) return;   // padding item, or an env whose iteration stopped
+  const int v0 = B.voff[e];
+  const int n = B.voff[e + 1] - v0;
+  const int ld = B.gld[e];
+  const int nrows = ROWS ? B.ccount[e] : n;
+  const int r0 = split * kSplitRows;
+  if (r0 >= nrows) return;   // the merge reads only the splits that hold rows
+  const int nr = min(kSplitRows, nrows - r0);
+  const T* G = B.G + B.goff[e];
+  for (int r = threadIdx.x; r < nr; r += kBlock) {
+    if (ROWS) {
+      const size_t j = (size_t)e * B.cap + r0 + r;
+      s_row[r] = B.cvert[j];
+      s_vec[r] = B.cforce[3 * j];
+      s_vec[kSplitRows + r] = B.cforce[3 * j + 1];
+      s_vec[2 * kSplitRows + r] = B.cforce[3 * j + 2];
+    } else {
+      s_row[r] = r0 + r;
+      s_vec[r] = B.b[v0 + r0 + r];
+      s_vec[kSplitRows + r] = B.b[B.NV + v0 + r0 + r];
+      s_vec[2 * kSplitRows + r] = B.b[2 * B.NV + v0 + r0 + r];
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col0 = tile0 + lane * VW;
+  T acc[VW][3];
+  for (int q = 0; q < VW; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0;
+  if (col0 < ld) {   // ld is a multiple of 32 columns: a lane's VW columns lie inside the row
+    for (int rb = wid; rb < nr; rb += WS * UNROLL) {
+      vec_t g[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int r = rb + WS * u;
+        if (r < nr) g[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(G + (size_t)s_row[r] * ld + col0));
+      }
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) {
+        const int r = rb + WS * u;
+        if (r < nr) {
+          const T b0 = s_vec[r], b1 = s_vec[kSplitRows + r], b2 = s_vec[2 * kSplitRows + r];
+#pragma unroll
+          for (int q = 0; q < VW; ++q) {
+            acc[q][0] += g[u][q] * b0;
+            acc[q][1] += g[u][q] * b1;
+            acc[q][2] += g[u][q] * b2;
+          }
+        }
+      }
+    }
+  }
+  // fixed-order reduction over the waves
+  if (wid > 0)
+    for (int q = 0; q < VW; ++q)
+      for (int k = 0; k < 3; ++k) s_red[((wid - 1) * 3 + k) * TILE + lane * VW + q] = acc[q][k];
+  __syncthreads();
+  if (wid == 0) {
+    T* P = partial + poff[e];
+    for (int q = 0; q < VW; ++q) {
+      const int col = col0 + q;
+      if (col >= n) continue;
+      for (int k = 0; k < 3; ++k) {
+        T s = acc[q][k];
+        for (int w = 0; w < WS - 1; ++w) s += s_red[(w * 3 + k) * TILE + lane * VW + q];
+        P[((size_t)split * 3 + k) * n + col] = s;
+      }
+    }
+  }
+}
+
+// Adds each env's row-split partials in split order: z = sum (ROWS = false) or u = z + h^2 sum.
+template <class T, bool ROWS>
+__global__ void __launch_bounds__(kBlock) k_gemv_merge(DevBatch<T> B, const int* skip, const T* partial,
+                                                       const int64_t* poff) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= B.NV) return;
+  const int e = B.vert_env[i];
+  if (skip && skip[e]) return;
+  const int v0 = B.voff[e];
+  const int n = B.voff[e + 1] - v0, col = i - v0;
+  const int nrows = ROWS ? B.ccount[e] : n;
+  const int ns = (nrows + kSplitRows - 1) / kSplitRows;
+  const T* P = partial + poff[e];
+  const T hh = (T)(B.h * B.h);
+  for (int k = 0; k < 3; ++k) {
+    T s = 0;
+    for (int sp = 0; sp < ns; ++sp) s += P[((size_t)sp * 3 + k) * n + col];
+    const size_t o = (size_t)k * B.NV + i;
+    if (ROWS) B.u[o] = B.z[o] + hh * s;
+    else B.z[o] = s;
+  }
+}
+
 }  // namespace
+
+template <class T>
+void launch_split_apply(const DevBatch<T>& B, const SplitSchedule& S, hipStream_t s) {
+  T* P = static_cast<T*>(S.partial);
+  hipLaunchKernelGGL((k_gemv_split<T, false>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items,
+                     (const int*)nullptr, P, S.poff);
+  hipLaunchKernelGGL((k_gemv_merge<T, false>), dim3((unsigned)((B.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, B,
+                     (const int*)nullptr, (const T*)P, S.poff);
+}
+
+template <class T>
+void launch_split_correct(const DevBatch<T>& B, const SplitSchedule& S, const int* skip, hipStream_t s) {
+  T* P = static_cast<T*>(S.partial);
+  hipLaunchKernelGGL((k_gemv_split<T, true>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items, skip, P,
+                     S.poff);
+  hipLaunchKernelGGL((k_gemv_merge<T, true>), dim3((unsigned)((B.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, B,
+                     skip, (const T*)P, S.poff);
+}
+
+template void launch_split_apply<float>(const DevBatch<float>&, const SplitSchedule&, hipStream_t);
+template void launch_split_apply<double>(const DevBatch<double>&, const SplitSchedule&, hipStream_t);
+template void launch_split_correct<float>(const DevBatch<float>&, const SplitSchedule&, const int*, hipStream_t);
+template void launch_split_correct<double>(const DevBatch<double>&, const SplitSchedule&, const int*, hipStream_t);
 
 template <class T>
 void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int it, int first_lg, hipStream_t s) {

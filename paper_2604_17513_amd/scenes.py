@@ -298,6 +298,33 @@ def cloth_drop(n: int = 16, side: float = 0.5, height: float = 0.05, seed: int =
     return Scene([env], [x0], [np.zeros_like(x0)], [obs], params, name="cloth_drop")
 
 
+def cloth_fold(n_envs: int = 1, n: int = 64, side: float = 0.6, lg_iterations: int = 5,
+               inner_iterations: int = 10, fold_time: float = 5.0, lift: float = 0.03) -> Scene:
+    """Cloth-folding stand-in for the paper's garment-folding throughput scene (Sec. V, Table II).
+
+    A square sheet of n x n vertices (side metres, FLASH cloth material: E 3e4, nu 0.4, bending
+    0.2, 1 mm thick, 1000 kg/m^3) lies 1 mm above a table (the ground plane, Coulomb mu = 1.0 as in
+    the paper's folding scene); h = 0.01 s.  Two grippers grasp the near corners (capture radius
+    1.2 vertex spacings: the corner and its two edge neighbours) and carry them at constant
+    velocity across to the sheet's midline and `lift` metres up over `fold_time` seconds, then
+    hold: a quasi-static fold of the near half over the far half.  Every env is the same copy (the
+    paper's throughput comparison steps copies of one scene).  Solver budget: lg_iterations local-
+    global iterations, inner_iterations multiplier updates each (the paper's 5 and 10)."""
+    rest, tris = cloth_grid(n, side, (-side / 2, -side / 2), 0.0)
+    x0 = rest + np.array([0.0, 1e-3, 0.0])
+    env = EnvDesc(TRI, rest, tris, density=1000.0, thickness=1e-3, young=3e4, poisson=0.4, bending=0.2, mu=1.0)
+    params = Params(h=0.01, lg_iterations=lg_iterations, max_inner_iterations=inner_iterations)
+    steps = int(round(fold_time / params.h))
+    vel = np.array([0.0, lift / fold_time, 0.5 * side / fold_time])
+    r = 1.2 * side / (n - 1)
+    near = [int(np.argmin(x0[:, 0] + x0[:, 2])), int(np.argmax(x0[:, 0] - x0[:, 2]))]
+    grips = [Gripper(x0[i].copy(), r, True, vel.copy(), steps) for i in near]
+    envs = [env] * n_envs
+    return Scene(envs, [x0.copy() for _ in range(n_envs)], [np.zeros_like(x0) for _ in range(n_envs)],
+                 [[ground()] for _ in range(n_envs)], params, name="cloth_fold",
+                 grippers=[[g.copy() for g in grips] for _ in range(n_envs)])
+
+
 def single_tet_scene(kind: str = "ground", seed: int = 0, tang_speed: float = 0.2) -> Scene:
     """Tiny scenes for brute-force enumeration of contact modes (1-3 contacts)."""
     rng = np.random.default_rng(seed)

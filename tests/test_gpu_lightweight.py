@@ -250,3 +250,46 @@ def test_two_grippers_lift_sheet_corners_beyond_lds_fp64():
         else:
             b.step(1)
         gr = [O.advance_gripper(g, p.h) for g in gr]
+
+
+def test_cloth_fold_matches_oracle_and_shares_the_inverse():
+    """The folding stand-in (32 x 32 sheet on the table, two grippers carrying the near corners,
+    h = 0.01, budget 5 x 10) in FP32: a step from a reset multiplier history matches the oracle's
+    lightweight step with the same grippers and held sets; three identical envs share one explicit
+    inverse and give the single env's bits."""
+    F = _F()
+    sc = scenes.cloth_fold(3, n=32)
+    p = sc.params
+    oe = O.precompute(sc.envs[0], p.h)
+    b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, max_contacts=32 * 32 + 8, inner_tol=1e-300,
+                     use_graph=True)
+    one = F.from_scene(scenes.cloth_fold(1, n=32), contact_metric=F.FLASH_METRIC_LIGHTWEIGHT,
+                       max_contacts=32 * 32 + 8, inner_tol=1e-300)
+    gr = [g.copy() for g in sc.grippers[0]]
+    held = None
+    L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+    for s in range(12):
+        if s in (0, 10):
+            x, v = b.get_state()
+            b.set_state(x, v)
+            xs, vs = b.split(x), b.split(v)
+            xo, vo = one.get_state()
+            one.set_state(xo, vo)
+            obs = b.get_obstacles(0)
+            b.step(1)
+            one.step(1)
+            x1 = b.split(b.get_state()[0])
+            ref = O.step_lightweight(oe, xs[0], vs[0], obs, p, newton_iterations=10, tol=0.0, grippers=gr, held=held)
+            err = float(np.abs(x1[0] - ref.x).max())
+            _say(f"fold step {s}: rows {ref.contacts.count} (attachments {int(ref.contacts.attach.sum())}) "
+                 f"max|dq| {err:.3e} oracle residual {ref.residual:.2e}")
+            assert int(ref.contacts.attach.sum()) == 6
+            assert err <= 1e-5 * max(np.abs(ref.x).max(), L)
+            held = ref.held
+        else:
+            b.step(1)
+            one.step(1)
+        gr = [O.advance_gripper(g, p.h) for g in gr]
+    xe = b.split(b.get_state()[0])
+    assert np.array_equal(xe[0], xe[1]) and np.array_equal(xe[0], xe[2])
+    assert np.array_equal(xe[0], one.get_state()[0])
