@@ -405,6 +405,46 @@ flash_status flash_ws_load(flash_batch *b, const uint16_t *weights_bf16, size_t 
  * Synchronises. */
 flash_status flash_ws_history(flash_batch *b, int64_t *started_out, int64_t *restarted_out, int32_t reset);
 
+/* ---- Batched depth rendering (supplementary: depth simulation: depth maps, instance
+ * segmentation masks and point clouds ray-cast from the simulation state). */
+
+/* Pinhole camera.  rot is the camera-to-world rotation, row-major, whose columns are the image's
+ * right, down and optical-axis directions in world coordinates; fx, fy, cx, cy in pixels.  Pixel
+ * (u, v) (column, row) casts the ray position + t rot ((u + 0.5 - cx) / fx, (v + 0.5 - cy) / fy, 1),
+ * so the parameter t of a hit is its depth along the optical axis. */
+typedef struct {
+  double position[3];
+  double rot[9];
+  double fx, fy, cx, cy;
+} flash_camera;
+
+typedef struct flash_renderer flash_renderer;
+
+/* A renderer for the surfaces of n_envs bodies described as for flash_create_batch (only elem,
+ * n_vertices, n_elements, rest_x and elements are read, host, copied): a cloth env shows its
+ * triangles, a tet env the faces that belong to one tet only (its boundary); triangles are
+ * two-sided.  Each env's bounding-volume hierarchy is built once on rest_x; every render refits it
+ * to the current positions.  Envs with equal surfaces share one hierarchy topology.  hip_stream:
+ * the stream the renders run on (NULL: the renderer's own).  FLASH_ERR_INVALID_ARG for an invalid
+ * description or a hierarchy deeper than 47 levels. */
+flash_status flash_renderer_create(const flash_env_desc *envs, int32_t n_envs, void *hip_stream,
+                                   flash_renderer **out);
+flash_status flash_renderer_destroy(flash_renderer *r);
+
+/* Renders every env's image.  x_dev: device float positions, structure of arrays [3][ld] over the
+ * concatenation of the envs' vertices (env e's vertex i at column n_vertices[0] + ... +
+ * n_vertices[e-1] + i; the layout flash_get_state_device writes).  obstacles: host
+ * [n_envs * FLASH_MAX_OBSTACLES] records with n_obstacles[e] valid ones per env (planes, boxes and
+ * capsules as in flash_set_obstacles, at the given pose), or NULL for none.  cams: host [n_envs].
+ * Device outputs, caller-allocated, each optional (NULL skips it), [n_envs][height][width]
+ * row-major: depth_dev float (metres along the optical axis, 0 where the ray hits nothing in front
+ * of the camera), instance_dev int32 (-1 nothing, 0 the env's surface, 1 + o obstacle o),
+ * points_dev float x 3 (world position of the hit, 0 where none).  FP32.  Runs on the renderer's
+ * stream and returns when the images are written. */
+flash_status flash_render(flash_renderer *r, const float *x_dev, int64_t ld, const flash_obstacle *obstacles,
+                          const int32_t *n_obstacles, const flash_camera *cams, int32_t width, int32_t height,
+                          float *depth_dev, int32_t *instance_dev, float *points_dev);
+
 /* Checkpoint and resume.  A checkpoint holds, per env, everything the next
  * step reads besides the constant model and the network weights: positions
  * and velocities (Eq. 1's q_h, v_h, in the batch's precision, bit for bit),

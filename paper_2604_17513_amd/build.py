@@ -17,6 +17,7 @@ SOURCES = {
     "flash_host.hip": [],
     "flash_state.hip": [],
     "flash_lite.hip": [],
+    "flash_render.hip": [],
     "flash_mlp.hip": [],
     "flash_mlp_host.hip": [],
 }

@@ -39,7 +39,7 @@ EXPORTED = [
     "flash_contacts", "flash_residual", "flash_residual_history", "flash_stats", "flash_set_kernel_timing",
     "flash_kernel_times", "flash_kernel_name", "flash_phase_times", "flash_schedule_info", "flash_ws_load",
     "flash_ws_record", "flash_ws_history", "flash_checkpoint_size", "flash_save_checkpoint",
-    "flash_load_checkpoint",
+    "flash_load_checkpoint", "flash_renderer_create", "flash_renderer_destroy", "flash_render",
     "flash_ws_collect", "flash_mlp_create", "flash_mlp_destroy", "flash_mlp_set_params", "flash_mlp_get_params",
     "flash_mlp_get_params_bf16", "flash_mlp_set_norm", "flash_mlp_get_norm", "flash_mlp_fit_norm",
     "flash_mlp_forward", "flash_mlp_grad", "flash_mlp_grad_noalloc", "flash_mlp_train", "flash_mlp_eval",
@@ -88,6 +88,11 @@ class flash_env_stats(C.Structure):
                 ("residual", C.c_double)]
 
 
+class flash_camera(C.Structure):
+    _fields_ = [("position", C.c_double * 3), ("rot", C.c_double * 9), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double)]
+
+
 class FlashError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"flash status {status}: {msg}")
@@ -125,6 +130,10 @@ def lib():
         L.flash_save_checkpoint.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
         L.flash_load_checkpoint.argtypes = [P, P, C.c_size_t]
         L.flash_synchronize.argtypes = [P]
+        L.flash_renderer_create.argtypes = [C.POINTER(flash_env_desc), I32, P, C.POINTER(P)]
+        L.flash_renderer_destroy.argtypes = [P]
+        L.flash_render.argtypes = [P, P, C.c_int64, C.POINTER(flash_obstacle), C.POINTER(I32),
+                                   C.POINTER(flash_camera), I32, I32, P, P, P]
         L.flash_contacts.argtypes = [P, I32, C.POINTER(flash_contact), I32, C.POINTER(I32)]
         L.flash_residual.argtypes = [P, D, D, C.POINTER(I32)]
         L.flash_stats.argtypes = [P, C.POINTER(flash_env_stats)]
@@ -227,6 +236,25 @@ def obstacle_struct(o: scenes.Obstacle) -> flash_obstacle:
     return s
 
 
+def env_descs(envs: Sequence[scenes.EnvDesc]):
+    """flash_env_desc array for envs, and the numpy arrays it points into (keep them alive)."""
+    keep = []
+    descs = (flash_env_desc * len(envs))()
+    for i, e in enumerate(envs):
+        rest = np.ascontiguousarray(e.rest_x, dtype=np.float64)
+        el = np.ascontiguousarray(e.elements, dtype=np.int32)
+        keep += [rest, el]
+        d = descs[i]
+        d.elem = e.elem
+        d.n_vertices = e.n_vertices
+        d.n_elements = e.n_elements
+        d.rest_x = _dptr(rest)
+        d.elements = el.ctypes.data_as(C.POINTER(C.c_int32))
+        d.density, d.thickness, d.young = e.density, e.thickness, e.young
+        d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
+    return descs, keep
+
+
 class Batch:
     """A batch of environments living on the GPU (wraps flash_create_batch)."""
 
@@ -239,20 +267,7 @@ class Batch:
         self.n_envs = len(envs)
         self.params = params
         self.nv = [e.n_vertices for e in envs]
-        self._keep = []
-        descs = (flash_env_desc * self.n_envs)()
-        for i, e in enumerate(envs):
-            rest = np.ascontiguousarray(e.rest_x, dtype=np.float64)
-            el = np.ascontiguousarray(e.elements, dtype=np.int32)
-            self._keep += [rest, el]
-            d = descs[i]
-            d.elem = e.elem
-            d.n_vertices = e.n_vertices
-            d.n_elements = e.n_elements
-            d.rest_x = _dptr(rest)
-            d.elements = el.ctypes.data_as(C.POINTER(C.c_int32))
-            d.density, d.thickness, d.young = e.density, e.thickness, e.young
-            d.poisson, d.bending, d.mu = e.poisson, e.bending, e.mu
+        descs, self._keep = env_descs(envs)
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
                                 contact_fp32, stream_groups, fused_lg, contact_metric, global_contact_solve)
         h = C.c_void_p()
@@ -560,6 +575,76 @@ def mlp_grad_noalloc(params_dev, x_dev, target_dev, n: int, grad_dev, loss_dev=N
                                         C.c_void_p(_devptr(target_dev)), int(n), C.c_void_p(_devptr(grad_dev)),
                                         C.c_void_p(_devptr(loss_dev)) if loss_dev is not None else None,
                                         C.c_void_p(stream)))
+
+
+def camera_struct(cam) -> flash_camera:
+    """cam: dict with position (3,), rot (3, 3) camera-to-world (columns: image right, image down,
+    optical axis), fx, fy, cx, cy in pixels."""
+    s = flash_camera()
+    R = np.asarray(cam["rot"], dtype=np.float64).reshape(-1)
+    for k in range(3):
+        s.position[k] = float(cam["position"][k])
+    for k in range(9):
+        s.rot[k] = float(R[k])
+    s.fx, s.fy, s.cx, s.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    return s
+
+
+class Renderer:
+    """Batched depth ray casting of the envs' surfaces (wraps flash_renderer_create / flash_render)."""
+
+    def __init__(self, envs: Sequence[scenes.EnvDesc], stream: Optional[int] = None):
+        self.n_envs = len(envs)
+        self.nv = [e.n_vertices for e in envs]
+        descs, keep = env_descs(envs)
+        h = C.c_void_p()
+        _check(lib().flash_renderer_create(descs, self.n_envs, C.c_void_p(stream or 0), C.byref(h)))
+        self._h = h
+
+    def render(self, x_dev, cams, width: int, height: int, obstacles=None, depth=True, instance=True,
+               points=False):
+        """x_dev: torch float32 CUDA tensor [3, ld] of all envs' vertex positions (ld >= total
+        vertices); cams: per-env camera dicts; obstacles: per-env lists of scenes.Obstacle (or None).
+        Returns a dict of torch CUDA tensors: depth [n_envs, height, width] (float32), instance
+        (int32) and points [n_envs, height, width, 3] (float32), each when asked for."""
+        import torch
+        assert x_dev.dtype == torch.float32 and x_dev.is_cuda and x_dev.dim() == 2 and x_dev.shape[0] == 3
+        x_dev = x_dev.contiguous()
+        n = self.n_envs
+        cam_arr = (flash_camera * n)()
+        for e in range(n):
+            cam_arr[e] = camera_struct(cams[e])
+        ob_arr = (flash_obstacle * (n * MAX_OBSTACLES))()
+        nob = (C.c_int32 * n)()
+        if obstacles is not None:
+            for e, lst in enumerate(obstacles):
+                nob[e] = len(lst)        # the library rejects counts above MAX_OBSTACLES
+                for q, o in enumerate(lst[:MAX_OBSTACLES]):
+                    ob_arr[e * MAX_OBSTACLES + q] = obstacle_struct(o)
+        dev = x_dev.device
+        out = {}
+        if depth:
+            out["depth"] = torch.empty((n, height, width), dtype=torch.float32, device=dev)
+        if instance:
+            out["instance"] = torch.empty((n, height, width), dtype=torch.int32, device=dev)
+        if points:
+            out["points"] = torch.empty((n, height, width, 3), dtype=torch.float32, device=dev)
+        ptr = lambda k: C.c_void_p(out[k].data_ptr() if k in out else 0)  # noqa: E731
+        torch.cuda.synchronize(dev)
+        _check(lib().flash_render(self._h, C.c_void_p(x_dev.data_ptr()), int(x_dev.stride(0)), ob_arr, nob,
+                                  cam_arr, int(width), int(height), ptr("depth"), ptr("instance"), ptr("points")))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().flash_renderer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,

@@ -131,7 +131,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = [F.flash_env_desc, F.flash_obstacle, F.flash_params, F.flash_contact, F.flash_env_stats,
-               F.flash_gripper]
+               F.flash_gripper, F.flash_camera]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "flash.h"', "int main(void) {"]
     expect = []
     for S in structs:
