@@ -40,6 +40,12 @@ Arms, each on a fresh batch over the same steps:
                    the paper's budget (5 local-global iterations x 10 updates) and
                    its low-iteration ablation (2 x 2); the paper's own RTX 4090
                    figures ride along as context.
+  depth_render     batched depth ray casting (depth, instance ids): a draped
+                   181 x 181 towel stand-in (32,761 vertices, the size of the
+                   paper's towel-folding scene) over a table, per-env seeded folds,
+                   one top-down camera per env, at 1, 8, 32, 64 and 128 envs and
+                   at 640 x 480 and 128 x 128 pixels: ms per frame (hierarchy refit
+                   + render), with the paper's own figures as context.
   contact_metric   the exact contact-space metric Z = h^2 J A^-1 H^T + E (Eq. 7)
                    against the inertia-only Z~ (Eq. 10), on the dropped cube
                    (FP64, 1 env, 120 steps) and on the squeeze workload from the
@@ -91,7 +97,10 @@ HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 K_FUSED_BIT = 1 << 9          # kernel class of k_lg_fused in flash_kernel_name order
 ALL_ARMS = ("plain", "batched", "batched_learned", "batched_groups", "cold_starts", "uneven_batched",
-            "contact_metric", "fold_sweep")
+            "contact_metric", "fold_sweep", "depth_render")
+RENDER_ENVS = (1, 8, 32, 64, 128)
+# the paper's depth-rendering overhead table (towel-folding scene, ms per frame): context only
+PAPER_RENDER_MS = {1: 0.75, 8: 2.23, 32: 7.20, 64: 14.18, 128: 27.31}
 FOLD_ENVS = (1, 8, 32, 64, 128, 256)
 # Table II of the paper (FLASH row, ms/step on one RTX 4090, T-shirt dual-sleeve folding): context only
 PAPER_TABLE_II = {1: 5.68, 8: 9.67, 32: 24.79, 64: 50.43, 128: 90.41, 256: 185.10}
@@ -480,6 +489,58 @@ def fold_sweep(F, scenes, args):
     return out
 
 
+def towel_positions(rest, n, seed):
+    """A draped towel stand-in: the flat sheet lifted into seeded folds 0-6 cm above the table."""
+    rng = np.random.default_rng(seed)
+    x = rest.copy()
+    k = rng.uniform(6.0, 14.0, size=2)
+    ph = rng.uniform(0.0, 2 * np.pi, size=2)
+    x[:, 1] = 0.03 + 0.03 * np.sin(k[0] * rest[:, 0] + ph[0]) * np.cos(k[1] * rest[:, 2] + ph[1])
+    return x
+
+
+def depth_render(F, scenes, torch, args):
+    """ms per frame of the batched renderer against the env count (the paper's rendering table)."""
+    n = 181
+    rest, tris = scenes.cloth_grid(n, 0.6, (-0.3, -0.3), 0.0)
+    env = scenes.EnvDesc(scenes.TRI, rest, tris, density=1000.0, thickness=1e-3, young=3e4, poisson=0.4,
+                         bending=0.2, mu=1.0)
+    down = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [0.0, 1.0, 0.0]])
+    out = {"workload": f"towel stand-in: {n}x{n} sheet ({n * n} vertices, {2 * (n - 1) ** 2} triangles) in seeded "
+                       f"folds over a table plane, one top-down camera per env at 0.9 m (fx = fy = 0.78 x width); "
+                       f"outputs depth and instance ids; positions resident on the GPU; refit + render per frame",
+           "rows": {}}
+    for (W, H) in ((640, 480), (128, 128)):
+        row = {}
+        cam = {"position": np.array([0.0, 0.9, 0.0]), "rot": down, "fx": 0.78 * W, "fy": 0.78 * W,
+               "cx": W / 2.0, "cy": H / 2.0}
+        for ne in RENDER_ENVS:
+            xs = np.concatenate([towel_positions(rest, n, s) for s in range(ne)]).T.copy()
+            x = torch.tensor(xs, dtype=torch.float32, device="cuda")
+            R = F.Renderer([env] * ne)
+            obs = [[scenes.ground()]] * ne
+            for _ in range(2):
+                R.render(x, [cam] * ne, W, H, obstacles=obs)
+            reps = 10
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                o = R.render(x, [cam] * ne, W, H, obstacles=obs)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            cover = float((o["instance"] == 0).float().mean().item())
+            R.close()
+            row[str(ne)] = {"ms_per_frame": round(1e3 * dt, 3), "mrays_per_s": round(ne * W * H / dt / 1e6, 1),
+                            "towel_pixels_frac": round(cover, 3)}
+            log(f"depth render {W}x{H}: {ne} envs {row[str(ne)]['ms_per_frame']} ms/frame")
+            del x
+        out["rows"][f"{W}x{H}"] = row
+    out["paper_ms_per_frame"] = {str(k): v for k, v in PAPER_RENDER_MS.items()}
+    out["note"] = ("the paper does not state its image size; its figures (another machine, its own ray-casting "
+                   "backend) are context, not a target")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -639,6 +700,9 @@ def main():
 
     if "fold_sweep" in arms_on:
         arms["fold_sweep"] = fold_sweep(F, scenes, args)
+
+    if "depth_render" in arms_on:
+        arms["depth_render"] = depth_render(F, scenes, torch, args)
 
     if "contact_metric" in arms_on:
         arms["contact_metric"] = metric_compare(F, scenes, args)
