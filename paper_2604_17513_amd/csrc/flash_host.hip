@@ -570,7 +570,7 @@ bool lite_in_global_memory(const flash_params& p) {
 }
 
 template <class T>
-void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env_desc* envs) {
+void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc* envs) {
   auto& own = b->owned;
   const int ne = b->n_envs;
   DevBatch<T> B{};
@@ -734,14 +734,20 @@ void build_device(flash_batch* b, const std::vector<HostEnv>& H, const flash_env
   }
   T* G = dalloc<T>((size_t)gtot, own);
   {
+    // one env at a time: its inverse (FP64, host), converted and uploaded, then freed, so that the
+    // host holds one inverse at a time whatever the batch
+    const int nth = std::max(1u, std::thread::hardware_concurrency());
     std::vector<T> blk;
     for (int e = 0; e < ne; ++e) {
       if (H[e].twin >= 0) continue;
-      const int n = H[e].n, ld = gld[e];
+      HostEnv& he = H[e];
+      system_inverse(envs[e], he, b->p.h, nth);
+      const int n = he.n, ld = gld[e];
       blk.assign((size_t)n * ld, T(0));
       for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) blk[(size_t)i * ld + j] = (T)H[e].Ginv[(size_t)i * n + j];
+        for (int j = 0; j < n; ++j) blk[(size_t)i * ld + j] = (T)he.Ginv[(size_t)i * n + j];
       HIPCHK(hipMemcpy(G + goff[e], blk.data(), blk.size() * sizeof(T), hipMemcpyHostToDevice));
+      std::vector<double>().swap(he.Ginv);
     }
   }
   auto up = [&](auto* dst, const auto& src) {
@@ -1299,11 +1305,9 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
       const uint64_t key = model_key(envs[e]);
       for (int f : seen[key])
         if (same_model(envs[e], envs[f])) { H[e].twin = f; break; }
-      if (H[e].twin < 0) {
-        system_inverse(envs[e], H[e], p->h, nth);
-        seen[key].push_back(e);
-      }
+      if (H[e].twin < 0) seen[key].push_back(e);
     }
+    (void)nth;
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS limit of the contact-solve kernels
     size_t static_lds = 0;

@@ -23,42 +23,65 @@ __device__ __forceinline__ short f2bf(float f) {
 }
 
 // C(m, n) = act(sum_k A(m, k) B(k, n) + bias[n]) (+ C if accumulate).
-// A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn]; one wave per
-// 32 x 32 tile of C; 32x32x8 lane layout: A row = lane % 32, k = 4 (lane / 32) + t;
-// B column = lane % 32, same k; D row = 8 (r / 4) + 4 (lane / 32) + r % 4, column = lane % 32.
-// blockIdx.z selects a K slice of g.kslice rows when the product is split over K: the
-// slice's partial sums go to g.work[z][M][N] and a second kernel adds the slices in order.
-__global__ void __launch_bounds__(64) k_gemm_bf16(GemmArgs g) {
-  const int l = threadIdx.x;
-  const long m0 = (long)blockIdx.x * 32, n0 = (long)blockIdx.y * 32;
-  const long i = m0 + (l & 31), j = n0 + (l & 31);
-  const int kq = 4 * (l >> 5);
+// A(m, k) = A[m * sam + k * sak], B(k, n) = B[k * sbk + n * sbn].  One workgroup of 4 waves per
+// 64 x 64 tile of C, each wave a 32 x 32 quadrant on v_mfma_f32_32x32x8bf16_1k (A row = lane % 32,
+// k = 4 (lane / 32) + t; B column = lane % 32, same k; D row = 8 (r / 4) + 4 (lane / 32) + r % 4,
+// column = lane % 32).  K runs in chunks of kKc staged in LDS as bf16, each element rounded once
+// and loaded along whichever of its two indices is contiguous; B is staged transposed so that every
+// MFMA operand is one 8-byte LDS read.  Every quadrant accumulates over k in steps of 8 from the
+// slice start, so the result does not depend on the chunking.
+// blockIdx.z selects a K slice of g.kslice rows when the product is split over K: the slice's
+// partial sums go to g.work[z][M][N] and a second kernel adds the slices in order.
+constexpr int kKc = 32;
+constexpr int kKp = kKc + 4;   // padded LDS row (shorts): rows 72 bytes apart
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ short As[64 * kKp];   // [m][k]
+  __shared__ short Bs[64 * kKp];   // [n][k]
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const long m0 = (long)blockIdx.x * 64, n0 = (long)blockIdx.y * 64;
+  const int wm = 32 * (w & 1), wn = 32 * (w >> 1);
   const int kb = g.work ? (int)blockIdx.z * g.kslice : 0;
   const int ke = g.work ? min(g.K, kb + g.kslice) : g.K;
+  const bool a_mfast = g.sam == 1, b_nfast = g.sbn == 1;
   floatx16 c = {};
-  for (int k0 = kb; k0 < ke; k0 += 8) {
-    bf16x4 a, b;
-    for (int t = 0; t < 4; ++t) {
-      const int k = k0 + kq + t;
-      const float av = (i < g.M && k < ke) ? g.A[i * g.sam + (long)k * g.sak] : 0.f;
-      const float bv = (j < g.N && k < ke) ? g.B[(long)k * g.sbk + j * g.sbn] : 0.f;
-      a[t] = f2bf(av);
-      b[t] = f2bf(bv);
+  for (int k0 = kb; k0 < ke; k0 += kKc) {
+    // stage: 64 x kKc of A and of B (8 elements per thread each)
+#pragma unroll
+    for (int q = 0; q < 64 * kKc / 256; ++q) {
+      const int e = tid + 256 * q;
+      const int am = a_mfast ? (e & 63) : (e / kKc), ak = a_mfast ? (e >> 6) : (e % kKc);
+      const long gm = m0 + am;
+      const int gk = k0 + ak;
+      const float av = (gm < g.M && gk < ke) ? g.A[gm * g.sam + (long)gk * g.sak] : 0.f;
+      As[am * kKp + ak] = f2bf(av);
+      const int bn = b_nfast ? (e & 63) : (e / kKc), bk = b_nfast ? (e >> 6) : (e % kKc);
+      const long gn = n0 + bn;
+      const int gk2 = k0 + bk;
+      const float bv = (gn < g.N && gk2 < ke) ? g.B[(long)gk2 * g.sbk + gn * g.sbn] : 0.f;
+      Bs[bn * kKp + bk] = f2bf(bv);
     }
-    c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+    __syncthreads();
+    const int kend = min(kKc, ke - k0);
+    for (int kk = 0; kk < kend; kk += 8) {
+      const int ko = kk + 4 * (l >> 5);
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(&As[(wm + (l & 31)) * kKp + ko]);
+      const bf16x4 b = *reinterpret_cast<const bf16x4*>(&Bs[(wn + (l & 31)) * kKp + ko]);
+      c = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+    }
+    __syncthreads();
   }
+  const long jj = n0 + wn + (l & 31);
   if (g.work) {
     float* wk = g.work + (size_t)blockIdx.z * g.M * g.N;
     for (int r = 0; r < 16; ++r) {
-      const long ii = m0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-      const long jj = n0 + (l & 31);
+      const long ii = m0 + wm + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
       if (ii < g.M && jj < g.N) wk[ii * g.N + jj] = c[r];
     }
     return;
   }
   for (int r = 0; r < 16; ++r) {
-    const long ii = m0 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-    const long jj = n0 + (l & 31);
+    const long ii = m0 + wm + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
     if (ii < g.M && jj < g.N) {
       float v = c[r];
       if (g.bias) v += g.bias[jj];
@@ -85,23 +108,25 @@ __global__ void k_splitk_reduce(GemmArgs g, int slices) {
 void launch_gemm(const GemmArgs& g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0) return;
   GemmArgs g = g0;
-  dim3 grid((unsigned)((g.M + 31) / 32), (unsigned)((g.N + 31) / 32));
-  const long tiles = (long)grid.x * grid.y;
-  // few output tiles over a long K (weight gradients): split K so that the chip fills
+  dim3 grid((unsigned)((g.M + 63) / 64), (unsigned)((g.N + 63) / 64));
+  // few output tiles over a long K (weight gradients): split K so that the chip fills.  The slice
+  // count is the one chosen for 32 x 32 tiles, so the slices (hence the bits) are those of that
+  // tiling.
+  const long tiles32 = ((g.M + 31) / 32) * (long)((g.N + 31) / 32);
   int slices = 1;
-  if (g.work && tiles < 512 && g.K > 256) {
-    slices = (int)std::min<long>((g.K + 127) / 128, std::max<long>(1, 1024 / tiles));
+  if (g.work && tiles32 < 512 && g.K > 256) {
+    slices = (int)std::min<long>((g.K + 127) / 128, std::max<long>(1, 1024 / tiles32));
     slices = std::min<long>(slices, g.work_cap / (g.M * g.N));
   }
   if (slices <= 1) {
     g.work = nullptr;
-    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, s, g);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
     return;
   }
   g.kslice = ((g.K + slices - 1) / slices + 7) / 8 * 8;
   slices = (g.K + g.kslice - 1) / g.kslice;
   grid.z = (unsigned)slices;
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(64), 0, s, g);
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
   const long mn = g.M * g.N;
   hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, s, g, slices);
 }
