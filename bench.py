@@ -54,6 +54,13 @@ Arms, each on a fresh batch over the same steps:
                    precompute of the explicit inverses) reported separately; the
                    largest sheet and the largest block checked against the oracle's
                    lightweight step from a history reset.
+  slab_press       (opt-in) the large-scene recipe: 64 envs of a 102,010-vertex,
+                   540,000-tet slab pressed by two pads (at most 20k contacts), FP32,
+                   lightweight metric from global memory, K = 10, budget 10, HIP
+                   graph; the envs are copies and share one explicit inverse
+                   (41.6 GB); create time and the HBM footprint reported; env 0
+                   checked against the oracle's lightweight step from a history
+                   reset.
   contact_metric   the exact contact-space metric Z = h^2 J A^-1 H^T + E (Eq. 7)
                    against the inertia-only Z~ (Eq. 10), on the dropped cube
                    (FP64, 1 env, 120 steps) and on the squeeze workload from the
@@ -106,7 +113,7 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 K_FUSED_BIT = 1 << 9          # kernel class of k_lg_fused in flash_kernel_name order
 ALL_ARMS = ("plain", "batched", "batched_learned", "batched_groups", "cold_starts", "uneven_batched",
             "contact_metric", "fold_sweep", "depth_render")
-OPT_IN_ARMS = ("uneven_full",)
+OPT_IN_ARMS = ("uneven_full", "slab_press")
 RENDER_ENVS = (1, 8, 32, 64, 128)
 # the paper's depth-rendering overhead table (towel-folding scene, ms per frame): context only
 PAPER_RENDER_MS = {1: 0.75, 8: 2.23, 32: 7.20, 64: 14.18, 128: 27.31}
@@ -633,6 +640,61 @@ def uneven_full(F, scenes, args):
     return out
 
 
+def slab_press(F, scenes, torch, args):
+    """The large-scene recipe with shared inverses (64 copies of a 100k-vertex slab)."""
+    from oracle import flash_oracle as O     # the oracle check of one env (test infrastructure)
+    ne = args.slab_envs
+    sc = scenes.slab_press(ne)
+    os.environ["FLASH_PROGRESS"] = "1"        # the 100k-vertex inverse reports progress while it is formed
+    free0 = torch.cuda.mem_get_info()[0]
+    t0 = time.perf_counter()
+    b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, global_contact_solve=1, max_contacts=30000,
+                     use_graph=True)
+    create_s = time.perf_counter() - t0
+    footprint = free0 - torch.cuda.mem_get_info()[0]
+    log(f"slab press: created {ne} envs in {create_s:.1f}s, HBM footprint {footprint / 1e9:.1f} GB")
+    b.step(args.warmup)
+    b.synchronize()
+    b.residual_history(reset=True)
+    t = time.perf_counter()
+    b.step(args.steps)
+    b.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    log(f"slab press: {1e3 * dt:.1f} ms/step")
+    mx, over, newton, st = b.residual_history(reset=True, full=True)
+    stats = b.stats()
+    cts = np.array([s_["contacts"] for s_ in stats])
+    res = np.array([s_["residual"] for s_ in stats])
+    n = sc.envs[0].n_vertices
+    out = {"workload": f"slab_press: {ne} envs of a {n}-vertex, {sc.envs[0].n_elements}-tet slab (100 x 9 x 100 "
+                       f"hexes of 5 mm) pressed 5 mm by two pads at 2 cm/s, FP32, lightweight metric from global "
+                       f"memory, K = 10, budget 10, HIP graph, one shared explicit inverse",
+           "create_s": round(create_s, 1), "hbm_footprint_gb": round(footprint / 1e9, 2),
+           "ms_per_step": round(1e3 * dt, 3), "env_steps_per_s": round(ne / dt, 2),
+           "timed_steps": [args.warmup, args.warmup + args.steps - 1],
+           "updates_per_lg_iteration": round(newton / max(st, 1) / 10, 2),
+           "contacts_per_env": {"mean": round(float(cts.mean()), 1), "max": int(cts.max())},
+           "end_of_step_residual_m": {"median": float(f"{np.median(res):.3e}"), "max": float(f"{mx:.3e}")},
+           "env_steps_above_ncp_tol": int(over), "env_steps": int(st),
+           "inverse_bytes_per_product": 4 * n * ((n + 31) // 32 * 32)}
+    x, v = b.get_state(env=0)
+    b.set_state(x, v, env=0)
+    obs = b.get_obstacles(0)
+    b.step(1)
+    x1 = b.get_state(env=0)[0]
+    b.close()
+    t1 = time.perf_counter()
+    oe = O.precompute(sc.envs[0], sc.params.h)
+    ref = O.step_lightweight(oe, x, v, obs, sc.params, newton_iterations=10, tol=0.25 * sc.params.ncp_tol)
+    L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+    err = float(np.abs(x1 - ref.x).max())
+    out["oracle_check_from_reset"] = {"env": 0, "contacts": int(ref.contacts.count), "max_abs_m": float(f"{err:.3e}"),
+                                      "max_rel": float(f"{err / max(np.abs(ref.x).max(), L):.3e}"),
+                                      "oracle_s": round(time.perf_counter() - t1, 1)}
+    log(f"slab press: env 0 against the oracle |dq| {err:.2e} ({ref.contacts.count} contacts)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -648,6 +710,7 @@ def main():
     ap.add_argument("--reset-every", type=int, default=5, help="steps between history drops in cold_starts")
     ap.add_argument("--uneven-envs", type=int, default=4096)
     ap.add_argument("--uneven-full-envs", type=int, default=1024)
+    ap.add_argument("--slab-envs", type=int, default=64)
     ap.add_argument("--fold-side", type=int, default=64, help="vertices per side of the folding sheet")
     ap.add_argument("--fold-warmup", type=int, default=20)
     ap.add_argument("--fold-steps", type=int, default=20)
@@ -799,6 +862,9 @@ def main():
 
     if "uneven_full" in arms_on:
         arms["uneven_full"] = uneven_full(F, scenes, args)
+
+    if "slab_press" in arms_on:
+        arms["slab_press"] = slab_press(F, scenes, torch, args)
 
     if "contact_metric" in arms_on:
         arms["contact_metric"] = metric_compare(F, scenes, args)

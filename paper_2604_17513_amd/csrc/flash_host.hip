@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -266,7 +267,13 @@ void system_inverse(const flash_env_desc& d, HostEnv& H, double h, int nthreads)
       }
   }
   // Crout factorisation in place
+  const bool progress = n >= 20000 && std::getenv("FLASH_PROGRESS") != nullptr;
+  const int step = std::max(1, n / 20);
   for (int i = 0; i < n; ++i) {
+    if (progress && i % step == 0) {
+      std::fprintf(stderr, "flash: Cholesky factor of a %d-vertex env: row %d (%d%%)\n", n, i, 100 * i / n);
+      std::fflush(stderr);
+    }
     for (int j = first[i]; j <= i; ++j) {
       double s = at(i, j);
       const int k0 = std::max(first[i], first[j]);
@@ -280,11 +287,17 @@ void system_inverse(const flash_env_desc& d, HostEnv& H, double h, int nthreads)
   }
   H.Ginv.assign((size_t)n * n, 0.0);
   std::atomic<int> next(0);
+  // FLASH_PROGRESS set: envs of 20,000 vertices or more report every 5% of their rows and columns
+  // on stderr (their factor and inverse take minutes on the host)
   auto worker = [&]() {
     std::vector<double> y(n);
     for (;;) {
       const int c = next.fetch_add(1);
       if (c >= n) break;
+      if (progress && c % step == 0) {
+        std::fprintf(stderr, "flash: explicit inverse of a %d-vertex env: column %d (%d%%)\n", n, c, 100 * c / n);
+        std::fflush(stderr);
+      }
       // L y = e_c
       y[c] = 1.0 / at(c, c);
       for (int i = c + 1; i < n; ++i) {
@@ -686,7 +699,7 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
   }
   if (B.lite_global) {
     // row-split work list of the global-memory lightweight route: every block (column tile, split
-    // of at most kSplitRows rows) of every env; an env's splits cover the most rows either product
+    // of split_rows rows) of every env; an env's splits cover the most rows either product
     // reads (its vertices, or its contact capacity).  Workgroups are dealt to the 8 XCDs round-robin,
     // so the list runs over groups of 8 consecutive blocks and gives every env the group's 8 blocks
     // in a row: block b always lands on XCD b mod 8, and all envs read it close together in time
@@ -698,8 +711,9 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
     int64_t ptot = 0;
     for (int e = 0; e < ne; ++e) {
       const int n = H[e].n;
-      const int rows = std::max(n, std::min(B.cap, kCacheSlots * n));
-      nsplit[e] = (rows + kSplitRows - 1) / kSplitRows;
+      const int rows = split_cover(n, B.cap);
+      const int R = split_rows(rows);
+      nsplit[e] = (rows + R - 1) / R;
       poff[e] = ptot;
       ptot += (int64_t)nsplit[e] * 3 * n;
     }
@@ -736,7 +750,7 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
   {
     // one env at a time: its inverse (FP64, host), converted and uploaded, then freed, so that the
     // host holds one inverse at a time whatever the batch
-    const int nth = std::max(1u, std::thread::hardware_concurrency());
+    const int nth = std::max(1, std::min(64, (int)std::thread::hardware_concurrency()));
     std::vector<T> blk;
     for (int e = 0; e < ne; ++e) {
       if (H[e].twin >= 0) continue;

@@ -29,11 +29,26 @@ struct GemvSchedule {
 template <class T> constexpr int gemv_tile(int vw) { return 64 * (int)((8 << vw) / sizeof(T)); }
 
 // Row-split explicit-inverse products of the global-memory lightweight route: each workgroup sums
-// at most kSplitRows rows for one column tile of 64 x 16 bytes into a partial, and a merge pass adds
-// an env's partials in split order.  The split depends only on the env's own sizes, so an env gives
-// the same bits alone or in any batch.
-constexpr int kSplitRows = 512;
+// one split of an env's rows (split_rows) for one column tile of 64 x 16 bytes into a partial, and a
+// merge pass adds an env's partials in split order.  The split depends only on the env's own sizes,
+// so an env gives the same bits alone or in any batch.
+constexpr int kSplitRows = 512;   // rows staged in LDS at a time; the least rows per split
+constexpr int kMaxSplits = 16;    // splits per env beyond which the splits grow instead
 template <class T> constexpr int split_tile() { return 64 * (int)(16 / sizeof(T)); }
+// Rows per split of an env whose products read at most `rows` rows: kSplitRows, or larger (a
+// multiple of kSplitRows) so that there are at most about kMaxSplits splits.  A function of the
+// env's own sizes only.
+__host__ __device__ inline int split_rows(int rows) {
+  const int per = (rows + kMaxSplits - 1) / kMaxSplits;
+  const int r = (per + kSplitRows - 1) / kSplitRows * kSplitRows;
+  return r > kSplitRows ? r : kSplitRows;
+}
+// The most rows an env's products read: its vertices (the apply) or its contact rows (position
+// update), at most kCacheSlots per vertex.
+__host__ __device__ inline int split_cover(int n, int cap) {
+  const int c = cap < kCacheSlots * n ? cap : kCacheSlots * n;
+  return n > c ? n : c;
+}
 struct SplitSchedule {
   const int4* items;       // (env, first column, split, 0) per workgroup
   int n_items;

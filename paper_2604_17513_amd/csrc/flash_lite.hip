@@ -170,29 +170,34 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
   const int n = B.voff[e + 1] - v0;
   const int ld = B.gld[e];
   const int nrows = ROWS ? B.ccount[e] : n;
-  const int r0 = split * kSplitRows;
+  const int R = split_rows(split_cover(n, B.cap));
+  const int r0 = split * R;
   if (r0 >= nrows) return;   // the merge reads only the splits that hold rows
-  const int nr = min(kSplitRows, nrows - r0);
+  const int r1 = min(r0 + R, nrows);
   const T* G = B.G + B.goff[e];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col0 = tile0 + lane * VW;
+  T acc[VW][3];
+  for (int q = 0; q < VW; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0;
+  // the split's rows in chunks of kSplitRows staged in LDS, summed in row order per wave
+  for (int c0 = r0; c0 < r1; c0 += kSplitRows) {
+  const int nr = min(kSplitRows, r1 - c0);
+  __syncthreads();
   for (int r = threadIdx.x; r < nr; r += kBlock) {
     if (ROWS) {
-      const size_t j = (size_t)e * B.cap + r0 + r;
+      const size_t j = (size_t)e * B.cap + c0 + r;
       s_row[r] = B.cvert[j];
       s_vec[r] = B.cforce[3 * j];
       s_vec[kSplitRows + r] = B.cforce[3 * j + 1];
       s_vec[2 * kSplitRows + r] = B.cforce[3 * j + 2];
     } else {
-      s_row[r] = r0 + r;
-      s_vec[r] = B.b[v0 + r0 + r];
-      s_vec[kSplitRows + r] = B.b[B.NV + v0 + r0 + r];
-      s_vec[2 * kSplitRows + r] = B.b[2 * B.NV + v0 + r0 + r];
+      s_row[r] = c0 + r;
+      s_vec[r] = B.b[v0 + c0 + r];
+      s_vec[kSplitRows + r] = B.b[B.NV + v0 + c0 + r];
+      s_vec[2 * kSplitRows + r] = B.b[2 * B.NV + v0 + c0 + r];
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  const int col0 = tile0 + lane * VW;
-  T acc[VW][3];
-  for (int q = 0; q < VW; ++q) acc[q][0] = acc[q][1] = acc[q][2] = 0;
   if (col0 < ld) {   // ld is a multiple of 32 columns: a lane's VW columns lie inside the row
     for (int rb = wid; rb < nr; rb += WS * UNROLL) {
       vec_t g[UNROLL];
@@ -215,6 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
         }
       }
     }
+  }
   }
   // fixed-order reduction over the waves
   if (wid > 0)
@@ -246,7 +252,8 @@ __global__ void __launch_bounds__(kBlock) k_gemv_merge(DevBatch<T> B, const int*
   const int v0 = B.voff[e];
   const int n = B.voff[e + 1] - v0, col = i - v0;
   const int nrows = ROWS ? B.ccount[e] : n;
-  const int ns = (nrows + kSplitRows - 1) / kSplitRows;
+  const int R = split_rows(split_cover(n, B.cap));
+  const int ns = (nrows + R - 1) / R;
   const T* P = partial + poff[e];
   const T hh = (T)(B.h * B.h);
   for (int k = 0; k < 3; ++k) {

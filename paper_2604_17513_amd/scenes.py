@@ -325,6 +325,32 @@ def cloth_fold(n_envs: int = 1, n: int = 64, side: float = 0.6, lg_iterations: i
                  grippers=[[g.copy() for g in grips] for _ in range(n_envs)])
 
 
+def slab_press(n_envs: int = 64, nx: int = 100, ny: int = 9, nz: int = 100, hex_size: float = 0.005,
+               press_speed: float = 0.02, indent: float = 0.005, lg_iterations: int = 10,
+               inner_iterations: int = 10) -> Scene:
+    """The large-scene recipe (about 100k vertices, 540k tets, at most 20k contacts per env).
+
+    A slab of nx x ny x nz hexes of hex_size (0.5 x 0.045 x 0.5 m at the defaults: 102,010 vertices,
+    540,000 tets; E 1e5 Pa, nu 0.3, 1000 kg/m^3, mu 0.5) rests 1 mm above the ground.  Two box finger
+    pads, each covering a little under half of the top face (their x half-extent is a quarter of the
+    slab minus 1.5 hexes, so that with the ground contacts every env stays at or below 20,000
+    contacts), start 1 mm above it and press down at press_speed until they are `indent` into the
+    slab, then hold.  h = 1/60 s; budget lg_iterations x inner_iterations; every env the same copy."""
+    sx, sy, sz = nx * hex_size, ny * hex_size, nz * hex_size
+    rest, tets = hex_lattice(nx, ny, nz, (sx, sy, sz), (-sx / 2, 0.0, -sz / 2))
+    x0 = rest + np.array([0.0, 1e-3, 0.0])
+    env = EnvDesc(TET, rest, tets, density=1000.0, young=1e5, poisson=0.3, mu=0.5)
+    top = sy + 1e-3
+    half = (sx / 4 - 1.5 * hex_size, 0.01, sz / 2 - 0.5 * hex_size)
+    steps = int(round((1e-3 + indent) / press_speed * 60.0))
+    def obstacles():
+        return [ground()] + [box((c * sx / 4, top + 1e-3 + half[1], 0.0), half, vel=(0.0, -press_speed, 0.0),
+                                 move_steps=steps) for c in (-1.0, 1.0)]
+    params = Params(lg_iterations=lg_iterations, max_inner_iterations=inner_iterations)
+    return Scene([env] * n_envs, [x0.copy() for _ in range(n_envs)], [np.zeros_like(x0) for _ in range(n_envs)],
+                 [obstacles() for _ in range(n_envs)], params, name="slab_press")
+
+
 def single_tet_scene(kind: str = "ground", seed: int = 0, tang_speed: float = 0.2) -> Scene:
     """Tiny scenes for brute-force enumeration of contact modes (1-3 contacts)."""
     rng = np.random.default_rng(seed)

@@ -293,3 +293,32 @@ def test_cloth_fold_matches_oracle_and_shares_the_inverse():
     xe = b.split(b.get_state()[0])
     assert np.array_equal(xe[0], xe[1]) and np.array_equal(xe[0], xe[2])
     assert np.array_equal(xe[0], one.get_state()[0])
+
+
+def test_pressed_slab_with_large_splits_matches_oracle():
+    """The large-scene recipe at reduced size (a 40 x 5 x 40-hex slab: 10,086 vertices, so each
+    row split of the inverse products spans two LDS chunks) pressed by two pads, two identical envs
+    sharing one inverse: FP32 lightweight steps from a history reset match the oracle within 1e-5
+    relative, and both envs give the same bits."""
+    F = _F()
+    sc = scenes.slab_press(2, nx=40, ny=5, nz=40)
+    p = sc.params
+    oe = O.precompute(sc.envs[0], p.h)
+    b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, global_contact_solve=1, max_contacts=6000,
+                     use_graph=True)
+    L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
+    b.step(6)
+    x, v = b.get_state()
+    b.set_state(x, v)
+    xs, vs = b.split(x), b.split(v)
+    obs = b.get_obstacles(0)
+    b.step(1)
+    x1 = b.split(b.get_state()[0])
+    ref = O.step_lightweight(oe, xs[0], vs[0], obs, p, newton_iterations=p.max_inner_iterations,
+                             tol=0.25 * p.ncp_tol)
+    err = float(np.abs(x1[0] - ref.x).max())
+    _say(f"pressed slab: {sc.envs[0].n_vertices} vertices, contacts {ref.contacts.count}, max|dq| {err:.3e}, "
+         f"oracle residual {ref.residual:.2e}")
+    assert ref.contacts.count > 1681
+    assert err <= 1e-5 * max(np.abs(ref.x).max(), L)
+    assert np.array_equal(x1[0], x1[1])
