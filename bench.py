@@ -685,7 +685,9 @@ def slab_press(F, scenes, torch, args):
     b.close()
     t1 = time.perf_counter()
     oe = O.precompute(sc.envs[0], sc.params.h)
-    ref = O.step_lightweight(oe, x, v, obs, sc.params, newton_iterations=10, tol=0.25 * sc.params.ncp_tol)
+    log(f"slab press: oracle precompute {time.perf_counter() - t1:.0f}s")
+    ref = O.step_lightweight(oe, x, v, obs, sc.params, newton_iterations=10, tol=0.25 * sc.params.ncp_tol,
+                             progress=lambda k: log(f"slab press: oracle local-global iteration {k} done"))
     L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
     err = float(np.abs(x1 - ref.x).max())
     out["oracle_check_from_reset"] = {"env": 0, "contacts": int(ref.contacts.count), "max_abs_m": float(f"{err:.3e}"),

@@ -928,10 +928,11 @@ def _contact_force_field(oe: OracleEnv, contacts: Contacts, lam):
 
 
 def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: int, tol: float = 0.0,
-                     lam_warm=None, grippers=None, held=None) -> StepResult:
+                     lam_warm=None, grippers=None, held=None, progress=None) -> StepResult:
     """One time step in the fixed-budget lightweight mode described above (K = params.lg_iterations,
     N = newton_iterations).  info['newton'] counts the multiplier updates, info['lam_history'] holds
-    the multipliers after each update."""
+    the multipliers after each update.  progress (optional) is called with the index of each finished
+    local-global iteration (large scenes take minutes)."""
     h = float(params.h)
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
@@ -978,6 +979,8 @@ def step_lightweight(oe: OracleEnv, x, v, obstacles, params, newton_iterations: 
                 info["lam_history"].append(lam.copy())
             info["csp_residuals"].append(r)
         q = oe.solve(b + h * h * _contact_force_field(oe, contacts, lam))
+        if progress is not None:
+            progress(k)
     xn = q
     vn = (q - x) / h
     impulse = h * np.einsum("jia,ja->ji", Fr, lam) if c else np.zeros((0, 3))
