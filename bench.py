@@ -653,14 +653,20 @@ def slab_press(F, scenes, torch, args):
     create_s = time.perf_counter() - t0
     footprint = free0 - torch.cuda.mem_get_info()[0]
     log(f"slab press: created {ne} envs in {create_s:.1f}s, HBM footprint {footprint / 1e9:.1f} GB")
-    b.step(args.warmup)
-    b.synchronize()
+    for s_ in range(args.warmup):
+        t = time.perf_counter()
+        b.step(1)
+        b.synchronize()
+        log(f"slab press: warm-up step {s_} {time.perf_counter() - t:.2f}s")
     b.residual_history(reset=True)
-    t = time.perf_counter()
-    b.step(args.steps)
-    b.synchronize()
-    dt = (time.perf_counter() - t) / args.steps
-    log(f"slab press: {1e3 * dt:.1f} ms/step")
+    per = []
+    for s_ in range(args.steps):
+        t = time.perf_counter()
+        b.step(1)
+        b.synchronize()
+        per.append(time.perf_counter() - t)
+        log(f"slab press: timed step {s_} {per[-1]:.2f}s")
+    dt = float(np.mean(per))
     mx, over, newton, st = b.residual_history(reset=True, full=True)
     stats = b.stats()
     cts = np.array([s_["contacts"] for s_ in stats])
@@ -683,6 +689,15 @@ def slab_press(F, scenes, torch, args):
     b.step(1)
     x1 = b.get_state(env=0)[0]
     b.close()
+    if args.slab_dump:
+        # the oracle check of this state runs elsewhere (it takes minutes): env 0's state, its next
+        # GPU step and the obstacles at that step
+        np.savez(args.slab_dump, x=x, v=v, x1=x1, kind=np.array([o.kind for o in obs]),
+                 center=np.array([o.center for o in obs]), rot=np.array([o.rot for o in obs]),
+                 size=np.array([o.size for o in obs]), vel=np.array([o.lin_vel for o in obs]),
+                 move=np.array([o.move_steps for o in obs]))
+        out["oracle_check_from_reset"] = {"state_written_to": args.slab_dump}
+        return out
     t1 = time.perf_counter()
     oe = O.precompute(sc.envs[0], sc.params.h)
     log(f"slab press: oracle precompute {time.perf_counter() - t1:.0f}s")
@@ -713,6 +728,7 @@ def main():
     ap.add_argument("--uneven-envs", type=int, default=4096)
     ap.add_argument("--uneven-full-envs", type=int, default=1024)
     ap.add_argument("--slab-envs", type=int, default=64)
+    ap.add_argument("--slab-dump", default="", help="write env 0's state for an offline oracle check instead")
     ap.add_argument("--fold-side", type=int, default=64, help="vertices per side of the folding sheet")
     ap.add_argument("--fold-warmup", type=int, default=20)
     ap.add_argument("--fold-steps", type=int, default=20)
