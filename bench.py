@@ -988,7 +988,8 @@ def main():
         over_step = overhead_bytes(sc.envs, contacts, K)
         achieved = per_step / (f_avg * 1e-3) / 1e9
         csrc = os.path.join(ROOT, "paper_2604_17513_amd", "csrc")
-        fused_hash = source_hash(os.path.join(csrc, "flash_kernels.hip"), os.path.join(csrc, "flash_device.h"))
+        fused_hash = source_hash(os.path.join(csrc, "flash_kernels.hip"), os.path.join(csrc, "flash_device.h"),
+                                 os.path.join(csrc, "flash_contact.h"))
         traffic = committed_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_lg_fused_squeeze_blocks_1024.md"),
                                     fused_hash) if args.envs == 1024 else None
         out["roofline"] = {
