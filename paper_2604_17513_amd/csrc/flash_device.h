@@ -45,6 +45,8 @@ struct DevBatch {
   int lite_global;            // 1: the lightweight update runs from global memory (k_lite_update)
   int* lite_done;             // [n_envs] the env's lightweight iteration stopped in this local-global
                               // iteration (tolerance or budget); its position updates are skipped
+  unsigned long long* lite_r; // [n_envs x lg_iterations x (max_newton + 1)] residual of each update of
+                              // the step (bits of a non-negative double, combined by atomic maximum)
 
   const int* voff;            // [n_envs+1]
   const int* toff;            // [n_envs+1]

@@ -442,7 +442,7 @@ struct flash_batch {
       // lightweight update from global memory: per local-global iteration the free displacement
       // z = Gbar b, then alternately u = z + h^2 Gbar H^T lambda (envs still iterating) and one
       // update of every vertex group; the last residual evaluation only decides
-      launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, -1, 0, stream); });
+      launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, 0, -1, 0, stream); });
       const int N = B.max_newton;
       for (int k = 0; k < p.lg_iterations; ++k) {
         launch(K_PROJECT, [&] { launch_project<T>(B, stream); });
@@ -450,7 +450,7 @@ struct flash_batch {
         launch(K_APPLY, [&] { launch_split_apply<T>(B, split, stream); });
         launch(K_CORRECT, [&] { launch_split_correct<T>(B, split, nullptr, stream); });
         for (int it = 0; it <= N; ++it) {
-          launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, it, k == 0 ? 1 : 0, stream); });
+          launch(K_CSP, [&] { launch_lite_update<T>(B, mu_d, k, it, k == 0 ? 1 : 0, stream); });
           if (it < N) launch(K_CORRECT, [&] { launch_split_correct<T>(B, split, B.lite_done, stream); });
         }
         if (k == 0 && ws_record) launch(K_MLP, [&] { launch_ws_labels<T>(B, mlp.feat, ws_lab, stream); });
@@ -541,7 +541,9 @@ struct flash_batch {
 
   void step(int n) {
     if (!tuned) {
-      if (!p.fixed_schedule) { if (fp64) autotune(bd); else autotune(bf); }
+      // the global-memory lightweight route runs the row-split products, not the tuned ones
+      const bool split_route = fp64 ? bd.lite_global : bf.lite_global;
+      if (!p.fixed_schedule && !split_route) { if (fp64) autotune(bd); else autotune(bf); }
       tuned = true;
     }
     if (p.use_graph && !timing) {
@@ -852,6 +854,7 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
   B.scr = dalloc<unsigned char>(B.lite_global ? 1 : ne * cap * 16 * cts, own);
   B.lite_done = dalloc<int>(ne, own);
   HIPCHK(hipMemset(B.lite_done, 0, ne * sizeof(int)));
+  B.lite_r = dalloc<unsigned long long>(B.lite_global ? (size_t)ne * B.lg_iterations * (B.max_newton + 1) : 1, own);
   B.cyf = dalloc<unsigned char>(3 * ne * cap * cts, own);
   B.lust = dalloc<int>(4 * ne, own);
   HIPCHK(hipMemset(B.lust, 0, 4 * ne * sizeof(int)));

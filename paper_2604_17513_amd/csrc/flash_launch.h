@@ -64,9 +64,10 @@ template <class T> void launch_csp(const DevBatch<T>& B, const T* mu_env, int fi
 // skip (optional): envs with skip[e] != 0 keep their u
 template <class T> void launch_correct(const DevBatch<T>& B, const GemvSchedule& S, hipStream_t s,
                                        const int* skip = nullptr);
-// lightweight update in global memory: it = -1 prepares the warm start's forces, it >= 0 is
-// the (it + 1)-th residual evaluation of the local-global iteration (an update unless done)
-template <class T> void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int it, int first_lg,
+// lightweight update in global memory: it = -1 prepares the warm start's forces (once per step),
+// it >= 0 is the (it + 1)-th residual evaluation of local-global iteration k (an update unless the
+// iteration stops)
+template <class T> void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int k, int it, int first_lg,
                                            hipStream_t s);
 // The whole local-global loop of a step, one workgroup per env (bitwise equal to the
 // kernel-per-phase sequence project, assemble, apply, csp, correct repeated K times).

@@ -5,8 +5,9 @@
 // of Alg. 1, formed by the explicit-inverse product over the contact rows), evaluates Phi and its
 // generalized-Jacobian blocks at Y = F^T u per contact, and takes lambda <- lambda + delta with
 // (K W~ + E) delta = -Phi per vertex, W~ = h^2 H M^-1 H^T.  The metric couples only the contacts
-// of one vertex, so every vertex group is updated by one thread from global memory; one
-// workgroup per env reduces the env's residual.  The contact displacement follows lambda through
+// of one vertex, so every vertex group is updated by one thread from global memory; the env's
+// residual is reduced over chunks of contacts first (one launch), then the update decides and
+// updates (a second launch), both spread over (chunks, envs).  The contact displacement follows lambda through
 // the global apply instead of the contact-space Delassus operator, so no cap x cap matrix exists.
 #include <hip/hip_runtime.h>
 
@@ -30,65 +31,97 @@ __device__ __forceinline__ double wg_max(double v, double* sh) {
   return m;
 }
 
-// One workgroup per env.  it = -1 (once per step, after detection): world forces F lambda of
-// the warm start, which the first position update reads.  it >= 0 counts the updates already
-// taken in this local-global iteration: the update evaluates the FP64 residual at (u, lambda) and
-// stops the env's iteration (done flag) when it is at inner_tol or `it` reached the budget;
-// otherwise it updates every vertex group.  The done flag is cleared by the iteration's first
-// call (it == 0).
+// Residual of contact j at (u, lambda), FP64, at the residual scale s = h^2 / m_v.
 template <class T, class CT>
-__global__ void __launch_bounds__(kBlock) k_lite_update(DevBatch<T> B, const T* mu_env, int it, int first_lg) {
+__device__ __forceinline__ double lite_residual(const DevBatch<T>& B, size_t cb, int j, const CT* Fr, int v0, CT mu) {
+  const int NV = B.NV;
+  const CT* F = Fr + 9 * j;
+  const int vi = v0 + B.cvert[cb + j];
+  const double uw0 = (double)B.u[vi], uw1 = (double)B.u[NV + vi], uw2 = (double)B.u[2 * NV + vi];
+  double Y[3];
+  for (int a = 0; a < 3; ++a) Y[a] = (double)F[3 * a] * uw0 + (double)F[3 * a + 1] * uw1 + (double)F[3 * a + 2] * uw2;
+  const double s = (double)B.cs[cb + j];
+  const double* lj = B.clam + 3 * (cb + j);
+  const double cnd = B.cd0d[cb + j] + Y[0];
+  const double ut1 = Y[1] - (double)B.cdob[2 * (cb + j)], ut2 = Y[2] - (double)B.cdob[2 * (cb + j) + 1];
+  const bool att = B.cobs[cb + j] >= kMaxObs;
+  const double pn = att ? cnd : fmin(cnd, s * lj[0]);
+  const double z1 = lj[1] - ut1 / s, z2 = lj[2] - ut2 / s;
+  const double nz = sqrt(z1 * z1 + z2 * z2);
+  const double rh = (double)mu * fmax(lj[0], 0.0);
+  double q1 = z1, q2 = z2;
+  if (!att && nz > rh) { const double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
+  const double t1 = s * (lj[1] - q1), t2 = s * (lj[2] - q2);
+  const double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
+  return rj == rj ? rj : INFINITY;
+}
+
+template <class T, class CT>
+__device__ __forceinline__ const CT* lite_frames(const DevBatch<T>& B, size_t cb) {
+  if constexpr (std::is_same<CT, T>::value) return B.cframe + 9 * cb;
+  else return B.cframe64 + 9 * cb;
+}
+
+// Once per step, after detection: world forces F lambda of the warm start (the first position
+// update reads them); the env's residual slots cleared; its iteration not stopped.  Grid: (chunks of
+// kBlock contacts, envs).
+template <class T, class CT>
+__global__ void __launch_bounds__(kBlock) k_lite_prepare(DevBatch<T> B) {
+  const int e = blockIdx.y;
+  const int c = B.ccount[e];
+  const size_t cb = (size_t)e * B.cap;
+  const CT* Fr = lite_frames<T, CT>(B, cb);
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < c) {
+    const CT* F = Fr + 9 * j;
+    const double* lj = B.clam + 3 * (cb + j);
+    const CT l0 = (CT)lj[0], l1 = (CT)lj[1], l2 = (CT)lj[2];
+    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
+  }
+  if (blockIdx.x == 0) {
+    const int ns = B.lg_iterations * (B.max_newton + 1);
+    for (int q = threadIdx.x; q < ns; q += kBlock) B.lite_r[(size_t)e * ns + q] = 0ull;
+    if (threadIdx.x == 0) B.lite_done[e] = 0;
+  }
+}
+
+// The env's residual at (u, lambda): each workgroup reduces one chunk of kBlock contacts and folds
+// its maximum into the env's slot for this update (non-negative doubles order like their bits, so an
+// integer atomic maximum gives the exact maximum whatever the order).
+template <class T, class CT>
+__global__ void __launch_bounds__(kBlock) k_lite_residual(DevBatch<T> B, const T* mu_env, int slot, int it) {
   __shared__ double sh_red[kBlock / 64];
-  const int e = blockIdx.x;
+  const int e = blockIdx.y;
   if (it > 0 && B.lite_done[e]) return;
   const int c = B.ccount[e];
-  const int tid = threadIdx.x;
+  const int j0 = blockIdx.x * kBlock;
+  if (j0 >= c) return;
   const size_t cb = (size_t)e * B.cap;
+  const CT* Fr = lite_frames<T, CT>(B, cb);
   const int v0 = B.voff[e];
-  const int NV = B.NV;
-  const CT* Fr;
-  if constexpr (std::is_same<CT, T>::value) Fr = B.cframe + 9 * cb;
-  else Fr = B.cframe64 + 9 * cb;
-  const int* cv = B.cvert + cb;
-  const int* cobs = B.cobs + cb;
   const CT mu = (CT)mu_env[e];
-  if (it < 0) {
-    for (int j = tid; j < c; j += kBlock) {
-      const CT* F = Fr + 9 * j;
-      const double* lj = B.clam + 3 * (cb + j);
-      const CT l0 = (CT)lj[0], l1 = (CT)lj[1], l2 = (CT)lj[2];
-      for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
-    }
-    if (tid == 0) B.lite_done[e] = 0;
-    return;
-  }
-  // residual at the residual scale s = h^2 / m_v (FP64)
-  double rloc = 0.0;
-  for (int j = tid; j < c; j += kBlock) {
-    const CT* F = Fr + 9 * j;
-    const int vi = v0 + cv[j];
-    const double uw0 = (double)B.u[vi], uw1 = (double)B.u[NV + vi], uw2 = (double)B.u[2 * NV + vi];
-    double Y[3];
-    for (int a = 0; a < 3; ++a) Y[a] = (double)F[3 * a] * uw0 + (double)F[3 * a + 1] * uw1 + (double)F[3 * a + 2] * uw2;
-    const double s = (double)B.cs[cb + j];
-    const double* lj = B.clam + 3 * (cb + j);
-    const double cnd = B.cd0d[cb + j] + Y[0];
-    const double ut1 = Y[1] - (double)B.cdob[2 * (cb + j)], ut2 = Y[2] - (double)B.cdob[2 * (cb + j) + 1];
-    const bool att = cobs[j] >= kMaxObs;
-    const double pn = att ? cnd : fmin(cnd, s * lj[0]);
-    const double z1 = lj[1] - ut1 / s, z2 = lj[2] - ut2 / s;
-    const double nz = sqrt(z1 * z1 + z2 * z2);
-    const double rh = (double)mu * fmax(lj[0], 0.0);
-    double q1 = z1, q2 = z2;
-    if (!att && nz > rh) { const double f = nz > 0 ? rh / nz : 0.0; q1 = f * z1; q2 = f * z2; }
-    const double t1 = s * (lj[1] - q1), t2 = s * (lj[2] - q2);
-    double rj = fmax(fabs(pn), sqrt(t1 * t1 + t2 * t2));
-    if (!(rj == rj)) rj = INFINITY;
-    rloc = fmax(rloc, rj);
-  }
+  const int j = j0 + threadIdx.x;
+  const double rloc = j < c ? lite_residual<T, CT>(B, cb, j, Fr, v0, mu) : 0.0;
   const double r = wg_max(rloc, sh_red);
+  if (threadIdx.x == 0) {
+    const int ns = B.lg_iterations * (B.max_newton + 1);
+    atomicMax(&B.lite_r[(size_t)e * ns + slot], (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// Decision and update: the env's iteration stops (done flag, counters, not-converged flag) when its
+// residual is at inner_tol or `it` reached the budget; otherwise every vertex group whose first
+// contact lies in this workgroup's chunk takes one update.
+template <class T, class CT>
+__global__ void __launch_bounds__(kBlock) k_lite_apply(DevBatch<T> B, const T* mu_env, int slot, int it, int first_lg) {
+  const int e = blockIdx.y;
+  if (it > 0 && B.lite_done[e]) return;
+  const int c = B.ccount[e];
+  const int ns = B.lg_iterations * (B.max_newton + 1);
+  const double r = __longlong_as_double((long long)B.lite_r[(size_t)e * ns + slot]);
+  const int tid = threadIdx.x;
   if (r <= B.tol || it >= B.max_newton) {
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
       B.lite_done[e] = 1;
       B.iters[e] += it;
       if (B.phase) {
@@ -102,49 +135,55 @@ __global__ void __launch_bounds__(kBlock) k_lite_update(DevBatch<T> B, const T* 
     }
     return;
   }
-  if (it == 0 && tid == 0) B.lite_done[e] = 0;
+  if (it == 0 && blockIdx.x == 0 && tid == 0) B.lite_done[e] = 0;
+  const int j = blockIdx.x * kBlock + tid;
+  if (j >= c) return;
+  const size_t cb = (size_t)e * B.cap;
+  const int* cv = B.cvert + cb;
+  if (j > 0 && cv[j - 1] == cv[j]) return;   // not the first contact of its vertex
+  const CT* Fr = lite_frames<T, CT>(B, cb);
+  const int* cobs = B.cobs + cb;
+  const int v0 = B.voff[e];
+  const int NV = B.NV;
+  const CT mu = (CT)mu_env[e];
   const double dmaxf = B.max_force;
-  // one update per vertex group (contacts are listed by vertex: a group is contiguous)
-  for (int j = tid; j < c; j += kBlock) {
-    if (j > 0 && cv[j - 1] == cv[j]) continue;
-    int m = 1;
-    while (j + m < c && cv[j + m] == cv[j] && m < kCacheSlots) ++m;
-    const int vi = v0 + cv[j];
-    const CT uw0 = (CT)B.u[vi], uw1 = (CT)B.u[NV + vi], uw2 = (CT)B.u[2 * NV + vi];
-    CT Y[3 * kCacheSlots], d0[kCacheSlots], dob[2 * kCacheSlots], dl[3 * kCacheSlots];
-    double lam[3 * kCacheSlots];
-    for (int q = 0; q < m; ++q) {
-      const CT* F = Fr + 9 * (j + q);
-      for (int a = 0; a < 3; ++a) {
-        Y[3 * q + a] = F[3 * a] * uw0 + F[3 * a + 1] * uw1 + F[3 * a + 2] * uw2;
-        lam[3 * q + a] = B.clam[3 * (cb + j + q) + a];
-      }
-      d0[q] = (CT)B.cd0[cb + j + q];
-      dob[2 * q] = (CT)B.cdob[2 * (cb + j + q)];
-      dob[2 * q + 1] = (CT)B.cdob[2 * (cb + j + q) + 1];
+  int m = 1;
+  while (j + m < c && cv[j + m] == cv[j] && m < kCacheSlots) ++m;
+  const int vi = v0 + cv[j];
+  const CT uw0 = (CT)B.u[vi], uw1 = (CT)B.u[NV + vi], uw2 = (CT)B.u[2 * NV + vi];
+  CT Y[3 * kCacheSlots], d0[kCacheSlots], dob[2 * kCacheSlots], dl[3 * kCacheSlots];
+  double lam[3 * kCacheSlots];
+  for (int q = 0; q < m; ++q) {
+    const CT* F = Fr + 9 * (j + q);
+    for (int a = 0; a < 3; ++a) {
+      Y[3 * q + a] = F[3 * a] * uw0 + F[3 * a + 1] * uw1 + F[3 * a + 2] * uw2;
+      lam[3 * q + a] = B.clam[3 * (cb + j + q) + a];
     }
-    const CT sp = (CT)B.cs[cb + j];
-    if (m == 1) {
-      CT ph[3], K[3][3], E[3][3];
-      lite_contact(sp, mu, d0[0], dob[0], dob[1], Y, lam, cobs[j] >= kMaxObs, ph, K, E);
-      // Z = sp K + E = [sp 0 0; E_tn sp I]
-      const CT dn = -ph[0] / sp;
-      dl[0] = dn;
-      dl[1] = (-ph[1] - E[1][0] * dn) / sp;
-      dl[2] = (-ph[2] - E[2][0] * dn) / sp;
-    } else {
-      lite_group_solve<CT>(m, sp, mu, Fr + 9 * j, d0, dob, Y, lam, cobs + j, dl);
+    d0[q] = (CT)B.cd0[cb + j + q];
+    dob[2 * q] = (CT)B.cdob[2 * (cb + j + q)];
+    dob[2 * q + 1] = (CT)B.cdob[2 * (cb + j + q) + 1];
+  }
+  const CT sp = (CT)B.cs[cb + j];
+  if (m == 1) {
+    CT ph[3], K[3][3], E[3][3];
+    lite_contact(sp, mu, d0[0], dob[0], dob[1], Y, lam, cobs[j] >= kMaxObs, ph, K, E);
+    // Z = sp K + E = [sp 0 0; E_tn sp I]
+    const CT dn = -ph[0] / sp;
+    dl[0] = dn;
+    dl[1] = (-ph[1] - E[1][0] * dn) / sp;
+    dl[2] = (-ph[2] - E[2][0] * dn) / sp;
+  } else {
+    lite_group_solve<CT>(m, sp, mu, Fr + 9 * j, d0, dob, Y, lam, cobs + j, dl);
+  }
+  for (int q = 0; q < m; ++q) {
+    const CT* F = Fr + 9 * (j + q);
+    double ln[3];
+    for (int a = 0; a < 3; ++a) {
+      ln[a] = fmin(fmax(lam[3 * q + a] + (double)dl[3 * q + a], -dmaxf), dmaxf);
+      B.clam[3 * (cb + j + q) + a] = ln[a];
     }
-    for (int q = 0; q < m; ++q) {
-      const CT* F = Fr + 9 * (j + q);
-      double ln[3];
-      for (int a = 0; a < 3; ++a) {
-        ln[a] = fmin(fmax(lam[3 * q + a] + (double)dl[3 * q + a], -dmaxf), dmaxf);
-        B.clam[3 * (cb + j + q) + a] = ln[a];
-      }
-      const CT l0 = (CT)ln[0], l1 = (CT)ln[1], l2 = (CT)ln[2];
-      for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j + q) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
-    }
+    const CT l0 = (CT)ln[0], l1 = (CT)ln[1], l2 = (CT)ln[2];
+    for (int k = 0; k < 3; ++k) B.cforce[3 * (cb + j + q) + k] = (T)(F[k] * l0 + F[3 + k] * l1 + F[6 + k] * l2);
   }
 }
 
@@ -291,13 +330,24 @@ template void launch_split_correct<float>(const DevBatch<float>&, const SplitSch
 template void launch_split_correct<double>(const DevBatch<double>&, const SplitSchedule&, const int*, hipStream_t);
 
 template <class T>
-void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int it, int first_lg, hipStream_t s) {
-  const dim3 g(B.n_envs), blk(kBlock);
-  if (B.csp64) hipLaunchKernelGGL((k_lite_update<T, double>), g, blk, 0, s, B, mu_env, it, first_lg);
-  else hipLaunchKernelGGL((k_lite_update<T, T>), g, blk, 0, s, B, mu_env, it, first_lg);
+void launch_lite_update(const DevBatch<T>& B, const T* mu_env, int k, int it, int first_lg, hipStream_t s) {
+  const dim3 g((unsigned)((B.cap + kBlock - 1) / kBlock), (unsigned)B.n_envs), blk(kBlock);
+  if (it < 0) {
+    if (B.csp64) hipLaunchKernelGGL((k_lite_prepare<T, double>), g, blk, 0, s, B);
+    else hipLaunchKernelGGL((k_lite_prepare<T, T>), g, blk, 0, s, B);
+    return;
+  }
+  const int slot = k * (B.max_newton + 1) + it;
+  if (B.csp64) {
+    hipLaunchKernelGGL((k_lite_residual<T, double>), g, blk, 0, s, B, mu_env, slot, it);
+    hipLaunchKernelGGL((k_lite_apply<T, double>), g, blk, 0, s, B, mu_env, slot, it, first_lg);
+  } else {
+    hipLaunchKernelGGL((k_lite_residual<T, T>), g, blk, 0, s, B, mu_env, slot, it);
+    hipLaunchKernelGGL((k_lite_apply<T, T>), g, blk, 0, s, B, mu_env, slot, it, first_lg);
+  }
 }
 
-template void launch_lite_update<float>(const DevBatch<float>&, const float*, int, int, hipStream_t);
-template void launch_lite_update<double>(const DevBatch<double>&, const double*, int, int, hipStream_t);
+template void launch_lite_update<float>(const DevBatch<float>&, const float*, int, int, int, hipStream_t);
+template void launch_lite_update<double>(const DevBatch<double>&, const double*, int, int, int, hipStream_t);
 
 }  // namespace flash
