@@ -218,9 +218,12 @@ typedef struct {
 
 /* Creates a batch of n_envs independent environments and runs the create-time
  * precompute (Alg. 1: assemble A per env and its exact inverse, in FP64 on the
- * host; masses, D_m^-1, weights).  hip_stream: a hipStream_t or NULL for a
- * stream owned by the batch.  State starts at the rest shapes with zero
- * velocity and no obstacles. */
+ * host, one env at a time; masses, D_m^-1, weights).  Envs whose mesh, material
+ * and h are equal share one inverse (host and device).  hip_stream: a
+ * hipStream_t or NULL for a stream owned by the batch.  State starts at the rest
+ * shapes with zero velocity and no obstacles.  With the environment variable
+ * FLASH_PROGRESS set, envs of 20,000 vertices or more report the progress of
+ * their factor and inverse on stderr (minutes on the host). */
 flash_status flash_create_batch(const flash_env_desc *envs, int32_t n_envs, const flash_params *p,
                                 void *hip_stream, flash_batch **out);
 flash_status flash_destroy_batch(flash_batch *b);
