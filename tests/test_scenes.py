@@ -53,3 +53,36 @@ def test_cloth_recipes_use_the_papers_parameters():
     # defaults that a new scene starts from
     p = scenes.Params()
     assert tuple(p.gravity) == tuple(g["gravity"]) and p.max_force == g["maxforce"]
+
+
+def test_cloth_fold_grippers_take_the_near_corners():
+    """Each gripper captures the near corner and its two edge neighbours (radius 1.2 spacings),
+    carries them to the midline and 3 cm up over 5 s (500 steps of 0.01 s), then holds; envs are
+    copies of one mesh."""
+    from oracle import flash_oracle as O
+    sc = scenes.cloth_fold(2, n=16, side=0.6)
+    x0 = sc.x0[0]
+    held = O.grasp_update(x0, sc.grippers[0], None)
+    assert [len(h) for h in held] == [3, 3]
+    for g in sc.grippers[0]:
+        assert g.move_steps == 500
+        np.testing.assert_allclose(g.lin_vel * 5.0, [0.0, 0.03, 0.3])
+    assert sc.params.h == 0.01 and sc.params.lg_iterations == 5 and sc.params.max_inner_iterations == 10
+    assert sc.envs[0] is sc.envs[1] and sc.envs[0].mu == 1.0
+    assert np.all(x0[:, 1] == 1e-3)
+
+
+def test_slab_press_has_the_large_scene_sizes():
+    """100 x 9 x 100 hexes of 5 mm: 102,010 vertices and 540,000 tets; at the start the ground and the
+    two pads give at most 20,000 contacts; the pads travel 6 mm (1 mm gap + 5 mm indentation) at
+    2 cm/s, then hold."""
+    from oracle import flash_oracle as O
+    sc = scenes.slab_press(1)
+    env = sc.envs[0]
+    assert env.n_vertices == 102010 and env.n_elements == 540000
+    con = O.detect(sc.x0[0], sc.v0[0], sc.obstacles[0], sc.params)
+    assert 10201 < con.count <= 20000
+    pads = sc.obstacles[0][1:]
+    for p in pads:
+        travel = p.move_steps * sc.params.h * -p.lin_vel[1]
+        assert abs(travel - 0.006) < 0.0005
