@@ -1314,8 +1314,8 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     b->NV = b->voff[n_envs];
     b->NT = b->toff[n_envs];
     std::vector<HostEnv> H(n_envs);
-    const int nth = std::max(1u, std::thread::hardware_concurrency());
-    // envs with the same mesh and material share one explicit inverse (host and device)
+    // envs with the same mesh and material share one explicit inverse (host and device); the
+    // inverses themselves are formed in build_device, one env at a time
     std::map<uint64_t, std::vector<int>> seen;
     for (int e = 0; e < n_envs; ++e) {
       if (envs[e].elem == FLASH_TET) tet_data(envs[e], H[e]); else tri_data(envs[e], H[e]);
@@ -1324,7 +1324,6 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
         if (same_model(envs[e], envs[f])) { H[e].twin = f; break; }
       if (H[e].twin < 0) seen[key].push_back(e);
     }
-    (void)nth;
     if (b->fp64) build_device<double>(b, H, envs); else build_device<float>(b, H, envs);
     // dynamic LDS limit of the contact-solve kernels
     size_t static_lds = 0;
