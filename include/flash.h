@@ -181,6 +181,13 @@ typedef struct {
                                      and max_contacts_per_env may reach 65536.  Same iteration; the
                                      two routes round differently.  With the exact metric it must
                                      be 0. */
+  int32_t twin_chunk;             /* global-memory lightweight route only: envs that share one
+                                     explicit inverse (same mesh and material) run the inverse
+                                     products in chunks of this many envs per workgroup, so that
+                                     each inverse row read serves the whole chunk.  0 (default):
+                                     automatic (8, else 4, while each product keeps at least 512
+                                     workgroups, else 1); 1: one env per workgroup; 2..8: that many.
+                                     Every choice gives the same bits. */
 } flash_params;
 
 enum { FLASH_METRIC_EXACT = 0, FLASH_METRIC_LIGHTWEIGHT = 1 };

@@ -719,15 +719,54 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
       poff[e] = ptot;
       ptot += (int64_t)nsplit[e] * 3 * n;
     }
-    std::vector<int> order(ne);
-    for (int e = 0; e < ne; ++e) order[e] = e;
+    // envs that share an inverse (twin >= 0 names the group's first env) run in chunks of up to
+    // kTwinChunk envs (k_gemv_split_twins); the others one env per workgroup (k_gemv_split)
+    std::vector<std::vector<int>> groups;
+    std::vector<int> group_of(ne, -1);
+    for (int e = 0; e < ne; ++e) {
+      if (H[e].twin < 0) { group_of[e] = (int)groups.size(); groups.push_back({e}); }
+      else groups[group_of[H[e].twin]].push_back(e);
+    }
+    // A group's chunk size is twin_chunk, or by default 8, else 4, whichever still leaves
+    // kMinTwinItems workgroups per product (fewer, longer workgroups leave CUs idle), else one env
+    // per workgroup.  Measured on the 64 x 64 folding sheet (5 x 10 budget, ms per step at chunk
+    // 1 / 4 / 8): 8 envs 3.8 / 5.4 / 7.4, 16 envs 6.2 / 5.7 / 7.5, 32 envs 10.0 / 9.5 / 7.8, 256 envs
+    // 60.2 / 52.4 / 43.2; chunks of 2 were slower than 1 at every size.
+    constexpr int kMinTwinItems = 512;
+    std::vector<int> order;       // envs run one per workgroup, largest first
+    std::vector<int> gorder;      // twin groups run in chunks, largest envs first
+    std::vector<int> gchunk(groups.size(), 1);
+    for (int g = 0; g < (int)groups.size(); ++g) {
+      const int e = groups[g][0], m = (int)groups[g].size();
+      const int per_env = (H[e].n + tile - 1) / tile * nsplit[e];
+      int c = 1;
+      if (b->p.twin_chunk > 0) {
+        c = std::min(b->p.twin_chunk, m);
+      } else {
+        for (const int cand : {kTwinChunk, 4})
+          if (m >= cand && (int64_t)((m + cand - 1) / cand) * per_env >= kMinTwinItems) { c = cand; break; }
+      }
+      gchunk[g] = c;
+      if (c == 1) order.insert(order.end(), groups[g].begin(), groups[g].end());
+      else gorder.push_back(g);
+    }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return H[a].n > H[c].n; });
+    std::stable_sort(gorder.begin(), gorder.end(),
+                     [&](int a, int c) { return H[groups[a][0]].n > H[groups[c][0]].n; });
     constexpr int kXcds = 8;
     int max_n = 0, max_split = 0;
     for (int e = 0; e < ne; ++e) { max_n = std::max(max_n, H[e].n); max_split = std::max(max_split, nsplit[e]); }
     const int nblk = (max_n + tile - 1) / tile * max_split;
-    std::vector<int4> items;
-    for (int bg = 0; bg < nblk; bg += kXcds)
+    std::vector<int4> items, titems;
+    std::vector<int> tenvs;
+    std::vector<int4> chunks;     // (first in tenvs, count, env, 0)
+    for (int g : gorder)
+      for (size_t c0 = 0; c0 < groups[g].size(); c0 += gchunk[g]) {
+        const int cnt = (int)std::min<size_t>(gchunk[g], groups[g].size() - c0);
+        chunks.push_back(make_int4((int)tenvs.size(), cnt, groups[g][0], 0));
+        tenvs.insert(tenvs.end(), groups[g].begin() + c0, groups[g].begin() + c0 + cnt);
+      }
+    for (int bg = 0; bg < nblk; bg += kXcds) {
       for (int e : order) {
         bool any = false;
         int4 grp[kXcds];
@@ -739,12 +778,35 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
         }
         if (any) items.insert(items.end(), grp, grp + kXcds);
       }
-    int4* d_items = dalloc<int4>(items.size(), own);
-    HIPCHK(hipMemcpy(d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+      for (const int4& ch : chunks) {
+        const int e = ch.z;
+        bool any = false;
+        int4 grp[kXcds];
+        for (int j = 0; j < kXcds; ++j) {
+          const int blk = bg + j, t0 = blk / max_split * tile, sp = blk % max_split;
+          const bool has = blk < nblk && t0 < H[e].n && sp < nsplit[e];
+          grp[j] = has ? make_int4(ch.x, t0, sp, ch.y) : make_int4(0, 0, 0, 0);
+          any = any || has;
+        }
+        if (any) titems.insert(titems.end(), grp, grp + kXcds);
+      }
+    }
+    int4* d_items = items.empty() ? nullptr : dalloc<int4>(items.size(), own);
+    if (!items.empty())
+      HIPCHK(hipMemcpy(d_items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice));
+    int4* d_titems = titems.empty() ? nullptr : dalloc<int4>(titems.size(), own);
+    int* d_tenvs = tenvs.empty() ? nullptr : dalloc<int>(tenvs.size(), own);
+    if (!titems.empty()) {
+      HIPCHK(hipMemcpy(d_titems, titems.data(), titems.size() * sizeof(int4), hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(d_tenvs, tenvs.data(), tenvs.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     int64_t* d_poff = dalloc<int64_t>(ne, own);
     HIPCHK(hipMemcpy(d_poff, poff.data(), ne * sizeof(int64_t), hipMemcpyHostToDevice));
     b->split.items = d_items;
     b->split.n_items = (int)items.size();
+    b->split.twin_items = d_titems;
+    b->split.n_twin_items = (int)titems.size();
+    b->split.twin_envs = d_tenvs;
     b->split.partial = dalloc<T>((size_t)ptot, own);
     b->split.poff = d_poff;
   }
@@ -1249,6 +1311,8 @@ flash_status flash_create_batch(const flash_env_desc* envs, int32_t n_envs, cons
     return fail(FLASH_ERR_INVALID_ARG, "global_contact_solve must be 0 or 1");
   if (p->global_contact_solve == 1 && !lite)
     return fail(FLASH_ERR_INVALID_ARG, "global_contact_solve = 1 needs the lightweight contact metric");
+  if (p->twin_chunk < 0 || p->twin_chunk > kTwinChunk)
+    return fail(FLASH_ERR_INVALID_ARG, "twin_chunk must be 0..8");
   if (!lite) {
     // one workgroup holds an env's contact data in LDS: the capacity must fit one CU's LDS
     // (the lightweight metric falls back to its global-memory update instead)

@@ -49,9 +49,16 @@ __host__ __device__ inline int split_cover(int n, int cap) {
   const int c = cap < kCacheSlots * n ? cap : kCacheSlots * n;
   return n > c ? n : c;
 }
+// Envs that share one inverse (identical mesh and material) run their split products in chunks of
+// up to kTwinChunk envs per workgroup: each inverse row vector loaded serves the whole chunk.
+constexpr int kTwinChunk = 8;
 struct SplitSchedule {
-  const int4* items;       // (env, first column, split, 0) per workgroup
+  const int4* items;       // (env, first column, split, 0) per workgroup, envs without a twin
   int n_items;
+  const int4* twin_items;  // (first env of the chunk in twin_envs, first column, split, envs in the
+                           // chunk; 0 pads) per workgroup, envs that share their inverse
+  int n_twin_items;
+  const int* twin_envs;    // chunks of envs sharing one inverse, in batch order within a group
   void* partial;           // T [sum over envs of splits x 3 x n]
   const int64_t* poff;     // [n_envs] element offset of each env's partials
 };

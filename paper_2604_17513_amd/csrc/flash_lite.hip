@@ -280,6 +280,182 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
   }
 }
 
+// k_gemv_split for a chunk of up to kTwinChunk envs that share one inverse.  A lane's inverse row
+// vector, loaded once, serves every env of the chunk that reads that row at that position of the
+// split: all of them in the apply, and in the position update wherever their contact rows
+// coincide (identical envs in identical states); where they differ, each env loads its own row.
+// Rows are staged kTwinRows at a time, a multiple of the wave count, so every row stays on the wave
+// k_gemv_split gives it; with its per-wave row order and its fixed-order reduction over the waves,
+// every env gets the bits it gets from k_gemv_split.  Loads are ordinary (cached): the other chunks
+// of a group read the same rows on the same XCD close in time.
+constexpr int kTwinRows = 128;
+template <class T, bool ROWS>
+__global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, const int4* items, const int* envs,
+                                                             const int* skip, T* partial, const int64_t* poff) {
+  constexpr int VW = (int)(16 / sizeof(T));
+  constexpr int TILE = 64 * VW;
+  constexpr int UNROLL = 4;
+  constexpr int WS = kBlock / 64;
+  constexpr int EB = kTwinChunk;
+  constexpr int SR = kTwinRows;
+  static_assert(kSplitRows % SR == 0 && SR % (WS * UNROLL) == 0, "staging must keep every row on its wave");
+  static_assert(UNROLL == 4, "a wave reads its rows' shared indices as one int4");
+  // s_one holds row r at perm_row(r): a wave's UNROLL rows rb + WS * u (rb = wave + WS * UNROLL * k)
+  // lie side by side from perm_row(rb) on
+  auto perm_row = [](int r) { return r / (WS * UNROLL) * (WS * UNROLL) + r % WS * UNROLL + r / WS % UNROLL; };
+  typedef T vec_t __attribute__((ext_vector_type(VW)));
+  typedef T f4_t __attribute__((ext_vector_type(4)));
+  __shared__ f4_t s_vec[SR * EB];   // [row][env] the env's right-hand side at this position, 0 if none
+  __shared__ int s_row[SR * EB];    // [row][env] inverse row the env reads at this position, -1 if none
+  __shared__ __align__(16) int s_one[SR];   // the row every reading env reads (rows permuted, below)
+  __shared__ int s_mixed;           // some position has envs reading different rows
+  __shared__ T s_red[(WS - 1) * 3 * TILE];
+  __shared__ int s_e[EB], s_r1[EB];
+  const int4 item = items[blockIdx.x];
+  if (item.w <= 0) return;   // padding item
+  const int tile0 = item.y, split = item.z, w = item.w;
+  const int e0 = envs[item.x];
+  const int n = B.voff[e0 + 1] - B.voff[e0];   // the same mesh, inverse and split size for the chunk
+  const int ld = B.gld[e0];
+  const int R = split_rows(split_cover(n, B.cap));
+  const int r0 = split * R;
+  if (threadIdx.x < EB) {
+    int e = -1, r1 = r0;
+    if ((int)threadIdx.x < w) {
+      e = envs[item.x + threadIdx.x];
+      const int nrows = ROWS ? B.ccount[e] : n;
+      if (!(skip && skip[e]) && r0 < nrows) r1 = min(r0 + R, nrows);
+    }
+    s_e[threadIdx.x] = e;
+    s_r1[threadIdx.x] = r1;
+  }
+  __syncthreads();
+  int r1m = r0;
+  for (int t = 0; t < EB; ++t) r1m = max(r1m, s_r1[t]);
+  if (r1m == r0) return;   // no env of the chunk reads rows in this split (uniform over the block)
+  const T* G = B.G + B.goff[e0];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int col0 = tile0 + lane * VW;
+  T acc[EB][VW][3];
+#pragma unroll
+  for (int t = 0; t < EB; ++t)
+#pragma unroll
+    for (int q = 0; q < VW; ++q) acc[t][q][0] = acc[t][q][1] = acc[t][q][2] = 0;
+  for (int c0 = r0; c0 < r1m; c0 += SR) {
+    const int nrm = min(SR, r1m - c0);
+    __syncthreads();
+    if (threadIdx.x == 0) s_mixed = 0;
+    // all SR x EB slots are written: an env that reads no row at a position (past its rows, past
+    // the chunk's envs) gets row -1 and a zero right-hand side
+    for (int idx = threadIdx.x; idx < SR * EB; idx += kBlock) {
+      const int r = idx / EB, t = idx - r * EB;
+      const int e = s_e[t];
+      int row = -1;
+      f4_t f = {0, 0, 0, 0};
+      if (e >= 0 && r < nrm && c0 + r < s_r1[t]) {
+        if (ROWS) {
+          const size_t j = (size_t)e * B.cap + c0 + r;
+          row = B.cvert[j];
+          f[0] = B.cforce[3 * j]; f[1] = B.cforce[3 * j + 1]; f[2] = B.cforce[3 * j + 2];
+        } else {
+          const int vb = B.voff[e] + c0 + r;
+          row = c0 + r;
+          f[0] = B.b[vb]; f[1] = B.b[B.NV + vb]; f[2] = B.b[2 * B.NV + vb];
+        }
+      }
+      s_row[idx] = row;
+      s_vec[idx] = f;
+    }
+    __syncthreads();
+    // the row every env that reads at this position reads (row 0 where none does); s_mixed is set
+    // where envs read different rows
+    for (int r = threadIdx.x; r < SR; r += kBlock) {
+      int one = -1;
+      bool same = true;
+      for (int t = 0; t < EB; ++t) {
+        const int q = s_row[r * EB + t];
+        if (q < 0) continue;
+        if (one < 0) one = q;
+        else if (q != one) same = false;
+      }
+      s_one[perm_row(r)] = one < 0 ? 0 : one;
+      if (!same) s_mixed = 1;
+    }
+    __syncthreads();
+    // One pass with one load per row for the whole chunk, or, where the envs read different rows
+    // somewhere in these rows, one pass per env over its own rows (its row indices written to
+    // s_one first, a scalar env mask selecting its sums).
+    const bool mixed = s_mixed != 0;   // the same over the block
+    const int npass = mixed ? w : 1;
+    const int wsc = __builtin_amdgcn_readfirstlane(wid);
+    for (int p = 0; p < npass; ++p) {
+      if (mixed) {
+        __syncthreads();
+        for (int r = threadIdx.x; r < SR; r += kBlock) {
+          const int q = s_row[r * EB + p];
+          s_one[perm_row(r)] = q < 0 ? 0 : q;
+        }
+        __syncthreads();
+      }
+      const unsigned mask = mixed ? (1u << p) : ((1u << w) - 1u);
+      if (col0 < ld) {   // ld is a multiple of 32 columns: a lane's VW columns lie inside the row
+        // Row indices are the same over the wave (scalar registers), so the UNROLL loads go out
+        // together.  An env's sum takes g * b at every row of the wave; where it reads nothing b
+        // is zero and g * 0 leaves the sum as it is (the sums start at +0 and the inverse is
+        // finite), so each env adds exactly its own rows in k_gemv_split's order.  The rows
+        // rb + WS * u stay below SR (SR is a multiple of WS * UNROLL).
+        for (int rb = wsc; rb < nrm; rb += WS * UNROLL) {
+          const int4 o4 = *reinterpret_cast<const int4*>(s_one + perm_row(rb));
+          const int ones[4] = {o4.x, o4.y, o4.z, o4.w};
+          vec_t g[UNROLL];
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u)
+            g[u] = *reinterpret_cast<const vec_t*>(G + (size_t)__builtin_amdgcn_readfirstlane(ones[u]) * ld + col0);
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+#pragma unroll
+            for (int t = 0; t < EB; ++t) {
+              if (!((mask >> t) & 1u)) continue;
+              const f4_t b = s_vec[(rb + WS * u) * EB + t];
+#pragma unroll
+              for (int q = 0; q < VW; ++q) {
+                acc[t][q][0] += g[u][q] * b[0];
+                acc[t][q][1] += g[u][q] * b[1];
+                acc[t][q][2] += g[u][q] * b[2];
+              }
+            }
+            // one row's right-hand sides (EB x 4 values) live at a time
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
+      }
+    }
+  }
+  // per env, k_gemv_split's fixed-order reduction over the waves
+#pragma unroll
+  for (int t = 0; t < EB; ++t) {
+    const int e = s_e[t];
+    if (e < 0 || s_r1[t] <= r0) continue;   // uniform over the block
+    __syncthreads();
+    if (wid > 0)
+      for (int q = 0; q < VW; ++q)
+        for (int k = 0; k < 3; ++k) s_red[((wid - 1) * 3 + k) * TILE + lane * VW + q] = acc[t][q][k];
+    __syncthreads();
+    if (wid == 0) {
+      T* P = partial + poff[e];
+      for (int q = 0; q < VW; ++q) {
+        const int col = col0 + q;
+        if (col >= n) continue;
+        for (int k = 0; k < 3; ++k) {
+          T s = acc[t][q][k];
+          for (int w2 = 0; w2 < WS - 1; ++w2) s += s_red[(w2 * 3 + k) * TILE + lane * VW + q];
+          P[((size_t)split * 3 + k) * n + col] = s;
+        }
+      }
+    }
+  }
+}
+
 // Adds each env's row-split partials in split order: z = sum (ROWS = false) or u = z + h^2 sum.
 template <class T, bool ROWS>
 __global__ void __launch_bounds__(kBlock) k_gemv_merge(DevBatch<T> B, const int* skip, const T* partial,
@@ -309,8 +485,12 @@ __global__ void __launch_bounds__(kBlock) k_gemv_merge(DevBatch<T> B, const int*
 template <class T>
 void launch_split_apply(const DevBatch<T>& B, const SplitSchedule& S, hipStream_t s) {
   T* P = static_cast<T*>(S.partial);
-  hipLaunchKernelGGL((k_gemv_split<T, false>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items,
-                     (const int*)nullptr, P, S.poff);
+  if (S.n_items > 0)
+    hipLaunchKernelGGL((k_gemv_split<T, false>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items,
+                       (const int*)nullptr, P, S.poff);
+  if (S.n_twin_items > 0)
+    hipLaunchKernelGGL((k_gemv_split_twins<T, false>), dim3((unsigned)S.n_twin_items), dim3(kBlock), 0, s, B,
+                       S.twin_items, S.twin_envs, (const int*)nullptr, P, S.poff);
   hipLaunchKernelGGL((k_gemv_merge<T, false>), dim3((unsigned)((B.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, B,
                      (const int*)nullptr, (const T*)P, S.poff);
 }
@@ -318,8 +498,12 @@ void launch_split_apply(const DevBatch<T>& B, const SplitSchedule& S, hipStream_
 template <class T>
 void launch_split_correct(const DevBatch<T>& B, const SplitSchedule& S, const int* skip, hipStream_t s) {
   T* P = static_cast<T*>(S.partial);
-  hipLaunchKernelGGL((k_gemv_split<T, true>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items, skip, P,
-                     S.poff);
+  if (S.n_items > 0)
+    hipLaunchKernelGGL((k_gemv_split<T, true>), dim3((unsigned)S.n_items), dim3(kBlock), 0, s, B, S.items, skip, P,
+                       S.poff);
+  if (S.n_twin_items > 0)
+    hipLaunchKernelGGL((k_gemv_split_twins<T, true>), dim3((unsigned)S.n_twin_items), dim3(kBlock), 0, s, B,
+                       S.twin_items, S.twin_envs, skip, P, S.poff);
   hipLaunchKernelGGL((k_gemv_merge<T, true>), dim3((unsigned)((B.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, B,
                      skip, (const T*)P, S.poff);
 }

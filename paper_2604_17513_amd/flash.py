@@ -73,7 +73,7 @@ class flash_params(C.Structure):
                 ("use_graph", C.c_int32), ("max_contacts_per_env", C.c_int32), ("inner_tol", C.c_double),
                 ("contact_fp32", C.c_int32), ("fixed_schedule", C.c_int32),
                 ("stream_groups", C.c_int32), ("fused_lg", C.c_int32), ("contact_metric", C.c_int32),
-                ("global_contact_solve", C.c_int32)]
+                ("global_contact_solve", C.c_int32), ("twin_chunk", C.c_int32)]
 
 
 class flash_contact(C.Structure):
@@ -187,7 +187,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
                   use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                   fixed_schedule: bool = False, contact_fp32: bool = False,
                   stream_groups: int = 0, fused_lg: bool = False, contact_metric: int = 0,
-                  global_contact_solve: int = 0) -> flash_params:
+                  global_contact_solve: int = 0, twin_chunk: int = 0) -> flash_params:
     s = flash_params()
     s.h = p.h
     for k in range(3):
@@ -208,6 +208,7 @@ def params_struct(p: scenes.Params, precision: int = FLASH_FP32, warm_start: int
     s.fused_lg = 1 if fused_lg else 0
     s.contact_metric = int(contact_metric)
     s.global_contact_solve = int(global_contact_solve)
+    s.twin_chunk = int(twin_chunk)
     return s
 
 
@@ -262,14 +263,15 @@ class Batch:
                  warm_start: int = FLASH_WS_PREV, use_graph: bool = False, max_contacts: int = 0,
                  stream: Optional[int] = None, inner_tol: float = 0.0, fixed_schedule: bool = False,
                  contact_fp32: bool = False, stream_groups: int = 0, fused_lg: bool = False,
-                 contact_metric: int = 0, global_contact_solve: int = 0):
+                 contact_metric: int = 0, global_contact_solve: int = 0, twin_chunk: int = 0):
         L = lib()
         self.n_envs = len(envs)
         self.params = params
         self.nv = [e.n_vertices for e in envs]
         descs, self._keep = env_descs(envs)
         self._p = params_struct(params, precision, warm_start, use_graph, max_contacts, inner_tol, fixed_schedule,
-                                contact_fp32, stream_groups, fused_lg, contact_metric, global_contact_solve)
+                                contact_fp32, stream_groups, fused_lg, contact_metric, global_contact_solve,
+                                twin_chunk)
         h = C.c_void_p()
         _check(L.flash_create_batch(descs, self.n_envs, C.byref(self._p), C.c_void_p(stream or 0), C.byref(h)))
         self._h = h
@@ -650,11 +652,13 @@ class Renderer:
 def from_scene(sc: scenes.Scene, precision: int = FLASH_FP32, warm_start: int = FLASH_WS_PREV,
                use_graph: bool = False, max_contacts: int = 0, inner_tol: float = 0.0,
                fixed_schedule: bool = False, contact_fp32: bool = False, stream_groups: int = 0,
-               fused_lg: bool = False, contact_metric: int = 0, global_contact_solve: int = 0) -> Batch:
+               fused_lg: bool = False, contact_metric: int = 0, global_contact_solve: int = 0,
+               twin_chunk: int = 0) -> Batch:
     """Creates a batch for a scene and uploads its initial state and obstacles."""
     b = Batch(sc.envs, sc.params, precision, warm_start, use_graph, max_contacts, inner_tol=inner_tol,
               fixed_schedule=fixed_schedule, contact_fp32=contact_fp32, stream_groups=stream_groups,
-              fused_lg=fused_lg, contact_metric=contact_metric, global_contact_solve=global_contact_solve)
+              fused_lg=fused_lg, contact_metric=contact_metric, global_contact_solve=global_contact_solve,
+              twin_chunk=twin_chunk)
     b.set_state(sc.x0, sc.v0)
     n_obs = {len(o) for o in sc.obstacles}
     if len(n_obs) == 1:

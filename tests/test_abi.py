@@ -111,13 +111,21 @@ def test_contact_capacity_beyond_lds_is_rejected_without_device():
         assert (st != F.FLASH_ERR_INVALID_ARG) == ok, (metric, glob, cap, L.flash_last_error())
         if st == F.FLASH_OK:
             L.flash_destroy_batch(h)
+    # envs per workgroup of the twin products: 0 (automatic) to 8
+    p.contact_metric, p.global_contact_solve, p.max_contacts_per_env = F.FLASH_METRIC_LIGHTWEIGHT, 1, 100
+    for chunk, ok in ((0, True), (8, True), (9, False), (-1, False)):
+        p.twin_chunk = chunk
+        st = L.flash_create_batch(d, 1, C.byref(p), None, C.byref(h))
+        assert (st != F.FLASH_ERR_INVALID_ARG) == ok, (chunk, L.flash_last_error())
+        if st == F.FLASH_OK:
+            L.flash_destroy_batch(h)
 
 
 def test_struct_layouts_match_header_field_order():
     # the ctypes mirrors follow the header's field order; sizes are those of the C structs on LP64
     assert C.sizeof(F.flash_obstacle) == 8 + 8 * (3 + 9 + 3 + 3)
     assert C.sizeof(F.flash_env_desc) == 16 + 16 + 8 * 6
-    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8 + 8
+    assert C.sizeof(F.flash_params) == 8 + 24 + 8 + 24 + 16 + 8 + 8 + 8 + 8 + 8
     assert C.sizeof(F.flash_contact) == 16 + 8 * (3 + 3 + 1 + 3 + 3)
     assert C.sizeof(F.flash_env_stats) == 24 + 8
 

@@ -298,14 +298,15 @@ def test_cloth_fold_matches_oracle_and_shares_the_inverse():
 def test_pressed_slab_with_large_splits_matches_oracle():
     """The large-scene recipe at reduced size (a 40 x 5 x 40-hex slab: 10,086 vertices, so each
     row split of the inverse products spans two LDS chunks) pressed by two pads, two identical envs
-    sharing one inverse: FP32 lightweight steps from a history reset match the oracle within 1e-5
-    relative, and both envs give the same bits."""
+    sharing one inverse and its products (one workgroup reads each row for both): FP32 lightweight
+    steps from a history reset match the oracle within 1e-5 relative, and both envs give the same
+    bits."""
     F = _F()
     sc = scenes.slab_press(2, nx=40, ny=5, nz=40)
     p = sc.params
     oe = O.precompute(sc.envs[0], p.h)
     b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, global_contact_solve=1, max_contacts=6000,
-                     use_graph=True)
+                     use_graph=True, twin_chunk=2)
     L = np.linalg.norm(sc.envs[0].rest_x.max(0) - sc.envs[0].rest_x.min(0))
     b.step(6)
     x, v = b.get_state()
@@ -322,3 +323,35 @@ def test_pressed_slab_with_large_splits_matches_oracle():
     assert ref.contacts.count > 1681
     assert err <= 1e-5 * max(np.abs(ref.x).max(), L)
     assert np.array_equal(x1[0], x1[1])
+
+
+@pytest.mark.parametrize("prec,chunk", [("fp32", 8), ("fp64", 3)])
+def test_twin_chunks_give_each_env_its_own_bits(prec, chunk):
+    """Ten identical slabs share one inverse and run their global-route products in chunks of
+    `chunk` envs per workgroup (8 + 2, or 3 + 3 + 3 + 1).  Three of them differ in state: pads one
+    hex further along x, pads pressing twice as fast, a slab starting 3 mm higher; so their contact
+    rows part from the others' (rows loaded per env).  With a loose tolerance the envs' iterations
+    stop at different updates (the stopped envs of a chunk skip the products).  After 8 steps every
+    env holds the bits it gets in a batch of its own (one env per workgroup)."""
+    F = _F()
+    sc = scenes.slab_press(10, nx=12, ny=3, nz=12, hex_size=0.01)
+    for ob in sc.obstacles[3][1:]:
+        ob.center[0] += 0.01
+    for ob in sc.obstacles[6][1:]:
+        ob.lin_vel[1] *= 2.0
+    sc.x0[9] = sc.x0[9] + np.array([0.0, 0.003, 0.0])
+    kw = dict(precision=F.FLASH_FP64 if prec == "fp64" else F.FLASH_FP32,
+              contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, global_contact_solve=1, max_contacts=400, inner_tol=5e-4)
+    b = F.from_scene(sc, twin_chunk=chunk, **kw)
+    b.step(8)
+    xb = b.split(b.get_state()[0])
+    cb = [b.stats()[e]["contacts"] for e in range(10)]
+    its = [b.stats()[e]["inner_iterations"] for e in range(10)]
+    _say(f"twin chunks {prec}: contacts per env {cb}, updates {its}")
+    v0 = b.contacts(0)["vertex"]
+    assert not np.array_equal(v0, b.contacts(3)["vertex"])
+    for e in range(10):
+        one = scenes.Scene([sc.envs[e]], [sc.x0[e]], [sc.v0[e]], [sc.obstacles[e]], sc.params, name="one")
+        bo = F.from_scene(one, **kw)
+        bo.step(8)
+        assert np.array_equal(bo.get_state()[0], xb[e]), e
