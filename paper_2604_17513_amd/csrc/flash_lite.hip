@@ -287,7 +287,8 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
 // Rows are staged kTwinRows at a time, a multiple of the wave count, so every row stays on the wave
 // k_gemv_split gives it; with its per-wave row order and its fixed-order reduction over the waves,
 // every env gets the bits it gets from k_gemv_split.  Loads are ordinary (cached): the other chunks
-// of a group read the same rows on the same XCD close in time.
+// of a group read the same rows on the same XCD close in time.  166-180 VGPRs (3 waves per SIMD in
+// FP32, 2 in FP64).
 constexpr int kTwinRows = 128;
 template <class T, bool ROWS>
 __global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, const int4* items, const int* envs,
@@ -300,6 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, cons
   constexpr int SR = kTwinRows;
   static_assert(kSplitRows % SR == 0 && SR % (WS * UNROLL) == 0, "staging must keep every row on its wave");
   static_assert(UNROLL == 4, "a wave reads its rows' shared indices as one int4");
+  static_assert(EB % 4 == 0, "right-hand sides are read 4 envs at a time");
   // s_one holds row r at perm_row(r): a wave's UNROLL rows rb + WS * u (rb = wave + WS * UNROLL * k)
   // lie side by side from perm_row(rb) on
   auto perm_row = [](int r) { return r / (WS * UNROLL) * (WS * UNROLL) + r % WS * UNROLL + r / WS % UNROLL; };
@@ -385,7 +387,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, cons
     // One pass with one load per row for the whole chunk, or, where the envs read different rows
     // somewhere in these rows, one pass per env over its own rows (its row indices written to
     // s_one first, a scalar env mask selecting its sums).
-    const bool mixed = s_mixed != 0;   // the same over the block
+    const bool mixed = __builtin_amdgcn_readfirstlane(s_mixed) != 0;   // the same over the block
     const int npass = mixed ? w : 1;
     const int wsc = __builtin_amdgcn_readfirstlane(wid);
     for (int p = 0; p < npass; ++p) {
@@ -400,32 +402,45 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, cons
       const unsigned mask = mixed ? (1u << p) : ((1u << w) - 1u);
       if (col0 < ld) {   // ld is a multiple of 32 columns: a lane's VW columns lie inside the row
         // Row indices are the same over the wave (scalar registers), so the UNROLL loads go out
-        // together.  An env's sum takes g * b at every row of the wave; where it reads nothing b
+        // together, and the next UNROLL rows' loads go out before this iteration's FMAs (double
+        // buffer).  An env's sum takes g * b at every row of the wave; where it reads nothing b
         // is zero and g * 0 leaves the sum as it is (the sums start at +0 and the inverse is
         // finite), so each env adds exactly its own rows in k_gemv_split's order.  The rows
         // rb + WS * u stay below SR (SR is a multiple of WS * UNROLL).
-        for (int rb = wsc; rb < nrm; rb += WS * UNROLL) {
+        auto load_rows = [&](int rb, vec_t* g) {
           const int4 o4 = *reinterpret_cast<const int4*>(s_one + perm_row(rb));
           const int ones[4] = {o4.x, o4.y, o4.z, o4.w};
-          vec_t g[UNROLL];
 #pragma unroll
           for (int u = 0; u < UNROLL; ++u)
             g[u] = *reinterpret_cast<const vec_t*>(G + (size_t)__builtin_amdgcn_readfirstlane(ones[u]) * ld + col0);
+        };
+        vec_t gn[UNROLL];
+        if (wsc < nrm) load_rows(wsc, gn);
+        for (int rb = wsc; rb < nrm; rb += WS * UNROLL) {
+          vec_t g[UNROLL];
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) g[u] = gn[u];
+          if (rb + WS * UNROLL < nrm) load_rows(rb + WS * UNROLL, gn);
 #pragma unroll
           for (int u = 0; u < UNROLL; ++u) {
+            // right-hand sides read 4 envs at a time (one LDS wait per 4 envs); 4 x 4 values live
 #pragma unroll
-            for (int t = 0; t < EB; ++t) {
-              if (!((mask >> t) & 1u)) continue;
-              const f4_t b = s_vec[(rb + WS * u) * EB + t];
+            for (int t0 = 0; t0 < EB; t0 += 4) {
+              f4_t bb[4];
 #pragma unroll
-              for (int q = 0; q < VW; ++q) {
-                acc[t][q][0] += g[u][q] * b[0];
-                acc[t][q][1] += g[u][q] * b[1];
-                acc[t][q][2] += g[u][q] * b[2];
+              for (int i = 0; i < 4; ++i) bb[i] = s_vec[(rb + WS * u) * EB + t0 + i];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                if (!((mask >> (t0 + i)) & 1u)) continue;
+#pragma unroll
+                for (int q = 0; q < VW; ++q) {
+                  acc[t0 + i][q][0] += g[u][q] * bb[i][0];
+                  acc[t0 + i][q][1] += g[u][q] * bb[i][1];
+                  acc[t0 + i][q][2] += g[u][q] * bb[i][2];
+                }
               }
+              __builtin_amdgcn_sched_barrier(0);
             }
-            // one row's right-hand sides (EB x 4 values) live at a time
-            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
