@@ -426,6 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split_twins(DevBatch<T> B, cons
             // right-hand sides read 4 envs at a time (one LDS wait per 4 envs); 4 x 4 values live
 #pragma unroll
             for (int t0 = 0; t0 < EB; t0 += 4) {
+              if (!((mask >> t0) & 0xFu)) continue;   // none of these 4 envs takes the row
               f4_t bb[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i) bb[i] = s_vec[(rb + WS * u) * EB + t0 + i];
