@@ -199,7 +199,8 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
   constexpr int UNROLL = 4;
   constexpr int WS = kBlock / 64;
   typedef T vec_t __attribute__((ext_vector_type(VW)));
-  __shared__ T s_vec[3 * kSplitRows];
+  typedef T f4_t __attribute__((ext_vector_type(4)));
+  __shared__ f4_t s_vec[kSplitRows];   // (b0, b1, b2, 0) per staged row
   __shared__ int s_row[kSplitRows];
   __shared__ T s_red[(WS - 1) * 3 * TILE];
   const int4 item = items[blockIdx.x];
@@ -223,38 +224,48 @@ __global__ void __launch_bounds__(kBlock) k_gemv_split(DevBatch<T> B, const int4
   const int nr = min(kSplitRows, r1 - c0);
   __syncthreads();
   for (int r = threadIdx.x; r < nr; r += kBlock) {
+    f4_t f;
     if (ROWS) {
       const size_t j = (size_t)e * B.cap + c0 + r;
       s_row[r] = B.cvert[j];
-      s_vec[r] = B.cforce[3 * j];
-      s_vec[kSplitRows + r] = B.cforce[3 * j + 1];
-      s_vec[2 * kSplitRows + r] = B.cforce[3 * j + 2];
+      f[0] = B.cforce[3 * j]; f[1] = B.cforce[3 * j + 1]; f[2] = B.cforce[3 * j + 2];
     } else {
       s_row[r] = c0 + r;
-      s_vec[r] = B.b[v0 + c0 + r];
-      s_vec[kSplitRows + r] = B.b[B.NV + v0 + c0 + r];
-      s_vec[2 * kSplitRows + r] = B.b[2 * B.NV + v0 + c0 + r];
+      f[0] = B.b[v0 + c0 + r]; f[1] = B.b[B.NV + v0 + c0 + r]; f[2] = B.b[2 * B.NV + v0 + c0 + r];
     }
+    f[3] = 0;
+    s_vec[r] = f;
   }
   __syncthreads();
   if (col0 < ld) {   // ld is a multiple of 32 columns: a lane's VW columns lie inside the row
-    for (int rb = wid; rb < nr; rb += WS * UNROLL) {
-      vec_t g[UNROLL];
+    // Row indices are the same over the wave (scalar registers): the UNROLL loads go out
+    // together, and the next UNROLL rows' loads before this iteration's FMAs (double buffer);
+    // rows past the staged ones load the last staged row, unused.
+    const int wsc = __builtin_amdgcn_readfirstlane(wid);
+    auto load_rows = [&](int rb, vec_t* g) {
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
-        const int r = rb + WS * u;
-        if (r < nr) g[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(G + (size_t)s_row[r] * ld + col0));
+        const int q = __builtin_amdgcn_readfirstlane(s_row[min(rb + WS * u, nr - 1)]);
+        g[u] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(G + (size_t)q * ld + col0));
       }
+    };
+    vec_t gn[UNROLL];
+    if (wsc < nr) load_rows(wsc, gn);
+    for (int rb = wsc; rb < nr; rb += WS * UNROLL) {
+      vec_t g[UNROLL];
+#pragma unroll
+      for (int u = 0; u < UNROLL; ++u) g[u] = gn[u];
+      if (rb + WS * UNROLL < nr) load_rows(rb + WS * UNROLL, gn);
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const int r = rb + WS * u;
         if (r < nr) {
-          const T b0 = s_vec[r], b1 = s_vec[kSplitRows + r], b2 = s_vec[2 * kSplitRows + r];
+          const f4_t b = s_vec[r];
 #pragma unroll
           for (int q = 0; q < VW; ++q) {
-            acc[q][0] += g[u][q] * b0;
-            acc[q][1] += g[u][q] * b1;
-            acc[q][2] += g[u][q] * b2;
+            acc[q][0] += g[u][q] * b[0];
+            acc[q][1] += g[u][q] * b[1];
+            acc[q][2] += g[u][q] * b[2];
           }
         }
       }
