@@ -481,7 +481,7 @@ def fold_sweep(F, scenes, args):
            "rows": {}}
     for name, (K, N) in (("lg5_linear10", (5, 10)), ("lg2_linear2", (2, 2))):
         row = {}
-        for ne in FOLD_ENVS:
+        for ne in args.fold_envs:
             sc = scenes.cloth_fold(ne, n=n, lg_iterations=K, inner_iterations=N)
             b = F.from_scene(sc, contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, max_contacts=n * n + 8, use_graph=True)
             b.step(args.fold_warmup)
@@ -732,6 +732,8 @@ def main():
     ap.add_argument("--fold-side", type=int, default=64, help="vertices per side of the folding sheet")
     ap.add_argument("--fold-warmup", type=int, default=20)
     ap.add_argument("--fold-steps", type=int, default=20)
+    ap.add_argument("--fold-envs", type=lambda s: [int(v) for v in s.split(",")], default=list(FOLD_ENVS),
+                    help="comma-separated env counts of the fold sweep")
     ap.add_argument("--profile-window", action="store_true",
                     help="pause the profiler except during the reported arm's timed steps (roctx)")
     ap.add_argument("--copy-probe", action="store_true",

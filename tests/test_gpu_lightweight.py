@@ -355,3 +355,19 @@ def test_twin_chunks_give_each_env_its_own_bits(prec, chunk):
         bo = F.from_scene(one, **kw)
         bo.step(8)
         assert np.array_equal(bo.get_state()[0], xb[e]), e
+
+
+def test_automatic_chunks_give_one_env_per_workgroup_bits():
+    """32 identical 64 x 64 folding sheets: the automatic choice runs their products in chunks of
+    8 envs (144 blocks per env, so 4 chunks keep 576 workgroups per product); after 6 steps in
+    HIP graphs every env holds the bits of the same batch run one env per workgroup."""
+    F = _F()
+    sc = scenes.cloth_fold(32, n=64)
+    kw = dict(contact_metric=F.FLASH_METRIC_LIGHTWEIGHT, max_contacts=64 * 64 + 8, use_graph=True)
+    a = F.from_scene(sc, **kw)
+    one = F.from_scene(sc, twin_chunk=1, **kw)
+    a.step(6)
+    one.step(6)
+    xa, x1 = a.get_state()[0], one.get_state()[0]
+    _say(f"automatic chunks vs one env per workgroup: max |dx| {np.abs(xa - x1).max():.1e}")
+    assert np.array_equal(xa, x1)
