@@ -1856,24 +1856,33 @@ restart:
     // factorisation: on stiff sheets the Woodbury direction alone loses too many digits (an FP64
     // cloth drop missed the oracle by 1e-3 m without it)
     apply_W(S.dl, S.Wd);
+    double rloc_b = 0.0, ploc_b = 0.0;
     for (int j = tid; j < c; j += kBlock) {
       if (S.pos[j] < 0) continue;
       CT K[3][3], E[3][3];
       contact_KE(S.cls[j], S.sp[j], mu, S.kap[j], S.yh0[j], S.yh1[j], K, E);
       const CT w0 = S.Wd[3 * j], w1 = S.Wd[3 * j + 1], w2 = S.Wd[3 * j + 2];
       const CT d0 = S.dl[3 * j], d1 = S.dl[3 * j + 1], d2 = S.dl[3 * j + 2];
-      for (int a = 0; a < 3; ++a)
+      for (int a = 0; a < 3; ++a) {
         S.rv[3 * j + a] = -S.ph[3 * j + a] - (K[a][0] * w0 + K[a][1] * w1 + K[a][2] * w2) -
                           (E[a][0] * d0 + E[a][1] * d1 + E[a][2] * d2);
+        rloc_b = fmax(rloc_b, fabs((double)S.rv[3 * j + a]));
+        ploc_b = fmax(ploc_b, fabs((double)S.ph[3 * j + a]));
+      }
     }
-    __syncthreads();
-    wsolve(S.rv, S.tmp);
-    for (int p = tid; p < nb; p += kBlock) {
-      const int j = S.bas[p];
-      for (int a = 0; a < 3; ++a) S.dl[3 * j + a] += S.tmp[3 * j + a];
+    // the refinement runs where the direction solves its linear system to fewer than 6 digits
+    // (relative to Phi on the base rows, max norms); otherwise W dl is already the line search's
+    const double rres = block_max(rloc_b, sh_red);
+    const double rphi = block_max(ploc_b, sh_red);
+    if (!(rres <= 1e-6 * rphi)) {
+      wsolve(S.rv, S.tmp);
+      for (int p = tid; p < nb; p += kBlock) {
+        const int j = S.bas[p];
+        for (int a = 0; a < 3; ++a) S.dl[3 * j + a] += S.tmp[3 * j + a];
+      }
+      __syncthreads();
+      apply_W(S.dl, S.Wd);
     }
-    __syncthreads();
-    apply_W(S.dl, S.Wd);
 
     mark(6);
     // ---- backtracking line search on 1/2 |Phi|^2 (inner scale) ----
