@@ -729,9 +729,10 @@ void build_device(flash_batch* b, std::vector<HostEnv>& H, const flash_env_desc*
     }
     // A group's chunk size is twin_chunk, or by default 8, else 4, whichever still leaves
     // kMinTwinItems workgroups per product (fewer, longer workgroups leave CUs idle), else one env
-    // per workgroup.  Measured on the 64 x 64 folding sheet (5 x 10 budget, ms per step at chunk
-    // 1 / 4 / 8): 8 envs 3.8 / 5.4 / 7.4, 16 envs 6.2 / 5.7 / 7.5, 32 envs 10.0 / 9.5 / 7.8, 256 envs
-    // 60.2 / 52.4 / 43.2; chunks of 2 were slower than 1 at every size.
+    // per workgroup.  Measured with the first version of the chunk kernel on the 64 x 64 folding
+    // sheet (5 x 10 budget, ms per step at chunk 1 / 4 / 8): 8 envs 3.8 / 5.4 / 7.4, 16 envs
+    // 6.2 / 5.7 / 7.5, 32 envs 10.0 / 9.5 / 7.8, 256 envs 60.2 / 52.4 / 43.2; chunks of 2 were
+    // slower than 1 at every size.
     constexpr int kMinTwinItems = 512;
     std::vector<int> order;       // envs run one per workgroup, largest first
     std::vector<int> gorder;      // twin groups run in chunks, largest envs first
